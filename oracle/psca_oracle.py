@@ -1,0 +1,414 @@
+"""FP64 CPU oracle for PSCA device activity detection (Tan & Cui, arXiv 2503.15259).
+
+TEST INFRASTRUCTURE ONLY.  This module is a plain, slow, obviously-correct
+restatement of the paper's per-iteration method in float64 / complex128
+NumPy.  Only the test suite, the smoke check and the benchmark's CPU-baseline
+leg may import it.  The HIP library never calls it, and it shares no code,
+constant table or helper with the HIP path.
+
+What it computes (paper Sec. III and IV, Algorithm 1 "PSCA Algorithms"):
+  x^(0) = 0; for k = 0, 1, ...:
+    Sigma_k  = S diag(w) S^H + sigma^2 I,  w = g*alpha (known g) or gamma
+    Sigma_k^-1 by Frobenius inversion (Sec. III-A, eqs. Frobenius_inversion_1/2)
+    q_n = s_n^H Sigma^-1 s_n,  r_n = s_n^H Sigma^-1 SigmaHat Sigma^-1 s_n
+    gradient of the variant's objective, curvature (g_n q_n)^2 or q_n^2
+    x~_n = clip(x_n - grad_n / curv_n, lo, hi)      (Lemmas 1-4)
+    x_n <- (1 - rho_k) x_n + rho_k x~_n              (eqs. Update_*)
+    rho_{k+1} = rho_k (1 - 0.5 rho_k), rho_0 = 0.5   (Sec. V)
+
+Readings where the paper is silent, ambiguous or garbled:
+  R1  MAP-K independent-prior gradient carries the 1/M factor of its
+      objective f_I (eq. ft); the printed gradient (eq. ft_gradient) drops it.
+  R2  The derivative of H2 (eq. pepsd, third case) uses coefficient 2, the
+      exact derivative of eq. H2; the printed 12 breaks Theorem 1(ii)'s
+      junction slope at g_l.
+  R3  Where p^eps = 0 (the gap [eps, g_l - eps], including its closed left
+      end of the H2 piece), the prior term p^eps'/p^eps is taken as 0.
+  R4  Pathloss map phi(d) = c0 d^-beta (power law), distance law area-uniform
+      on the annulus [d_l, d_u] (eq. dispdf); one common annulus for all n.
+  R5  Step sizes: rho_0 = 0.5, rho_{k+1} = rho_k (1 - 0.5 rho_k); the update
+      at iteration k uses rho_k.  Fixed iteration count (no stopping rule).
+  R6  Clip bounds are inclusive; K variants [0, 1], ML-UD [0, inf),
+      MAP-UR [0, g_u].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+import math
+
+import numpy as np
+
+ML_K, MAP_K, ML_UD, MAP_UR = 0, 1, 2, 3
+VARIANT_NAMES = {ML_K: "ML-K", MAP_K: "MAP-K", ML_UD: "ML-UD", MAP_UR: "MAP-UR"}
+KNOWN_PATHLOSS = (ML_K, MAP_K)
+
+
+# ---------------------------------------------------------------------------
+# Covariances (Sec. III-A eq. cov_a, Sec. IV-A eq. cov_b, and the empirical
+# covariance defined with eq. likelihood_Y)
+# ---------------------------------------------------------------------------
+
+def sample_covariance(Y: np.ndarray) -> np.ndarray:
+    """SigmaHat_Y = Y Y^H / M (the sufficient statistic; computed once)."""
+    Y = np.asarray(Y, dtype=np.complex128)
+    return Y @ Y.conj().T / Y.shape[1]
+
+
+def model_covariance(S: np.ndarray, w: np.ndarray, sigma2: float) -> np.ndarray:
+    """Sigma = S Diag(w) S^H + sigma^2 I  (w = g*alpha or gamma)."""
+    L = S.shape[0]
+    return S @ np.diag(np.asarray(w, dtype=np.float64)) @ S.conj().T + sigma2 * np.eye(L)
+
+
+def frobenius_inverse(Sigma: np.ndarray) -> np.ndarray:
+    """Inverse of a complex positive-definite matrix from real inverses
+    (Sec. III-A, eqs. Frobenius_inversion_1 and _2):
+        Re(Sigma^-1) = (A + B A^-1 B)^-1
+        Im(Sigma^-1) = -A^-1 B (A + B A^-1 B)^-1,   A = Re Sigma, B = Im Sigma.
+    """
+    A = Sigma.real
+    B = Sigma.imag
+    A_inv = np.linalg.inv(A)
+    re = np.linalg.inv(A + B @ A_inv @ B)
+    im = -A_inv @ B @ re
+    return re + 1j * im
+
+
+def quadratic_forms(S: np.ndarray, Sigma_inv: np.ndarray, Sigma_hat: np.ndarray):
+    """q_n = s_n^H Sigma^-1 s_n and r_n = s_n^H Sigma^-1 SigmaHat Sigma^-1 s_n,
+    the two terms of the ML gradients (eqs. gradient_ML, gradient_ML_U).
+    Both are real for Hermitian Sigma, SigmaHat; the imaginary round-off is
+    dropped."""
+    N = S.shape[1]
+    q = np.empty(N)
+    r = np.empty(N)
+    T = Sigma_inv @ Sigma_hat @ Sigma_inv
+    for n in range(N):
+        s = S[:, n]
+        q[n] = np.real(s.conj() @ Sigma_inv @ s)
+        r[n] = np.real(s.conj() @ T @ s)
+    return q, r
+
+
+# ---------------------------------------------------------------------------
+# MAP-UR prior (Sec. II: eqs. dispdf, gn, pg, pgamma, H2, peps; Sec. IV-B:
+# eq. pepsd; Theorem 1)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class PowerLawPrior:
+    """Effective-pathloss prior for one device with phi(d) = c0 d^-beta,
+    distance area-uniform on [d_l, d_u], activity probability p and Hermite
+    smoothing width eps."""
+    p: float
+    d_l: float
+    d_u: float
+    c0: float
+    beta: float
+    eps: float
+
+    # psi = phi^-1 and its derivatives
+    def psi(self, x):
+        return (self.c0 / x) ** (1.0 / self.beta)
+
+    def dpsi(self, x):
+        return -self.psi(x) / (self.beta * x)
+
+    def ddpsi(self, x):
+        return self.psi(x) * (1.0 / self.beta) * (1.0 / self.beta + 1.0) / (x * x)
+
+    @property
+    def g_l(self):
+        return self.c0 * self.d_u ** (-self.beta)
+
+    @property
+    def g_u(self):
+        return self.c0 * self.d_l ** (-self.beta)
+
+    @property
+    def D(self):
+        return self.d_u ** 2 - self.d_l ** 2
+
+    def p_G(self, x):
+        """Pathloss density on [g_l, g_u] (eq. pg)."""
+        return -2.0 * self.psi(x) * self.dpsi(x) / self.D
+
+    def p_upsilon_cont(self, x):
+        """Continuous part of eq. pgamma on [g_l, g_u]: p * p_G."""
+        return self.p * self.p_G(x)
+
+    def dp_upsilon_cont(self, x):
+        """Derivative of the continuous part (fourth case of eq. pepsd)."""
+        return -2.0 * self.p / self.D * (self.dpsi(x) ** 2 + self.psi(x) * self.ddpsi(x))
+
+    def H1(self, x):
+        e = self.eps
+        return (1.0 - self.p) * (1.0 + 2.0 * x / e) * ((x - e) / e) ** 2
+
+    def dH1(self, x):
+        e = self.eps
+        return 6.0 * (1.0 - self.p) / e ** 3 * x * (x - e)
+
+    def _AB(self):
+        gl = self.g_l
+        A = -2.0 * self.p * self.d_u / self.D * self.dpsi(gl)
+        B = -2.0 * self.p / self.D * (self.dpsi(gl) ** 2 + self.ddpsi(gl) * self.d_u)
+        return A, B
+
+    def H2(self, x):
+        """Eq. H2, u = gamma - g_l."""
+        A, B = self._AB()
+        e = self.eps
+        u = x - self.g_l
+        return A * (1.0 - 2.0 * u / e) * ((u + e) / e) ** 2 + B * u * ((u + e) / e) ** 2
+
+    def dH2(self, x):
+        """Exact derivative of eq. H2 (reading R2: coefficient 2, not 12)."""
+        A, B = self._AB()
+        e = self.eps
+        u = x - self.g_l
+        return -6.0 * A / e ** 3 * u * (u + e) + B / e ** 2 * (u + e) * (3.0 * u + e)
+
+    def branch(self, x) -> int:
+        """Which piece of eq. peps holds x: 0 H1, 1 gap, 2 H2, 3 density."""
+        if x < self.eps:
+            return 0
+        if x < self.g_l - self.eps:
+            return 1
+        if x < self.g_l:
+            return 2
+        return 3
+
+    def p_eps(self, x):
+        """Smoothed prior density p^eps (eq. peps)."""
+        b = self.branch(x)
+        if b == 0:
+            return self.H1(x)
+        if b == 1:
+            return 0.0
+        if b == 2:
+            return self.H2(x)
+        return self.p_upsilon_cont(x)
+
+    def dp_eps(self, x):
+        """Its derivative (eq. pepsd with reading R2)."""
+        b = self.branch(x)
+        if b == 0:
+            return self.dH1(x)
+        if b == 1:
+            return 0.0
+        if b == 2:
+            return self.dH2(x)
+        return self.dp_upsilon_cont(x)
+
+    def log_ratio(self, x):
+        """p^eps'(x) / p^eps(x), the prior term of eq. gradient_MAP_U;
+        0 where p^eps = 0 (reading R3)."""
+        pe = self.p_eps(x)
+        if pe == 0.0:
+            return 0.0
+        return self.dp_eps(x) / pe
+
+
+def make_prior(p, d_l, d_u, c0, beta, eps) -> PowerLawPrior:
+    return PowerLawPrior(p=float(p), d_l=float(d_l), d_u=float(d_u), c0=float(c0),
+                         beta=float(beta), eps=float(eps))
+
+
+# ---------------------------------------------------------------------------
+# Objectives (eqs. likelihood_Y, likelihood_Y_MAP with f_I of eq. ft,
+# likelihood_Y_U, likelihood_Y_MAP_U with eq. feps)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    """Inputs of one detection: SigmaHat, S, sigma^2, M and the variant data."""
+    Sigma_hat: np.ndarray
+    S: np.ndarray
+    sigma2: float
+    M: int
+    variant: int
+    g: np.ndarray | None = None        # known pathloss (ML-K, MAP-K)
+    p: np.ndarray | None = None        # activity probabilities (MAP-K)
+    prior: PowerLawPrior | None = None  # MAP-UR prior (common to all devices)
+
+    @property
+    def N(self):
+        return self.S.shape[1]
+
+    def weights(self, x):
+        """w in Sigma = S Diag(w) S^H + sigma^2 I."""
+        if self.variant in KNOWN_PATHLOSS:
+            return self.g * x
+        return np.asarray(x, dtype=np.float64)
+
+    def bounds(self):
+        if self.variant in KNOWN_PATHLOSS:
+            return 0.0, 1.0
+        if self.variant == ML_UD:
+            return 0.0, math.inf
+        return 0.0, self.prior.g_u
+
+
+def ml_objective(Sigma: np.ndarray, Sigma_hat: np.ndarray) -> float:
+    """log|Sigma| + tr(Sigma^-1 SigmaHat), via slogdet and a linear solve."""
+    sign, logdet = np.linalg.slogdet(Sigma)
+    assert sign.real > 0
+    return float(logdet.real + np.real(np.trace(np.linalg.solve(Sigma, Sigma_hat))))
+
+
+def objective(prob: Problem, x: np.ndarray) -> float:
+    """The variant's objective f(x); +inf for MAP-UR where p^eps(x_n) = 0."""
+    Sigma = model_covariance(prob.S, prob.weights(x), prob.sigma2)
+    f = ml_objective(Sigma, prob.Sigma_hat)
+    if prob.variant == MAP_K:
+        f += -np.sum(np.log(prob.p / (1.0 - prob.p)) * x) / prob.M
+    elif prob.variant == MAP_UR:
+        for xn in x:
+            pe = prob.prior.p_eps(float(xn))
+            if pe <= 0.0:
+                return math.inf
+            f += -math.log(pe) / prob.M
+    return f
+
+
+# ---------------------------------------------------------------------------
+# One PSCA iteration (Algorithm 1, steps 5-8)
+# ---------------------------------------------------------------------------
+
+def gradient_and_curvature(prob: Problem, x: np.ndarray, q: np.ndarray, r: np.ndarray):
+    """Partial derivatives of the objective and the surrogate's quadratic
+    coefficient 2c (eqs. gradient_ML, gradient_MAP + ft_gradient,
+    gradient_ML_U, gradient_MAP_U; Surrogate_*_separate)."""
+    v = prob.variant
+    if v == ML_K:
+        grad = prob.g * (q - r)
+        curv = (prob.g * q) ** 2
+    elif v == MAP_K:
+        grad = prob.g * (q - r) - np.log(prob.p / (1.0 - prob.p)) / prob.M   # reading R1
+        curv = (prob.g * q) ** 2
+    elif v == ML_UD:
+        grad = q - r
+        curv = q ** 2
+    elif v == MAP_UR:
+        lr = np.array([prob.prior.log_ratio(float(xn)) for xn in x])
+        grad = q - r - lr / prob.M
+        curv = q ** 2
+    else:
+        raise ValueError(f"unknown variant {v}")
+    return grad, curv
+
+
+def coordinate_step(x: np.ndarray, grad: np.ndarray, curv: np.ndarray, lo: float, hi: float):
+    """Minimiser of grad (t - x) + curv/2 (t - x)^2 over [lo, hi]
+    (Lemmas 1-4 via Lemmas 5-6 of Appendix C)."""
+    return np.minimum(np.maximum(x - grad / curv, lo), hi)
+
+
+@dataclass
+class IterationRecord:
+    x: np.ndarray        # x^(k)
+    q: np.ndarray
+    r: np.ndarray
+    x_tilde: np.ndarray
+    rho: float
+    x_next: np.ndarray   # x^(k+1)
+
+
+def psca_iteration(prob: Problem, x: np.ndarray, rho: float) -> IterationRecord:
+    """Steps 5-8 of Algorithm 1 for one iteration."""
+    Sigma = model_covariance(prob.S, prob.weights(x), prob.sigma2)
+    Sigma_inv = frobenius_inverse(Sigma)
+    q, r = quadratic_forms(prob.S, Sigma_inv, prob.Sigma_hat)
+    grad, curv = gradient_and_curvature(prob, x, q, r)
+    lo, hi = prob.bounds()
+    x_tilde = coordinate_step(x, grad, curv, lo, hi)
+    x_next = (1.0 - rho) * x + rho * x_tilde
+    return IterationRecord(x=x.copy(), q=q, r=r, x_tilde=x_tilde, rho=rho, x_next=x_next)
+
+
+def step_sizes(iters: int, rho0: float = 0.5, decay: float = 0.5) -> np.ndarray:
+    """rho_0 = rho0, rho_{k+1} = rho_k (1 - decay rho_k) (Sec. V)."""
+    out = np.empty(iters)
+    rho = rho0
+    for k in range(iters):
+        out[k] = rho
+        rho = rho * (1.0 - decay * rho)
+    return out
+
+
+def psca(prob: Problem, iters: int, rho=None, record: bool = False):
+    """Algorithm 1 from x^(0) = 0 for a fixed number of iterations.
+
+    rho: None for the paper's schedule, else an explicit per-iteration list
+    (used by the unrolled network, whose step sizes are learned).
+    Returns x^(iters) and, if record, the list of IterationRecord."""
+    rhos = step_sizes(iters) if rho is None else np.asarray(rho, dtype=np.float64)
+    x = np.zeros(prob.N)
+    hist = []
+    for k in range(iters):
+        rec = psca_iteration(prob, x, float(rhos[k]))
+        if record:
+            hist.append(rec)
+        x = rec.x_next
+    return (x, hist) if record else x
+
+
+def problem_from_instance(inst, variant: int, eps: float = 0.01) -> Problem:
+    """Wrap a generated instance (fields S, Y, g, p, sigma2, d_lo, d_hi,
+    pl_c0, pl_beta) as an oracle Problem; SigmaHat is formed here."""
+    Sh = sample_covariance(inst.Y)
+    N = inst.S.shape[1]
+    kw = dict(Sigma_hat=Sh, S=np.asarray(inst.S, np.complex128), sigma2=float(inst.sigma2),
+              M=int(inst.Y.shape[1]), variant=variant)
+    if variant in KNOWN_PATHLOSS:
+        kw["g"] = np.asarray(inst.g, np.float64)
+    if variant == MAP_K:
+        kw["p"] = np.full(N, float(inst.p))
+    if variant == MAP_UR:
+        kw["prior"] = make_prior(inst.p, inst.d_lo, inst.d_hi, inst.pl_c0, inst.pl_beta, eps)
+    return Problem(**kw)
+
+
+# ---------------------------------------------------------------------------
+# Detection and error rates (threshold module of Sec. III-A; P_MD = P_FA
+# operating point)
+# ---------------------------------------------------------------------------
+
+def threshold(x: np.ndarray, theta: float) -> np.ndarray:
+    """alpha_hat_n = 1[x_n >= theta]."""
+    return (np.asarray(x) >= theta).astype(np.uint8)
+
+
+def miss_false_alarm(scores: np.ndarray, truth: np.ndarray, theta: float):
+    """(P_MD, P_FA) at threshold theta, pooled over all entries."""
+    truth = np.asarray(truth).astype(bool)
+    det = np.asarray(scores) >= theta
+    n_act = max(int(truth.sum()), 1)
+    n_ina = max(int((~truth).sum()), 1)
+    pmd = float(np.sum(truth & ~det)) / n_act
+    pfa = float(np.sum(~truth & det)) / n_ina
+    return pmd, pfa
+
+
+def equal_error_rate(scores: np.ndarray, truth: np.ndarray):
+    """Threshold where P_MD = P_FA, searched over the candidate set of
+    distinct scores: minimise |P_MD - P_FA|, then (P_MD + P_FA)/2, then
+    prefer the larger threshold.  Returns (eer, theta, pmd, pfa) with
+    eer = (P_MD + P_FA)/2 at that threshold."""
+    scores = np.asarray(scores, dtype=np.float64).ravel()
+    truth = np.asarray(truth).ravel()
+    best = None
+    for theta in np.unique(scores):
+        pmd, pfa = miss_false_alarm(scores, truth, theta)
+        key = (abs(pmd - pfa), 0.5 * (pmd + pfa), -theta)
+        if best is None or key < best[0]:
+            best = (key, theta, pmd, pfa)
+    _, theta, pmd, pfa = best
+    return 0.5 * (pmd + pfa), float(theta), pmd, pfa
+
+
+def error_rate(scores: np.ndarray, truth: np.ndarray, theta: float) -> float:
+    """Average error rate ||alpha_hat - alpha||_1 / (N I)."""
+    det = threshold(scores, theta)
+    return float(np.mean(np.abs(det.astype(np.int64) - np.asarray(truth).astype(np.int64))))
