@@ -1,0 +1,146 @@
+/*
+ * psca.h — C ABI of the MI355X (gfx950) PSCA device-activity-detection library.
+ *
+ * The library computes the per-iteration hot path of the PSCA algorithms of
+ * Tan & Cui, "Fast MLE and MAPE-Based Device Activity Detection for
+ * Grant-Free Access via PSCA and PSCA-Net" (arXiv 2503.15259), Algorithm 1,
+ * for the four estimators of Sec. III and IV:
+ *   PSCA_ML_K   MLE of the activity alpha in [0,1]^N, known pathloss g (Sec. III-A)
+ *   PSCA_MAP_K  MAPE of alpha with the independent Bernoulli prior (Sec. III-B)
+ *   PSCA_ML_UD  MLE of the effective pathloss gamma >= 0, unknown g (Sec. IV-A)
+ *   PSCA_MAP_UR MAPE of gamma with the Hermite-smoothed prior p^eps (Sec. IV-B)
+ *
+ * Conventions shared by every entry point:
+ *   - Complex numbers are interleaved single precision (psca_c32, the layout
+ *     of std::complex<float> / torch.complex64).
+ *   - Matrices are column-major.  S is L x N with column n the pilot s_n
+ *     (L contiguous elements); Y is L x M; SigmaHat is L x L.
+ *   - All array arguments are DEVICE pointers on the context's GPU, owned by
+ *     the caller; the library never frees or retains them past the call's
+ *     stream work.  Host pointers are named *_host.
+ *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = the
+ *     default stream).  Outputs are valid once that stream's prior work is done.
+ *   - Return value: PSCA_OK (0) or a negative psca_status.  Argument errors are
+ *     detected on the host before any launch (PSCA_EINVAL, nothing written).
+ *     Numerical failure found on the device (a Cholesky pivot <= 0 or not
+ *     finite) is written to the optional device word `status` (PSCA_ENOTPD);
+ *     the iterate stops advancing at the last finite value.
+ *   - Work buffers live in the context (grown on demand with hipMalloc);
+ *     calls on one context must not overlap in time (use one context per
+ *     concurrent stream).
+ */
+#ifndef PSCA_H
+#define PSCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } psca_c32;
+
+typedef enum {
+  PSCA_ML_K = 0,
+  PSCA_MAP_K = 1,
+  PSCA_ML_UD = 2,
+  PSCA_MAP_UR = 3
+} psca_variant;
+
+typedef enum {
+  PSCA_OK = 0,
+  PSCA_EINVAL = -1,   /* bad argument (host-side validation, nothing launched) */
+  PSCA_ENOTPD = -2,   /* Sigma not numerically positive definite (device) */
+  PSCA_EHIP = -3,     /* a HIP runtime call failed */
+  PSCA_ENOMEM = -4,   /* device allocation failed */
+  PSCA_ENOTSUP = -5   /* size outside what this build supports (e.g. L > PSCA_MAX_L) */
+} psca_status;
+
+/* Largest pilot length L handled on chip (the L x L factor lives in LDS). */
+#define PSCA_MAX_L 96
+
+/*
+ * Parameters of one detection (Algorithm 1 inputs besides SigmaHat and S).
+ *   variant    psca_variant.
+ *   iters      number of iterations k = 0 .. iters-1 (>= 0); the paper leaves
+ *              the stopping rule open, this library runs a fixed count.
+ *   rho0, rho_decay   step sizes rho_0 = rho0, rho_{k+1} = rho_k (1 - rho_decay rho_k)
+ *              (Sec. V uses 0.5 and 0.5).  rho0 in (0, 1], rho_decay in [0, 2].
+ *   rho        optional DEVICE array of `iters` step sizes in [0, 1] that
+ *              replaces the schedule (the unrolled network's learned steps); NULL
+ *              for the schedule.
+ *   sigma2     noise power sigma^2 > 0 (eq. cov_a / cov_b).
+ *   M          number of BS antennas >= 1 (scales the MAP prior terms by 1/M).
+ *   g          DEVICE [N] known pathloss, > 0; required by ML-K and MAP-K.
+ *   p          DEVICE [N] activity probabilities in (0, 1); required by MAP-K.
+ *   d_lo, d_hi, pl_c0, pl_beta, eps   MAP-UR prior (Sec. II eqs. dispdf, gn,
+ *              pg, pgamma, peps): devices area-uniform on the annulus
+ *              [d_lo, d_hi] (0 < d_lo < d_hi), pathloss map phi(d) = pl_c0 *
+ *              d^-pl_beta (pl_c0 > 0, pl_beta > 0), Hermite width eps with
+ *              0 < eps and 2 eps < g_l = phi(d_hi).  The gradient's prior term
+ *              p^eps'/p^eps does not depend on the activity probability.
+ */
+typedef struct {
+  int32_t variant;
+  int32_t iters;
+  float rho0;
+  float rho_decay;
+  const float *rho;
+  float sigma2;
+  int32_t M;
+  const float *g;
+  const float *p;
+  float d_lo, d_hi, pl_c0, pl_beta, eps;
+} psca_params;
+
+typedef struct psca_ctx psca_ctx;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int psca_version(void);
+
+/* Human-readable text for a psca_status; never NULL. */
+const char *psca_strerror(int code);
+
+/* Create a context bound to HIP device `device`.  *ctx receives the handle.
+ * Returns PSCA_EINVAL for a NULL ctx or a bad device, PSCA_EHIP otherwise. */
+int psca_create(psca_ctx **ctx, int device);
+
+/* Free a context and its work buffers (waits for the device).  NULL is a no-op. */
+int psca_destroy(psca_ctx *ctx);
+
+/* Sample covariance SigmaHat = Y Y^H / M (the sufficient statistic defined with
+ * eq. likelihood_Y; computed once per detection, footnote to Algorithm 1).
+ * Y: L x M, SigmaHat: L x L output (exactly Hermitian).  1 <= L <= PSCA_MAX_L, M >= 1. */
+int psca_sample_cov(psca_ctx *ctx, const psca_c32 *Y, int L, int M,
+                    psca_c32 *Sigma_hat, void *stream);
+
+/* Algorithm 1 from x^(0) = 0 for prm->iters iterations.
+ * Sigma_hat: L x L Hermitian PSD; S: L x N; x_out: [N] final iterate
+ * (alpha for the K variants, gamma for the U variants).
+ * status: optional DEVICE int32 receiving PSCA_OK or PSCA_ENOTPD. */
+int psca_detect(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                const psca_params *prm, float *x_out, int32_t *status, void *stream);
+
+/* psca_sample_cov (with M = prm->M columns of Y) followed by psca_detect. */
+int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, int N,
+                  const psca_params *prm, float *x_out, int32_t *status, void *stream);
+
+/* One iteration of Algorithm 1 (steps 5-8) from an arbitrary iterate:
+ * Sigma = S diag(w(x_in)) S^H + sigma^2 I, its Cholesky factor and inverse,
+ * q_n = s_n^H Sigma^-1 s_n, r_n = s_n^H Sigma^-1 SigmaHat Sigma^-1 s_n, the
+ * closed-form coordinate step x~ (Lemmas 1-4) and
+ * x_out = (1 - rho) x_in + rho x~ (eqs. Update_*).  prm->iters and prm->rho are
+ * ignored.  q_out, r_out, xt_out are optional DEVICE [N] outputs (NULL to skip).
+ * x_in and x_out may not alias. */
+int psca_iterate(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                 const psca_params *prm, float rho, const float *x_in, float *x_out,
+                 float *q_out, float *r_out, float *xt_out, int32_t *status, void *stream);
+
+/* Threshold module: support[n] = (x[n] >= theta) ? 1 : 0 (Sec. III-A). */
+int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSCA_H */

@@ -1,0 +1,94 @@
+"""ctypes declarations of the C ABI in include/psca.h.
+
+Loading fails loudly: there is no CPU fallback anywhere in this package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpsca.so")
+
+PSCA_OK = 0
+PSCA_EINVAL = -1
+PSCA_ENOTPD = -2
+PSCA_EHIP = -3
+PSCA_ENOMEM = -4
+PSCA_ENOTSUP = -5
+
+ML_K, MAP_K, ML_UD, MAP_UR = 0, 1, 2, 3
+MAX_L = 96
+
+# every symbol include/psca.h declares
+EXPORTED = (
+    "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
+    "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold",
+)
+
+
+class PscaParams(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("rho0", ctypes.c_float),
+        ("rho_decay", ctypes.c_float),
+        ("rho", ctypes.c_void_p),
+        ("sigma2", ctypes.c_float),
+        ("M", ctypes.c_int32),
+        ("g", ctypes.c_void_p),
+        ("p", ctypes.c_void_p),
+        ("d_lo", ctypes.c_float),
+        ("d_hi", ctypes.c_float),
+        ("pl_c0", ctypes.c_float),
+        ("pl_beta", ctypes.c_float),
+        ("eps", ctypes.c_float),
+    ]
+
+
+class PscaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpsca.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2503_15259_amd.build` "
+            "(this package has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_float
+    P = ctypes.POINTER(PscaParams)
+    sig = {
+        "psca_version": ([], i32),
+        "psca_strerror": ([i32], ctypes.c_char_p),
+        "psca_create": ([ctypes.POINTER(vp), i32], i32),
+        "psca_destroy": ([vp], i32),
+        "psca_sample_cov": ([vp, vp, i32, i32, vp, vp], i32),
+        "psca_detect": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
+        "psca_detect_y": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
+        "psca_iterate": ([vp, vp, vp, i32, i32, P, f32, vp, vp, vp, vp, vp, vp, vp], i32),
+        "psca_threshold": ([vp, i32, f32, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().psca_strerror(code).decode()
+
+
+def check(code: int, what: str) -> None:
+    if code != PSCA_OK:
+        raise PscaError(code, what)

@@ -1,0 +1,207 @@
+"""Python binding of the PSCA C ABI (argument marshalling only).
+
+Every computation runs in the HIP kernels of libpsca.so; torch provides the
+device memory and the stream.  Complex matrices are torch.complex64 tensors
+with the mathematical shape (L x N for S, L x M for Y, L x L for SigmaHat);
+the ABI wants them column-major, i.e. with strides (1, L).  `colmajor()`
+produces that layout (a no-op for a tensor that already has it).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _native as N
+from ._native import ML_K, MAP_K, ML_UD, MAP_UR, MAX_L, PscaError  # noqa: F401
+
+VARIANTS = {"ML-K": ML_K, "MAP-K": MAP_K, "ML-UD": ML_UD, "MAP-UR": MAP_UR}
+
+
+def colmajor(t: torch.Tensor) -> torch.Tensor:
+    """Same matrix, column-major storage (strides (1, rows))."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    if t.stride(0) == 1 and t.stride(1) == t.shape[0]:
+        return t
+    return t.mT.contiguous().mT
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device, stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, device, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != device:
+        raise TypeError(f"{name} must be a {dtype} tensor on {device}")
+
+
+class Context:
+    """Owns a psca_ctx (work buffers) on one GPU."""
+
+    def __init__(self, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        self._lib = N.load()
+        h = ctypes.c_void_p()
+        N.check(self._lib.psca_create(ctypes.byref(h), self.device.index), "psca_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.psca_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device=None) -> Context:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = dev.index or 0
+    if key not in _default_ctx:
+        _default_ctx[key] = Context(key)
+    return _default_ctx[key]
+
+
+@dataclass
+class Params:
+    """psca_params (include/psca.h).  Tensors must live on the context's GPU."""
+    variant: int
+    iters: int = 100
+    sigma2: float = 1.0
+    M: int = 1
+    g: Optional[torch.Tensor] = None
+    p: Optional[torch.Tensor] = None
+    rho0: float = 0.5
+    rho_decay: float = 0.5
+    rho: Optional[torch.Tensor] = None
+    d_lo: float = 0.05
+    d_hi: float = 0.5
+    pl_c0: float = 10.0 ** 0.89
+    pl_beta: float = 3.76
+    eps: float = 0.01
+
+    def to_c(self) -> N.PscaParams:
+        c = N.PscaParams()
+        c.variant = int(self.variant)
+        c.iters = int(self.iters)
+        c.rho0 = float(self.rho0)
+        c.rho_decay = float(self.rho_decay)
+        c.rho = None if self.rho is None else self.rho.data_ptr()
+        c.sigma2 = float(self.sigma2)
+        c.M = int(self.M)
+        c.g = None if self.g is None else self.g.data_ptr()
+        c.p = None if self.p is None else self.p.data_ptr()
+        c.d_lo, c.d_hi = float(self.d_lo), float(self.d_hi)
+        c.pl_c0, c.pl_beta, c.eps = float(self.pl_c0), float(self.pl_beta), float(self.eps)
+        return c
+
+    def check_tensors(self, device, n):
+        for name in ("g", "p"):
+            t = getattr(self, name)
+            if t is not None:
+                _need(t, torch.float32, device, name)
+                if t.numel() != n or not t.is_contiguous():
+                    raise ValueError(f"{name} must be a contiguous float32 vector of length N")
+        if self.rho is not None:
+            _need(self.rho, torch.float32, device, "rho")
+            if self.rho.numel() < self.iters or not self.rho.is_contiguous():
+                raise ValueError("rho must hold `iters` contiguous float32 step sizes")
+
+
+def sample_cov(Y: torch.Tensor, ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """SigmaHat = Y Y^H / M on the GPU (psca_sample_cov)."""
+    ctx = ctx or default_context(Y.device)
+    _need(Y, torch.complex64, ctx.device, "Y")
+    Y = colmajor(Y)
+    L, M = Y.shape
+    out = torch.empty((L, L), dtype=torch.complex64, device=ctx.device).mT
+    N.check(ctx._lib.psca_sample_cov(ctx.handle, _ptr(Y), L, M, _ptr(out), _stream(ctx.device, stream)),
+            "psca_sample_cov")
+    return out
+
+
+def detect(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Context] = None,
+           stream=None, out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
+    """Algorithm 1 from x = 0 for params.iters iterations (psca_detect).
+    Returns x (float32, length N).  `status`, if given, is a device int32[1]
+    that receives 0 or PSCA_ENOTPD."""
+    ctx = ctx or default_context(S.device)
+    _need(S, torch.complex64, ctx.device, "S")
+    _need(Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
+    S = colmajor(S)
+    Sigma_hat = colmajor(Sigma_hat)
+    L, n = S.shape
+    if Sigma_hat.shape != (L, L):
+        raise ValueError("Sigma_hat must be L x L")
+    params.check_tensors(ctx.device, n)
+    x = torch.empty(n, dtype=torch.float32, device=ctx.device) if out is None else out
+    c = params.to_c()
+    N.check(ctx._lib.psca_detect(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c), _ptr(x),
+                                 _ptr(status), _stream(ctx.device, stream)), "psca_detect")
+    return x
+
+
+def detect_y(Y: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Context] = None,
+             stream=None, out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
+    """psca_detect_y: SigmaHat from Y (M = Y.shape[1]) then Algorithm 1."""
+    ctx = ctx or default_context(S.device)
+    _need(S, torch.complex64, ctx.device, "S")
+    _need(Y, torch.complex64, ctx.device, "Y")
+    S = colmajor(S)
+    Y = colmajor(Y)
+    L, n = S.shape
+    if Y.shape[0] != L or Y.shape[1] != params.M:
+        raise ValueError("Y must be L x M with M = params.M")
+    params.check_tensors(ctx.device, n)
+    x = torch.empty(n, dtype=torch.float32, device=ctx.device) if out is None else out
+    c = params.to_c()
+    N.check(ctx._lib.psca_detect_y(ctx.handle, _ptr(Y), _ptr(S), L, n, ctypes.byref(c), _ptr(x),
+                                   _ptr(status), _stream(ctx.device, stream)), "psca_detect_y")
+    return x
+
+
+def iterate(Sigma_hat: torch.Tensor, S: torch.Tensor, x: torch.Tensor, rho: float, params: Params,
+            ctx: Optional[Context] = None, stream=None, status: Optional[torch.Tensor] = None):
+    """One iteration (psca_iterate).  Returns (x_next, q, r, x_tilde)."""
+    ctx = ctx or default_context(S.device)
+    _need(S, torch.complex64, ctx.device, "S")
+    _need(Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
+    _need(x, torch.float32, ctx.device, "x")
+    S = colmajor(S)
+    Sigma_hat = colmajor(Sigma_hat)
+    L, n = S.shape
+    if x.numel() != n or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 vector of length N")
+    params.check_tensors(ctx.device, n)
+    x_next, q, r, xt = (torch.empty(n, dtype=torch.float32, device=ctx.device) for _ in range(4))
+    c = params.to_c()
+    N.check(ctx._lib.psca_iterate(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c),
+                                  ctypes.c_float(rho), _ptr(x), _ptr(x_next), _ptr(q), _ptr(r), _ptr(xt),
+                                  _ptr(status), _stream(ctx.device, stream)), "psca_iterate")
+    return x_next, q, r, xt
+
+
+def threshold(x: torch.Tensor, theta: float, stream=None) -> torch.Tensor:
+    """support = 1[x >= theta] (psca_threshold)."""
+    lib = N.load()
+    if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+        raise TypeError("x must be a contiguous float32 CUDA tensor")
+    out = torch.empty(x.numel(), dtype=torch.uint8, device=x.device)
+    N.check(lib.psca_threshold(_ptr(x), x.numel(), ctypes.c_float(theta), _ptr(out), _stream(x.device, stream)),
+            "psca_threshold")
+    return out

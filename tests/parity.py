@@ -1,0 +1,55 @@
+"""Shared helpers of the GPU parity tests (no GPU needed to import)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+# Tolerances of the HIP path (complex FP32, FP32 accumulation) against the
+# FP64 oracle, after a fixed number of iterations:
+#   gamma (unknown pathloss): |err| <= REL_GAMMA * |x_ref| on entries with
+#       |x_ref| >= FLOOR_FRAC * max|x_ref|, else <= ABS_SMALL_GAMMA * max|x_ref|
+#   alpha (known pathloss, values in [0, 1]): |err| <= ABS_ALPHA
+REL_GAMMA = 1e-4
+FLOOR_FRAC = 1e-3
+ABS_SMALL_GAMMA = 1e-6
+ABS_ALPHA = 1e-4
+
+
+def parity_report(x_gpu, x_ref, variant):
+    x_gpu = np.asarray(x_gpu, dtype=np.float64)
+    x_ref = np.asarray(x_ref, dtype=np.float64)
+    err = np.abs(x_gpu - x_ref)
+    if variant in O.KNOWN_PATHLOSS:
+        bad = err > ABS_ALPHA
+        return {"max_abs": float(err.max()), "n_bad": int(bad.sum()), "bad": np.nonzero(bad)[0]}
+    scale = float(np.max(np.abs(x_ref))) if x_ref.size else 0.0
+    big = np.abs(x_ref) >= FLOOR_FRAC * scale
+    tol = np.where(big, REL_GAMMA * np.abs(x_ref), ABS_SMALL_GAMMA * scale)
+    bad = err > tol
+    rel = err[big] / np.abs(x_ref[big]) if big.any() else np.zeros(1)
+    return {"max_rel_big": float(rel.max()), "max_abs_small_over_scale":
+            float((err[~big].max() / scale) if (~big).any() and scale > 0 else 0.0),
+            "n_bad": int(bad.sum()), "bad": np.nonzero(bad)[0]}
+
+
+def assert_parity(x_gpu, x_ref, variant, what=""):
+    rep = parity_report(x_gpu, x_ref, variant)
+    assert rep["n_bad"] == 0, f"{what} {O.VARIANT_NAMES[variant]}: {rep}"
+    return rep
+
+
+def assert_same_support(x_gpu, x_ref, truth, variant, what=""):
+    """Identical detected support at the oracle's equal-error threshold (and at
+    0.5 for the known-pathloss variants), excluding devices whose oracle score
+    lies within a relative 1e-4 of the threshold."""
+    x_gpu = np.asarray(x_gpu, dtype=np.float64)
+    x_ref = np.asarray(x_ref, dtype=np.float64)
+    _, theta, _, _ = O.equal_error_rate(x_ref, truth)
+    thetas = [theta] + ([0.5] if variant in O.KNOWN_PATHLOSS else [])
+    scale = float(np.max(np.abs(x_ref)))
+    for th in thetas:
+        near = np.abs(x_ref - th) <= 1e-4 * max(scale, abs(th))
+        flips = (x_gpu >= th) != (x_ref >= th)
+        n_flip = int(np.sum(flips & ~near))
+        assert n_flip == 0, f"{what} {O.VARIANT_NAMES[variant]}: {n_flip} support flips at theta={th}"

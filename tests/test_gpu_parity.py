@@ -1,0 +1,198 @@
+"""HIP path vs the FP64 oracle, through the C ABI (needs an MI355X)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_15259_amd import instances as I
+from parity import assert_parity, assert_same_support
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [O.ML_K, O.MAP_K, O.ML_UD, O.MAP_UR]
+EPS = 0.01
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_15259_amd import psca
+    return psca
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def c64(a):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(np.complex64)).to(dev())
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).astype(np.float32)).to(dev())
+
+
+def params_for(P, inst, variant, iters):
+    kw = dict(variant=variant, iters=iters, sigma2=inst.sigma2, M=inst.M,
+              d_lo=inst.d_lo, d_hi=inst.d_hi, pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS)
+    if variant in O.KNOWN_PATHLOSS:
+        kw["g"] = f32(inst.g)
+    if variant == O.MAP_K:
+        kw["p"] = f32(np.full(inst.N, inst.p))
+    return P.Params(**kw)
+
+
+def run_gpu(P, inst, variant, iters):
+    Y, S = c64(inst.Y), c64(inst.S)
+    status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+    x = P.detect_y(Y, S, params_for(P, inst, variant, iters), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    return x.cpu().numpy()
+
+
+def label(inst, variant, iters):
+    return f"[{O.VARIANT_NAMES[variant]} N={inst.N} L={inst.L} M={inst.M} seed={inst.seed} iters={iters}]"
+
+
+def test_sample_covariance(P):
+    for (N, L, M) in [(10, 1, 1), (30, 13, 7), (100, 64, 128), (50, 96, 256)]:
+        inst = I.make_instance(7, L, N, L, M, 0.2)
+        print(f"sample_cov L={L} M={M}", flush=True)
+        got = P.sample_cov(c64(inst.Y))
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().astype(np.complex128)
+        ref = O.sample_covariance(inst.Y)
+        assert np.linalg.norm(got - ref) <= 2e-6 * np.linalg.norm(ref)
+        assert np.array_equal(got, got.conj().T)        # exactly Hermitian
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_first_iteration_from_zero(P, variant):
+    inst = I.workload_instance("small", 1)
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    rec = O.psca_iteration(prob, np.zeros(inst.N), 0.5)
+    Sh = P.sample_cov(c64(inst.Y))
+    xn, q, r, xt = P.iterate(Sh, c64(inst.S), f32(np.zeros(inst.N)), 0.5, params_for(P, inst, variant, 1))
+    torch.cuda.synchronize()
+    for name, got, ref in [("q", q, rec.q), ("r", r, rec.r), ("x~", xt, rec.x_tilde), ("x+", xn, rec.x_next)]:
+        got = got.cpu().numpy().astype(np.float64)
+        tol = 2e-5 * np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+        assert np.all(np.abs(got - ref) <= tol), (name, np.max(np.abs(got - ref) / np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_iteration_from_a_mid_trajectory_point(P, variant):
+    """Factorisation of a realistic Sigma (iterate 15 of the oracle)."""
+    inst = I.workload_instance("single", 2)
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    x15 = O.psca(prob, 15)
+    rho = float(O.step_sizes(16)[15])
+    rec = O.psca_iteration(prob, x15, rho)
+    Sh = P.sample_cov(c64(inst.Y))
+    xn, q, r, xt = P.iterate(Sh, c64(inst.S), f32(x15), rho, params_for(P, inst, variant, 1))
+    torch.cuda.synchronize()
+    for name, got, ref in [("q", q, rec.q), ("r", r, rec.r)]:
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-3, name
+    assert_parity(xn.cpu().numpy(), rec.x_next, variant, label(inst, variant, 1))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_detect_small_workload(P, variant):
+    inst = I.workload_instance("small", 0)
+    iters = 100
+    ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
+    got = run_gpu(P, inst, variant, iters)
+    assert_parity(got, ref, variant, label(inst, variant, iters))
+    assert_same_support(got, ref, inst.alpha, variant, label(inst, variant, iters))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_detect_single_instance_workload(P, variant):
+    """Full-size single-instance workload: N = 1000, L = 64, M = 128, 100 iterations."""
+    inst = I.workload_instance("single", 0)
+    iters = 100
+    ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
+    print(label(inst, variant, iters), flush=True)
+    got = run_gpu(P, inst, variant, iters)
+    assert_parity(got, ref, variant, label(inst, variant, iters))
+    assert_same_support(got, ref, inst.alpha, variant, label(inst, variant, iters))
+
+
+@pytest.mark.parametrize("N,L,M", [(1, 1, 4), (1, 8, 16), (65, 13, 9), (129, 3, 40), (200, 96, 64),
+                                   (300, 96, 256), (64, 64, 64), (1000, 33, 128)])
+def test_detect_ragged_and_edge_shapes(P, N, L, M):
+    inst = I.make_instance(5, N * 1000 + L, N, L, M, 0.2)
+    for variant in (O.ML_K, O.ML_UD):
+        iters = 30
+        ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
+        print(label(inst, variant, iters), flush=True)
+        got = run_gpu(P, inst, variant, iters)
+        assert_parity(got, ref, variant, label(inst, variant, iters))
+
+
+def test_zero_iterations_returns_zero(P):
+    inst = I.make_instance(5, 1, 70, 8, 16, 0.2)
+    got = run_gpu(P, inst, O.ML_UD, 0)
+    assert np.array_equal(got, np.zeros(inst.N, np.float32))
+
+
+def test_explicit_step_sizes_match_schedule(P):
+    inst = I.workload_instance("small", 2)
+    iters = 12
+    rho = f32(O.step_sizes(iters))
+    prm = params_for(P, inst, O.ML_K, iters)
+    prm.rho = rho
+    x = P.detect_y(c64(inst.Y), c64(inst.S), prm)
+    ref = O.psca(O.problem_from_instance(inst, O.ML_K), iters)
+    torch.cuda.synchronize()
+    assert_parity(x.cpu().numpy(), ref, O.ML_K)
+
+
+def test_threshold_bit_exact(P):
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 1, 1001).astype(np.float32)
+    x[::7] = 0.5
+    got = P.threshold(f32(x), 0.5)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), O.threshold(x, np.float32(0.5)))
+
+
+def test_not_positive_definite_is_reported_and_iterate_held(P):
+    """A negative iterate makes Sigma indefinite; the device reports it and
+    leaves x unchanged (forced from the host: no fault, every kernel exits)."""
+    inst = I.make_instance(5, 2, 80, 8, 16, 0.2)
+    Sh = P.sample_cov(c64(inst.Y))
+    x_in = f32(np.full(inst.N, -10.0))
+    status = torch.zeros(1, dtype=torch.int32, device=dev())
+    xn, _, _, _ = P.iterate(Sh, c64(inst.S), x_in, 0.5, params_for(P, inst, O.ML_UD, 1), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == -2
+    assert np.array_equal(xn.cpu().numpy(), x_in.cpu().numpy())
+    # a non-finite iterate is reported the same way
+    x_nan = f32(np.full(inst.N, np.nan))
+    xn, _, _, _ = P.iterate(Sh, c64(inst.S), x_nan, 0.5, params_for(P, inst, O.ML_UD, 1), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == -2
+
+
+def test_host_validation_errors(P):
+    inst = I.make_instance(5, 3, 20, 8, 16, 0.2)
+    Y, S = c64(inst.Y), c64(inst.S)
+    with pytest.raises(P.PscaError) as e:
+        P.detect_y(Y, S, P.Params(variant=O.ML_K, iters=5, M=16))          # g missing
+    assert e.value.code == -1
+    with pytest.raises(P.PscaError):
+        P.detect_y(Y, S, P.Params(variant=O.ML_UD, iters=5, M=16, sigma2=0.0))
+    with pytest.raises(P.PscaError):
+        P.detect_y(Y, S, P.Params(variant=O.ML_UD, iters=5, M=16, rho0=1.5))
+    with pytest.raises(P.PscaError):
+        P.detect_y(Y, S, P.Params(variant=O.MAP_UR, iters=5, M=16, eps=100.0))   # 2 eps >= g_l
+    big = I.make_instance(5, 4, 20, 97, 8, 0.2)
+    with pytest.raises(P.PscaError) as e:
+        P.detect_y(c64(big.Y), c64(big.S), P.Params(variant=O.ML_UD, iters=5, M=8))
+    assert e.value.code == -5
