@@ -64,3 +64,10 @@ def test_missing_library_fails_loudly(tmp_path):
             N2.load(str(tmp_path / "nope.so"))
     finally:
         N2._lib = saved
+
+
+def test_binding_module_imports_without_a_gpu():
+    from paper_2503_15259_amd import psca
+    assert psca.VARIANTS["MAP-UR"] == N.MAP_UR
+    p = psca.Params(variant=N.ML_UD, iters=3, M=8).to_c()
+    assert p.iters == 3 and p.g is None
