@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark: PSCA detection instances/s on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Workload: single-instance PSCA at N = 1000 devices, pilot length L = 64,
+M = 128 antennas, activity p = 0.1, 100 iterations, all four estimators
+(ML-K, MAP-K, ML-UD, MAP-UR).  One step detects four instances, one per
+estimator, each from its received pilots Y (the sample covariance is formed
+inside the timed region).  Inputs live in HBM before timing starts.
+
+Prints one JSON line (see the keys at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "detection instances/sec at fixed P_MD=P_FA; PSCA vs unrolled net, 1 MI355X"
+VARIANT_NAMES = ["ML-K", "MAP-K", "ML-UD", "MAP-UR"]
+WORKLOAD = "single"
+POOL = 8           # distinct instances resident on the GPU
+EPS = 0.01         # MAP-UR Hermite width (noise-normalised units)
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def algorithmic_flops(N, L, M, iters):
+    """Real flops the method needs: SigmaHat (Hermitian, 4 L^2 M) once; per
+    iteration Sigma (Hermitian, 4 N L^2), B = Sigma^-1 S and D = SigmaHat B
+    (16 N L^2), quadratic forms (8 N L), factor/inverse ((4/3) L^3)."""
+    return 4.0 * L * L * M + iters * (20.0 * N * L * L + 8.0 * N * L + (4.0 / 3.0) * L ** 3)
+
+
+def algorithmic_bytes(N, L, M, iters):
+    """HBM bytes the method must move at least once: Y, S, g/p, x."""
+    return 8.0 * L * M + 8.0 * N * L + 3 * 4.0 * N
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores (bounded sample)
+# ---------------------------------------------------------------------------
+
+def _oracle_task(args):
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    variant, index = args
+    import numpy as np  # noqa: F401
+    import oracle as O
+    from paper_2503_15259_amd import instances as I
+    w = I.WORKLOADS[WORKLOAD]
+    inst = I.workload_instance(WORKLOAD, index)
+    t0 = time.perf_counter()
+    prob = O.problem_from_instance(inst, variant, eps=EPS)   # includes SigmaHat
+    x = O.psca(prob, w["iters"])
+    dt = time.perf_counter() - t0
+    return variant, index, dt, x
+
+
+def cpu_baseline(n_per_variant=2):
+    tasks = [(v, i) for i in range(n_per_variant) for v in range(4)]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(len(tasks), cores, 16))
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_task, tasks)
+    wall = time.perf_counter() - t0
+    per = [r[2] for r in res]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info = {
+        "value": len(tasks) / wall,
+        "unit": "instances/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": (f"{len(tasks)} detections ({n_per_variant} instances x 4 estimators) of the same "
+                   f"workload, FP64 NumPy oracle, one single-threaded process per detection"),
+        "s_per_instance_1core": sum(per) / len(per),
+        "wall_s": wall,
+        "cpu": model or platform.processor(),
+    }
+    return info, {(r[0], r[1]): r[3] for r in res}
+
+
+# ---------------------------------------------------------------------------
+# GPU leg
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(independent instances would shard by instance with no communication).", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        sys.exit("--steps must be >= 1 and --warmup >= 0")
+
+    cpu_info, cpu_x = (None, {})
+    if not args.no_cpu_baseline:
+        cpu_info, cpu_x = cpu_baseline()
+
+    import numpy as np
+    import torch
+    from paper_2503_15259_amd import instances as I
+    from paper_2503_15259_amd import metrics
+    from paper_2503_15259_amd import psca as P
+
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = I.WORKLOADS[WORKLOAD]
+    N, L, M, iters = w["N"], w["L"], w["M"], w["iters"]
+
+    insts = [I.workload_instance(WORKLOAD, i) for i in range(POOL)]
+    Ys = [P.colmajor(torch.from_numpy(x.Y.astype(np.complex64)).to(dev)) for x in insts]
+    Ss = [P.colmajor(torch.from_numpy(x.S.astype(np.complex64)).to(dev)) for x in insts]
+    gs = [torch.from_numpy(x.g.astype(np.float32)).to(dev) for x in insts]
+    ps = [torch.full((N,), x.p, dtype=torch.float32, device=dev) for x in insts]
+    params = []
+    for i, inst in enumerate(insts):
+        row = []
+        for v in range(4):
+            kw = dict(variant=v, iters=iters, sigma2=inst.sigma2, M=M, d_lo=inst.d_lo, d_hi=inst.d_hi,
+                      pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS)
+            if v in (P.ML_K, P.MAP_K):
+                kw["g"] = gs[i]
+            if v == P.MAP_K:
+                kw["p"] = ps[i]
+            row.append(P.Params(**kw))
+        params.append(row)
+    outs = [[torch.empty(N, dtype=torch.float32, device=dev) for _ in range(4)] for _ in range(POOL)]
+    status = torch.zeros(4, dtype=torch.int32, device=dev)
+    ctxs = [P.Context(0) for _ in range(4)]
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step(s, events=None):
+        for v in range(4):
+            i = (4 * s + v) % POOL
+            if events is not None:
+                events[v][0].record(stream)
+            P.detect_y(Ys[i], Ss[i], params[i][v], ctx=ctxs[v], out=outs[i][v], status=status[v:v + 1])
+            if events is not None:
+                events[v][1].record(stream)
+
+    for s in range(args.warmup):
+        one_step(s)
+    torch.cuda.synchronize()
+
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(4)]
+          for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for s in range(args.steps):
+        one_step(s, ev[s])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    per_variant_ms = [float(np.mean([ev[s][v][0].elapsed_time(ev[s][v][1]) for s in range(args.steps)]))
+                      for v in range(4)]
+    assert int(status.abs().sum().item()) == 0, "device reported a factorisation failure"
+
+    ms_per_step = total_ms / args.steps
+    value = 4.0 * args.steps / (total_ms / 1e3)
+
+    # detection quality at the equal-error point, one pass over the pool
+    eer = {}
+    xs = {}
+    for v in range(4):
+        scores, truth = [], []
+        for i in range(POOL):
+            x = P.detect_y(Ys[i], Ss[i], params[i][v], ctx=ctxs[v])
+            xs[(v, i)] = x
+        torch.cuda.synchronize()
+        for i in range(POOL):
+            scores.append(xs[(v, i)].cpu().numpy())
+            truth.append(insts[i].alpha)
+        e, theta, pmd, pfa = metrics.equal_error_point(np.concatenate(scores), np.concatenate(truth))
+        eer[VARIANT_NAMES[v]] = {"eer": round(e, 5), "theta": theta, "p_md": round(pmd, 5), "p_fa": round(pfa, 5)}
+
+    # parity of the GPU outputs against the oracle outputs of the CPU-baseline sample
+    parity = None
+    if cpu_x:
+        worst = {}
+        for (v, i), xr in cpu_x.items():
+            xg = xs[(v, i)].cpu().numpy().astype(np.float64)
+            if v in (P.ML_K, P.MAP_K):
+                err = float(np.max(np.abs(xg - xr)))
+                key = "max_abs_err_alpha"
+            else:
+                big = np.abs(xr) >= 1e-3 * np.max(np.abs(xr))
+                err = float(np.max(np.abs(xg - xr)[big] / np.abs(xr[big])))
+                key = "max_rel_err_gamma"
+            name = VARIANT_NAMES[v]
+            worst[name] = {key: max(err, worst.get(name, {}).get(key, 0.0))}
+        parity = worst
+
+    flops = algorithmic_flops(N, L, M, iters)
+    # the detection chain of one estimator is the unit timed by the per-call events
+    avg_call_s = float(np.mean(per_variant_ms)) / 1e3
+    achieved = flops / avg_call_s / 1e12
+    roofline = {
+        "bound": "mfma",
+        "achieved": round(achieved, 4),
+        "peak": PEAK_FP32_MFMA_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6),
+        "traffic": None,
+        "kernel": "psca_detect_y chain (sample covariance + 100 iterations)",
+        "flops_per_launch": flops,
+        "avg_launch_ms": round(avg_call_s * 1e3, 4),
+    }
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"single-instance PSCA detection N={N} L={L} M={M}, {iters} iterations, "
+                        "one instance per estimator (ML-K, MAP-K, ML-UD, MAP-UR) per step",
+            "N": N, "L": L, "M": M, "p": w["p"], "iters": iters, "instances_per_step": 4,
+            "eps_map_ur": EPS, "pool": POOL,
+        },
+        "per_estimator_ms": {VARIANT_NAMES[v]: round(per_variant_ms[v], 4) for v in range(4)},
+        "equal_error": eer,
+        "parity_vs_oracle": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu_info,
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

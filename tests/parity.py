@@ -24,10 +24,10 @@ def parity_report(x_gpu, x_ref, variant):
         bad = err > ABS_ALPHA
         return {"max_abs": float(err.max()), "n_bad": int(bad.sum()), "bad": np.nonzero(bad)[0]}
     scale = float(np.max(np.abs(x_ref))) if x_ref.size else 0.0
-    big = np.abs(x_ref) >= FLOOR_FRAC * scale
+    big = (np.abs(x_ref) >= FLOOR_FRAC * scale) & (np.abs(x_ref) > 0)
     tol = np.where(big, REL_GAMMA * np.abs(x_ref), ABS_SMALL_GAMMA * scale)
     bad = err > tol
-    rel = err[big] / np.abs(x_ref[big]) if big.any() else np.zeros(1)
+    rel = err[big] / np.abs(x_ref[big]) if (big.any() and scale > 0) else np.zeros(1)
     return {"max_rel_big": float(rel.max()), "max_abs_small_over_scale":
             float((err[~big].max() / scale) if (~big).any() and scale > 0 else 0.0),
             "n_bad": int(bad.sum()), "bad": np.nonzero(bad)[0]}
