@@ -24,7 +24,9 @@
  *     detected on the host before any launch (PSCA_EINVAL, nothing written).
  *     Numerical failure found on the device (a Cholesky pivot <= 0 or not
  *     finite) is written to the optional device word `status` (PSCA_ENOTPD);
- *     the iterate stops advancing at the last finite value.
+ *     the iterate stops advancing at the last finite value.  PSCA_ESYNC in
+ *     `status` means the persistent kernel's device-wide barrier gave up
+ *     waiting (bounded wait; the kernel still exits) and x_out is not valid.
  *   - Work buffers live in the context (grown on demand with hipMalloc);
  *     calls on one context must not overlap in time (use one context per
  *     concurrent stream).
@@ -54,7 +56,8 @@ typedef enum {
   PSCA_ENOTPD = -2,   /* Sigma not numerically positive definite (device) */
   PSCA_EHIP = -3,     /* a HIP runtime call failed */
   PSCA_ENOMEM = -4,   /* device allocation failed */
-  PSCA_ENOTSUP = -5   /* size outside what this build supports (e.g. L > PSCA_MAX_L) */
+  PSCA_ENOTSUP = -5,  /* size outside what this build supports (e.g. L > PSCA_MAX_L) */
+  PSCA_ESYNC = -6     /* a device-wide barrier timed out (device status word only) */
 } psca_status;
 
 /* Largest pilot length L handled on chip (the L x L factor lives in LDS). */

@@ -15,6 +15,7 @@ PSCA_ENOTPD = -2
 PSCA_EHIP = -3
 PSCA_ENOMEM = -4
 PSCA_ENOTSUP = -5
+PSCA_ESYNC = -6
 
 ML_K, MAP_K, ML_UD, MAP_UR = 0, 1, 2, 3
 MAX_L = 96
