@@ -37,6 +37,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 
 #include "psca.h"
 
@@ -48,21 +49,33 @@ constexpr int kMaxL = PSCA_MAX_L;                          // 96
 constexpr int kMaxNcb = 4;                                 // column blocks per workgroup
 constexpr unsigned kSpinLimit = 1u << 20;                  // grid-barrier wait bound
 
-// Register-array sizes of k_psca for a padded pilot length of at most LPMAX
-// with THREADS threads per workgroup.
-template <int LPMAX, int THREADS>
-struct Shape {
-  static constexpr int kWaves = THREADS / 64;
-  static constexpr int kMaxLb = LPMAX / kBlk;
-  static constexpr int kMaxNB = kMaxLb * (kMaxLb + 1) / 2;
-  static constexpr int kMaxTri = LPMAX * (LPMAX + 1) / 2;
-  static constexpr int kSlots = (kMaxTri + THREADS - 1) / THREADS;     // entries per thread
-  static constexpr int kRowBlocksPerWave = (kMaxLb + kWaves - 1) / kWaves;
-  static constexpr int kBlocksPerWave = (kMaxNB + kWaves - 1) / kWaves;
-  static constexpr int kKSteps = LPMAX / 4;
-};
-
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Optional phase timer for profiling builds (-DPSCA_PHASE_TRACE): workgroup 0
+// stamps the 100 MHz real-time counter at phase boundaries of each iteration.
+#ifdef PSCA_PHASE_TRACE
+constexpr int kTraceIters = 128, kTraceMarks = 16;
+__device__ unsigned long long g_phase_trace[kTraceIters * kTraceMarks];
+__device__ unsigned long long g_step_trace[128];
+__device__ unsigned long long g_sub_trace[128 * 4];
+#define PSCA_SUB_MARK(it, k, id)                                                             \
+  do {                                                                                      \
+    if ((it) == 5 && blockIdx.x == 0 && threadIdx.x == 0) g_sub_trace[(k) * 4 + (id)] = __builtin_readcyclecounter(); \
+  } while (0)
+#define PSCA_STEP_MARK(it, k)                                                               \
+  do {                                                                                      \
+    if ((it) == 5 && blockIdx.x == 0 && threadIdx.x == 0) g_step_trace[k] = __builtin_amdgcn_s_memrealtime(); \
+  } while (0)
+#define PSCA_MARK(it, id)                                                                   \
+  do {                                                                                      \
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (it) < kTraceIters)                          \
+      g_phase_trace[(it) * kTraceMarks + (id)] = __builtin_amdgcn_s_memrealtime();          \
+  } while (0)
+#else
+#define PSCA_MARK(it, id) ((void)0)
+#define PSCA_STEP_MARK(it, k) ((void)0)
+#define PSCA_SUB_MARK(it, k, id) ((void)0)
+#endif
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -75,6 +88,10 @@ __device__ __forceinline__ void cmfma(float2 a, float2 b, f4 &cr, f4 &ci) {
   ci = mfma4(a.x, b.y, ci);
   ci = mfma4(a.y, b.x, ci);
 }
+
+// Keeps the enclosing block a real (scalar) branch: the compiler may not
+// speculate it into unconditional code plus selects.
+#define PSCA_KEEP_BRANCH() asm volatile("" ::: "memory")
 
 __device__ __forceinline__ float2 cmul_conj(float2 a, float2 b) {  // a * conj(b)
   return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
@@ -157,32 +174,52 @@ __device__ __forceinline__ float coordinate_step(float x, float q, float r, floa
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier (agent scope).  bar[0] counts arrivals, bar[1] is the
-// generation.  A waiter gives up after kSpinLimit polls and raises *abort,
-// which every workgroup checks, so a missing workgroup cannot hang the grid.
+// Grid barrier (agent scope).  Each workgroup raises its own arrival word
+// (64-byte stride, no contended atomics); workgroup 0 gathers them and
+// publishes the generation.  Every wait is bounded by kSpinLimit polls: a
+// waiter that gives up raises *abort, and all waiters also watch *abort, so a
+// missing workgroup cannot hang the grid.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned G, unsigned &gen, int32_t *abort_flag,
-                                          int *s_ok) {
+struct GridBar {
+  unsigned *arrive;    // [G * 16]
+  unsigned *release;   // generation published by workgroup 0
+  int32_t *abort_flag;
+};
+
+__device__ __forceinline__ bool spin_until(const unsigned *word, unsigned target, const int32_t *abort_flag) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+    if (++spins > kSpinLimit) return false;
+    if ((spins & 255u) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool grid_sync(const GridBar &b, unsigned G, unsigned &gen, int *s_ok) {
   __syncthreads();
+  const unsigned target = gen + 1;
+  gen = target;
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&b.arrive[blockIdx.x * 16], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (blockIdx.x == 0) {
     int ok = 1;
-    const unsigned target = gen + 1;
-    const unsigned old = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == G - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) { ok = 0; break; }
-        if ((spins & 1023u) == 0 &&
-            __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
-      }
+    for (unsigned w = threadIdx.x; w < G; w += blockDim.x)
+      if (!spin_until(&b.arrive[w * 16], target, b.abort_flag)) ok = 0;
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) {
+      if (!ok) __hip_atomic_store(b.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      __hip_atomic_store(b.release, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-    gen = target;
-    if (!ok) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) {
+    int ok = spin_until(b.release, target, b.abort_flag) ? 1 : 0;
+    if (__hip_atomic_load(b.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    if (!ok) __hip_atomic_store(b.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *s_ok = ok;
   }
   __syncthreads();
@@ -195,7 +232,7 @@ __device__ __forceinline__ bool grid_sync(unsigned *bar, unsigned G, unsigned &g
 struct CoopArgs {
   const float2 *S;      // L x N, column-major
   const float2 *Sh;     // L x L, column-major
-  int L, N, Lp, Lb, NB; // Lp = L rounded up to 16, Lb = Lp / 16, NB = Lb (Lb + 1) / 2
+  int L, N;
   int G, ncb, NT;       // workgroups, 16-column blocks per workgroup, columns per workgroup
   int iters;
   double rho0, rho_decay;
@@ -208,45 +245,226 @@ struct CoopArgs {
   int32_t *status;
   float2 *partials;     // [G][NB * 256]
   float2 *sigma;        // [NB * 256]
-  unsigned *bar;        // [2]
-  int32_t *abort_flag;
+  GridBar bar;
 };
 
-// LDS footprint in bytes for a launch shape
-__host__ __device__ inline size_t lds_bytes(int Lp, int NT, int Lb) {
-  const size_t pt = (size_t)NT + 1;
-  size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * Lp + 5 * (size_t)Lp;
-  size_t fl = 3 * (size_t)NT + 2 * (size_t)Lb * NT;
-  return f2 * sizeof(float2) + fl * sizeof(float);
+// LDS footprint in bytes of k_psca<Lp, 64 * waves> for NT columns per workgroup
+__host__ __device__ inline size_t lds_bytes(int Lp, int NT, int waves) {
+  const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
+  const bool sh_lds = Lp <= 64;
+  const size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256 + 32 +
+                    (size_t)waves * 64;
+  const size_t f4b = 3 * (size_t)NT + 2 * Lb * NT + (size_t)Lp;   // floats
+  return f2 * sizeof(float2) + f4b * 4;
+}
+
+#define PSCA_LDS_F2(p) (*(const float2 *)(p))
+
+// Complex 16x16 block product C += A * B with both operands in LDS,
+// column-major with pitch ld: A[i][k] at A[k * ld + i], B[k][j] at B[j * ld + k].
+__device__ __forceinline__ void cblock_mma(const float2 *A, const float2 *B, int ld, int l16, int lq, f4 &cr,
+                                           f4 &ci) {
+  float2 a[4], b[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    a[ks] = A[(4 * ks + lq) * ld + l16];
+    b[ks] = B[l16 * ld + 4 * ks + lq];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) cmfma(a[ks], b[ks], cr, ci);
+}
+
+// Complex 16x16 block product over k in [k0, k0 + 16): A column-major in LDS
+// (A[i][k] at A[k * lda + i]), B row-major in LDS (B[k][j] at B[k * ldb + j]).
+__device__ __forceinline__ void cblock_mma_rm(const float2 *A, int lda, const float2 *B, int ldb, int k0, int l16,
+                                              int lq, f4 &cr, f4 &ci) {
+  float2 a[4], b[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = k0 + 4 * ks + lq;
+    a[ks] = A[k * lda + l16];
+    b[ks] = B[k * ldb + l16];
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) cmfma(a[ks], b[ks], cr, ci);
+}
+
+// ---------------------------------------------------------------------------
+// Factorisation state and the compile-time pivot schedule
+// ---------------------------------------------------------------------------
+// Thread tid's slot s holds packed entry s * THREADS + tid of the Cholesky
+// triangle (column-packed) and of the diagonal 16x16 blocks of W = L^-1
+// (block by block, row-packed), so slot s of all threads covers one
+// contiguous range of entries whose columns / rows are known at compile time.
+// Every pivot step is generated for its k: it touches only the slots still
+// holding entries to update, with fixed LDS offsets and no bookkeeping.
+template <int LP, int THREADS>
+struct FactorGeom {
+  static constexpr int Tp = LP * (LP + 1) / 2;
+  static constexpr int Td = (LP / 16) * 136;
+  static constexpr int kSlots = (Tp + THREADS - 1) / THREADS;
+  static constexpr int kWSlots = (Td + THREADS - 1) / THREADS;
+  static constexpr int P = LP + 1;
+  static constexpr int col_of(int e) {   // column of column-packed entry e
+    int j = 0, st = 0;
+    while (st + (LP - j) <= e) { st += LP - j; ++j; }
+    return j;
+  }
+  static constexpr int c_lo(int s) { return col_of(s * THREADS); }
+  static constexpr int c_hi(int s) { return col_of(s * THREADS + THREADS - 1 < Tp ? s * THREADS + THREADS - 1 : Tp - 1); }
+  static constexpr int w_e0(int s) { return s * THREADS; }
+  static constexpr int w_e1(int s) { return s * THREADS + THREADS - 1 < Td ? s * THREADS + THREADS - 1 : Td - 1; }
+  // W slot s holds rows >= k of the diagonal block containing k
+  static constexpr bool w_act(int s, int k) {
+    return w_e0(s) <= (k / 16) * 136 + 135 && w_e1(s) >= (k / 16) * 136 + (k % 16) * (k % 16 + 1) / 2;
+  }
+};
+
+template <int LP, int THREADS>
+struct FactorState {
+  using Geo = FactorGeom<LP, THREADS>;
+  float2 av[Geo::kSlots], wx[Geo::kWSlots];
+  int c_i8[Geo::kSlots], c_j8[Geo::kSlots];   // LDS byte offsets row*8 / column*8
+  int w_i[Geo::kWSlots], w_c[Geo::kWSlots];   // (row, column) of the W entry
+  float2 *WS, *wbuf, *dummy;
+  float *rsv;
+  int tid;
+  float rs_prev;
+  bool failed;
+};
+
+template <int LP, int THREADS, int S>
+__device__ __forceinline__ void fstep_load(FactorState<LP, THREADS> &F, int k, const char *colk, float2 *cu,
+                                           float2 *cv) {
+  using Geo = FactorGeom<LP, THREADS>;
+  if (Geo::c_hi(S) > k) {   // uniform: slot S still holds trailing entries
+    cu[S] = *(const float2 *)(colk + F.c_i8[S]);
+    cv[S] = *(const float2 *)(colk + F.c_j8[S]);
+  }
+}
+
+template <int LP, int THREADS, int S>
+__device__ __forceinline__ void fstep_wload(FactorState<LP, THREADS> &F, int k, const char *colp,
+                                            const float2 *wprev, float2 *wl, float2 *ww) {
+  using Geo = FactorGeom<LP, THREADS>;
+  if ((k & 15) != 0 && Geo::w_act(S, k)) {
+    wl[S] = *(const float2 *)(colp + 8 * F.w_i[S]);
+    ww[S] = wprev[F.w_c[S] & 15];
+  }
+}
+
+template <int LP, int THREADS, int S>
+__device__ __forceinline__ void fstep_wupd(FactorState<LP, THREADS> &F, int k, const float2 *wl,
+                                           const float2 *ww, float rs, float2 *wnew) {
+  using Geo = FactorGeom<LP, THREADS>;
+  if (Geo::w_act(S, k)) {
+    if ((k & 15) != 0) {   // X[i][c] -= L[i][k-1] W[k-1][c], rows i >= k, columns c < k of k's block
+      const float m = ((F.w_i[S] >> 4) == (k >> 4) && F.w_i[S] >= k && F.w_c[S] < k) ? F.rs_prev : 0.0f;
+      const float2 t = cmul(wl[S], ww[S]);
+      F.wx[S].x -= t.x * m;
+      F.wx[S].y -= t.y * m;
+    }
+    const bool fin = (F.w_i[S] == k);   // row k is final: W[k][c] = X[k][c] / L[k][k]
+    const float f = fin ? rs : 1.0f;
+    F.wx[S].x *= f;
+    F.wx[S].y *= f;
+    *(fin ? &wnew[F.w_c[S] & 15] : &F.dummy[F.tid]) = F.wx[S];
+  }
+}
+
+template <int LP, int THREADS, int S>
+__device__ __forceinline__ void fstep_upd(FactorState<LP, THREADS> &F, int k, const float2 *cu,
+                                          const float2 *cv, float invd) {
+  using Geo = FactorGeom<LP, THREADS>;
+  if (Geo::c_hi(S) > k) {   // A[i][j] -= A[i][k] conj(A[j][k]) / A[k][k]
+    const float2 t = cmul_conj(cu[S], cv[S]);
+    F.av[S].x -= t.x * invd;
+    F.av[S].y -= t.y * invd;
+    if (Geo::c_lo(S) <= k + 1) {   // publish column k+1
+      const bool pub = (F.c_j8[S] == 8 * (k + 1));
+      *(pub ? &F.WS[(k + 1) * Geo::P + (F.c_i8[S] >> 3)] : &F.dummy[F.tid]) = F.av[S];
+    }
+  }
+}
+
+// One right-looking step k: read the raw pivot column k (published in LDS
+// after step k-1), update the trailing entries, publish column k+1; the
+// diagonal W block of k advances one step behind (row k-1 updates rows >= k,
+// then row k is scaled by 1 / L[k][k] and published).  The slot loops are
+// unrolled, so each slot's column range is a constant and the tests against
+// k are uniform scalar branches.
+template <int LP, int THREADS, int... Ss, int... Ws>
+__device__ __forceinline__ void fstep(FactorState<LP, THREADS> &F, int k, std::integer_sequence<int, Ss...>,
+                                      std::integer_sequence<int, Ws...>) {
+  using Geo = FactorGeom<LP, THREADS>;
+  constexpr int P = Geo::P;
+  __syncthreads();
+  const char *colk = (const char *)(F.WS + k * P);                           // raw pivot column k
+  const char *colp = (const char *)(F.WS + ((k & 15) ? k - 1 : k) * P);      // raw column k-1
+  const float2 *wprev = F.wbuf + ((k + 1) & 1) * 16;                          // row k-1 of the W block
+  float2 cu[Geo::kSlots], cv[Geo::kSlots], wl[Geo::kWSlots], ww[Geo::kWSlots];
+  (fstep_load<LP, THREADS, Ss>(F, k, colk, cu, cv), ...);
+  (fstep_wload<LP, THREADS, Ws>(F, k, colp, wprev, wl, ww), ...);
+  const float d = ((const float2 *)colk)[k].x;
+  if (!(d > 0.0f) || !(d < INFINITY)) {   // uniform: every thread reads the same pivot
+    F.failed = true;
+    return;
+  }
+  float rs = __builtin_amdgcn_rsqf(d);
+  rs = rs * (1.5f - 0.5f * d * rs * rs);   // one Newton step
+  const float invd = rs * rs;
+  if (F.tid == 0) F.rsv[k] = rs;
+  float2 *wnew = F.wbuf + (k & 1) * 16;
+  (fstep_wupd<LP, THREADS, Ws>(F, k, wl, ww, rs, wnew), ...);
+  (fstep_upd<LP, THREADS, Ss>(F, k, cu, cv, invd), ...);
+  F.rs_prev = rs;
+}
+
+template <int LP, int THREADS>
+__device__ __forceinline__ void factor_all(FactorState<LP, THREADS> &F) {
+  using Geo = FactorGeom<LP, THREADS>;
+#pragma unroll 1
+  for (int k = 0; k < LP; ++k) {
+    fstep(F, k, std::make_integer_sequence<int, Geo::kSlots>{}, std::make_integer_sequence<int, Geo::kWSlots>{});
+    if (F.failed) break;   // uniform
+  }
 }
 
 template <int LPMAX, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
-  using Sh = Shape<LPMAX, THREADS>;
-  constexpr int kWaves = Sh::kWaves;
-  constexpr int kMaxSlots = Sh::kSlots;
-  constexpr int kMaxRowBlocksPerWave = Sh::kRowBlocksPerWave;
-  constexpr int kMaxBlocksPerWave = Sh::kBlocksPerWave;
-  constexpr int kMaxKSteps = Sh::kKSteps;
+  constexpr int kWaves = THREADS / 64;
+  constexpr int Lp = LPMAX, Lb = LPMAX / kBlk, NB = Lb * (Lb + 1) / 2;   // padded pilot length
+  constexpr int P = Lp + 1;                                             // pitch of the L x L LDS matrix
+  constexpr bool kShLds = LPMAX <= 64;                                  // SigmaHat resident in LDS
+  constexpr int Tp = Lp * (Lp + 1) / 2;                                 // lower-triangle entries
+  constexpr int kSlots = (Tp + THREADS - 1) / THREADS;                  // Cholesky entries per thread
+  constexpr int Td = Lb * 136;                                          // entries of the diagonal W blocks
+  constexpr int kWSlots = (Td + THREADS - 1) / THREADS;
+  constexpr int kRowBlocksPerWave = (Lb + kWaves - 1) / kWaves;
+  constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
+  static_assert(kSlots <= 20, "Duff dispatch covers 20 slots");
   extern __shared__ float4 smem_raw[];
   __shared__ int s_ok;
-  const int Lp = A.Lp, Lb = A.Lb, NB = A.NB, NT = A.NT, PT = A.NT + 1;
+  const int NT = A.NT, PT = A.NT + 1;
   float2 *St = (float2 *)smem_raw;          // [Lp][PT]  S tile, row i at i * PT
   float2 *Bt = St + Lp * PT;                // [Lp][PT]  B tile (also reduction scratch)
-  float2 *WS = Bt + Lp * PT;                // [Lp][Lp]  W (row-major) then Sigma^-1 (column-major)
-  float2 *colbuf = WS + Lp * Lp;            // [3][Lp]   published pivot columns
-  float2 *wbuf = colbuf + 3 * Lp;           // [2][Lp]   published rows of W
-  float *xs = (float *)(wbuf + 2 * Lp);     // [NT] iterate of the tile
+  float2 *WS = Bt + Lp * PT;                // [Lp][P]   column-major: Cholesky columns, W, Sigma^-1
+  float2 *ShL = WS + Lp * P;                // [Lp][P]   SigmaHat, column-major (kShLds)
+  float2 *scr = ShL + (kShLds ? Lp * P : 0);// [kWaves][256] per-wave 16x16 scratch
+  float2 *wbuf = scr + kWaves * 256;        // [2][16]   published rows of a diagonal W block
+  float2 *dummy = wbuf + 32;                // [THREADS] write sink of the factorisation step
+  float *xs = (float *)(dummy + THREADS);   // [NT] iterate of the tile
   float *gs = xs + NT;                      // [NT] pathloss
   float *ls = gs + NT;                      // [NT] log(p / (1 - p))
   float *red_q = ls + NT;                   // [Lb][NT]
   float *red_r = red_q + Lb * NT;           // [Lb][NT]
+  float *rsv = red_r + Lb * NT;             // [Lp] 1 / L[k][k]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int g = blockIdx.x;
   const int n0 = g * NT;
-  const int E = NB * 256;
+  constexpr int E = NB * 256;
   unsigned gen = 0;
   const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
 
@@ -268,51 +486,48 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
     }
     ls[c] = lg;
   }
-  // ---- ownership of lower-triangle entries for the factorisation --------
-  // Cholesky entries in column-packed order, W entries in row-packed order;
-  // chunk c of 64 consecutive entries belongs to wave c % 4, slot c / 4.
-  // Packed per slot: (bound << 16) | (i << 8) | j  with bound = last column
-  // (Cholesky) or last row (W) of the chunk; i = 255 marks an empty slot.
-  const int Tp = Lp * (Lp + 1) / 2;
-  int ch_meta[kMaxSlots], w_meta[kMaxSlots];
-#pragma unroll
-  for (int s = 0; s < kMaxSlots; ++s) {
-    const int chunk = kWaves * s + wave;
-    const int e = chunk * 64 + lane;
-    const int elast = min(chunk * 64 + 63, Tp - 1);
-    int ci = 255, cj = 0, cbound = -1, wi = 255, wc = 0, wbound = -1;
-    if (chunk * 64 < Tp) {
-      // column-packed: column j holds rows j..Lp-1
-      int j = 0, start = 0;
-      while (j < Lp && start + (Lp - j) <= elast) { start += Lp - j; ++j; }
-      cbound = j;  // column of the chunk's last entry
-      if (e < Tp) {
-        int jj = 0, st = 0;
-        while (st + (Lp - jj) <= e) { st += Lp - jj; ++jj; }
-        cj = jj;
-        ci = jj + (e - st);
-      }
-      // row-packed: row i holds columns 0..i
-      int r = 0;
-      while ((r + 1) * (r + 2) / 2 <= elast) ++r;
-      wbound = r;
-      if (e < Tp) {
-        int rr = 0;
-        while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
-        wi = rr;
-        wc = e - rr * (rr + 1) / 2;
-      }
+  if constexpr (kShLds) {
+    for (int e = tid; e < Lp * Lp; e += THREADS) {
+      const int k = e / Lp, i = e - k * Lp;
+      ShL[k * P + i] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
     }
-    ch_meta[s] = ((cbound & 0xff) << 16) | (ci << 8) | cj;
-    w_meta[s] = ((wbound & 0xff) << 16) | (wi << 8) | wc;
-    if (cbound < 0) ch_meta[s] = (0xff << 8);          // empty chunk: never active
-    if (wbound < 0) w_meta[s] = (0xff << 8);
+  }
+
+  // ---- ownership of the factorisation's entries ---------------------------
+  // Cholesky: lower-triangle entries in column-packed order.  W: entries of
+  // the 16x16 diagonal blocks of L^-1, block by block, row-packed inside a
+  // block.  Thread tid's slot s holds entry s * THREADS + tid; threads past
+  // the last entry alias the last entry (Lp-1, Lp-1) and repeat its
+  // arithmetic exactly.
+  FactorState<Lp, THREADS> F;
+  F.WS = WS;
+  F.wbuf = wbuf;
+  F.dummy = dummy;
+  F.rsv = rsv;
+  F.tid = tid;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int e = min(s * THREADS + tid, Tp - 1);
+    int j = 0, st = 0;
+    while (st + (Lp - j) <= e) { st += Lp - j; ++j; }
+    F.c_j8[s] = j * 8;
+    F.c_i8[s] = (j + (e - st)) * 8;
+  }
+#pragma unroll
+  for (int s = 0; s < kWSlots; ++s) {
+    const int e = min(s * THREADS + tid, Td - 1);
+    const int I = e / 136, r = e - I * 136;
+    int ii = 0;
+    while ((ii + 1) * (ii + 2) / 2 <= r) ++ii;
+    F.w_i[s] = 16 * I + ii;
+    F.w_c[s] = 16 * I + (r - ii * (ii + 1) / 2);
   }
 
   double rho_d = A.rho0;
   bool failed = false, aborted = false;
   int it = 0;
   for (; it < A.iters; ++it) {
+    PSCA_MARK(it, 0);
     // ===== A. partial of Sigma from this tile =============================
     for (int c = tid; c < NT; c += THREADS)   // weights w_c
       red_q[c] = known ? gs[c] * xs[c] : xs[c];
@@ -320,35 +535,47 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
     {
       const float *wv = red_q;
       float2 *dst = A.partials + (size_t)g * E;
-      for (int b = wave; b < NB; b += kWaves) {
-        int I, J;
-        blk_coords(b, I, J);
-        f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-        for (int c0 = 0; c0 < NT; c0 += 4) {
-          const int c = c0 + lq;
-          const float2 a = St[(16 * I + l16) * PT + c];
-          const float2 s = St[(16 * J + l16) * PT + c];
-          const float w = wv[c];
-          cmfma(a, make_float2(w * s.x, -w * s.y), cr, ci);
+#pragma unroll
+      for (int q = 0; q < kBlocksPerWave; ++q) {
+        const int b = wave + kWaves * q;
+        if (b < NB) {
+          int I, J;
+          blk_coords(b, I, J);
+          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+          for (int cb = 0; cb < A.ncb; ++cb) {
+            float2 av4[4], bv4[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+              const int c = 16 * cb + 4 * ks + lq;
+              const float2 s = St[(16 * J + l16) * PT + c];
+              const float w = wv[c];
+              av4[ks] = St[(16 * I + l16) * PT + c];
+              bv4[ks] = make_float2(w * s.x, -w * s.y);
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) cmfma(av4[ks], bv4[ks], cr, ci);
+          }
+          float4 *o = (float4 *)(dst + b * 256 + l16 * 16 + 4 * lq);
+          o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
+          o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
         }
-        float4 *o = (float4 *)(dst + b * 256 + l16 * 16 + 4 * lq);
-        o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
-        o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
       }
     }
-    if (!grid_sync(A.bar, A.G, gen, A.abort_flag, &s_ok)) { aborted = true; break; }
+    PSCA_MARK(it, 1);
+    if (!grid_sync(A.bar, A.G, gen, &s_ok)) { aborted = true; break; }
 
     // ===== B. reduce a slice of the partials into Sigma ===================
+    PSCA_MARK(it, 2);
     {
       const int per = (E + A.G - 1) / A.G;
       const int start = g * per, end = min(E, start + per);
       const int cnt = max(0, end - start);
       if (cnt > 0 && cnt <= THREADS) {
-        const int P = THREADS / cnt;   // threads per element
-        float2 acc = make_float2(0.f, 0.f);
-        if (tid < cnt * P) {
+        const int Pp = THREADS / cnt;   // threads per element
+        if (tid < cnt * Pp) {
           const int e = start + tid % cnt, part = tid / cnt;
-          for (int h = part; h < A.G; h += P) {
+          float2 acc = make_float2(0.f, 0.f);
+          for (int h = part; h < A.G; h += Pp) {
             const float2 v = A.partials[(size_t)h * E + e];
             acc.x += v.x;
             acc.y += v.y;
@@ -357,11 +584,11 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
         }
         __syncthreads();
         if (tid < cnt) {
-          float2 s = make_float2(0.f, 0.f);
-          for (int part = 0; part < P; ++part) {
+          float2 sm = make_float2(0.f, 0.f);
+          for (int part = 0; part < Pp; ++part) {
             const float2 v = Bt[part * cnt + tid];
-            s.x += v.x;
-            s.y += v.y;
+            sm.x += v.x;
+            sm.y += v.y;
           }
           const int e = start + tid;
           const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
@@ -369,177 +596,171 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
           blk_coords(b, I, J);
           if (I == J && ii == jj) {
             const int i = 16 * I + ii;
-            s.x += (i < A.L) ? A.sigma2 : 1.0f;   // padded rows: isolated unit pivots
-            s.y = 0.0f;
+            sm.x += (i < A.L) ? A.sigma2 : 1.0f;   // padded rows: isolated unit pivots
+            sm.y = 0.0f;
           }
-          A.sigma[e] = s;
+          A.sigma[e] = sm;
         }
       } else {
         for (int e = start + tid; e < end; e += THREADS) {
-          float2 s = make_float2(0.f, 0.f);
+          float2 sm = make_float2(0.f, 0.f);
           for (int h = 0; h < A.G; ++h) {
             const float2 v = A.partials[(size_t)h * E + e];
-            s.x += v.x;
-            s.y += v.y;
+            sm.x += v.x;
+            sm.y += v.y;
           }
           const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
           int I, J;
           blk_coords(b, I, J);
           if (I == J && ii == jj) {
             const int i = 16 * I + ii;
-            s.x += (i < A.L) ? A.sigma2 : 1.0f;
-            s.y = 0.0f;
+            sm.x += (i < A.L) ? A.sigma2 : 1.0f;
+            sm.y = 0.0f;
           }
-          A.sigma[e] = s;
+          A.sigma[e] = sm;
         }
       }
     }
-    if (!grid_sync(A.bar, A.G, gen, A.abort_flag, &s_ok)) { aborted = true; break; }
+    PSCA_MARK(it, 3);
+    if (!grid_sync(A.bar, A.G, gen, &s_ok)) { aborted = true; break; }
 
-    // ===== C1. Cholesky Sigma = L L^H fused with W = L^-1 ===================
-    float2 av[kMaxSlots], wx[kMaxSlots];
+    // ===== C1. Cholesky Sigma = L L^H, with the diagonal blocks of W = L^-1 ==
+    // Right-looking: at step k every thread reads the raw pivot column k from
+    // WS (published there by the owners of its entries after step k-1) and
+    // updates its trailing entries; the owners of column k+1 publish it into
+    // WS.  The diagonal 16x16 blocks of W advance one step behind inside their
+    // block: row k-1 of W_II updates rows >= k, then row k is scaled by
+    // 1 / L[k][k] and published.  One workgroup barrier per step.
+    PSCA_MARK(it, 4);
 #pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) {
-      const int i = (ch_meta[s] >> 8) & 0xff, j = ch_meta[s] & 0xff;
-      av[s] = (i != 0xff) ? A.sigma[bp_offset(i, j)] : make_float2(0.f, 0.f);
-      const int wi = (w_meta[s] >> 8) & 0xff, wc = w_meta[s] & 0xff;
-      wx[s] = make_float2((wi != 0xff && wi == wc) ? 1.0f : 0.0f, 0.0f);
-    }
-    for (int e = tid; e < Lp * Lp; e += THREADS) WS[e] = make_float2(0.f, 0.f);
+    for (int s = 0; s < kSlots; ++s) F.av[s] = A.sigma[bp_offset(F.c_i8[s] >> 3, F.c_j8[s] >> 3)];
 #pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) {        // publish column 0
-      const int i = (ch_meta[s] >> 8) & 0xff, j = ch_meta[s] & 0xff;
-      if (i != 0xff && j == 0) colbuf[i] = av[s];
-    }
-    float rs_prev = 0.0f;
-    for (int k = 0; k < Lp; ++k) {
-      __syncthreads();
-      const float2 *cbk = colbuf + (k % 3) * Lp;
-      const float d = cbk[k].x;
-      if (!(d > 0.0f) || !(d < INFINITY)) { failed = true; break; }   // uniform
-      const float rs = 1.0f / sqrtf(d);
-      const float invd = rs * rs;
-      if (k > 0) {   // W rows >= k receive row k-1:  X[i][c] -= L[i][k-1] W[k-1][c]
-        const float2 *colp = colbuf + ((k + 2) % 3) * Lp;
-        const float2 *wrow = wbuf + ((k - 1) & 1) * Lp;
+    for (int s = 0; s < kWSlots; ++s) F.wx[s] = make_float2(F.w_i[s] == F.w_c[s] ? 1.0f : 0.0f, 0.0f);
+    for (int e = tid; e < Lp * P; e += THREADS) WS[e] = make_float2(0.f, 0.f);
+    __syncthreads();
 #pragma unroll
-        for (int s = 0; s < kMaxSlots; ++s) {
-          if (((w_meta[s] >> 16) & 0xff) >= k) {
-            const int i = (w_meta[s] >> 8) & 0xff, c = w_meta[s] & 0xff;
-            if (i != 0xff && i >= k && c < k) {
-              const float2 lv = colp[i];
-              const float2 wv = wrow[c];
-              const float2 t = cmul(make_float2(lv.x * rs_prev, lv.y * rs_prev), wv);
-              wx[s].x -= t.x;
-              wx[s].y -= t.y;
-            }
-          }
-        }
-      }
-      {  // finalise row k of W: W[k][c] = X[k][c] / L[k][k]
-        float2 *wnew = wbuf + (k & 1) * Lp;
-#pragma unroll
-        for (int s = 0; s < kMaxSlots; ++s) {
-          const int i = (w_meta[s] >> 8) & 0xff, c = w_meta[s] & 0xff;
-          if (i == k) {
-            wx[s].x *= rs;
-            wx[s].y *= rs;
-            wnew[c] = wx[s];
-          }
-        }
-      }
-      {  // trailing update A[i][j] -= A[i][k] conj(A[j][k]) / A[k][k]; publish column k+1
-        float2 *cbn = colbuf + ((k + 1) % 3) * Lp;
-#pragma unroll
-        for (int s = 0; s < kMaxSlots; ++s) {
-          if (((ch_meta[s] >> 16) & 0xff) > k) {
-            const int i = (ch_meta[s] >> 8) & 0xff, j = ch_meta[s] & 0xff;
-            if (i != 0xff && j > k) {
-              const float2 t = cmul_conj(cbk[i], cbk[j]);
-              av[s].x -= t.x * invd;
-              av[s].y -= t.y * invd;
-              if (j == k + 1) cbn[i] = av[s];
-            }
-          }
-        }
-      }
-      rs_prev = rs;
-    }
+    for (int s = 0; s < kSlots; ++s)          // publish column 0
+      if (F.c_j8[s] == 0) WS[F.c_i8[s] >> 3] = F.av[s];
+    F.rs_prev = 0.0f;
+    F.failed = false;
+    factor_all(F);
+    failed = F.failed;
+    PSCA_MARK(it, 5);
     if (failed) break;   // uniform: every workgroup factors the same Sigma
-
-    // ===== C2. Sigma^-1 = W^H W (MFMA), stored full column-major in WS ======
-#pragma unroll
-    for (int s = 0; s < kMaxSlots; ++s) {
-      const int i = (w_meta[s] >> 8) & 0xff, c = w_meta[s] & 0xff;
-      if (i != 0xff) WS[i * Lp + c] = wx[s];
-    }
     __syncthreads();
-    f4 sir[kMaxBlocksPerWave], sii[kMaxBlocksPerWave];
+
+    // ===== C2. W = L^-1 in WS: diagonal blocks, scaled L below them =========
 #pragma unroll
-    for (int q = 0; q < kMaxBlocksPerWave; ++q) {
-      sir[q] = (f4){0.f, 0.f, 0.f, 0.f};
-      sii[q] = (f4){0.f, 0.f, 0.f, 0.f};
-      const int b = wave + kWaves * q;
-      if (b < NB) {
-        int I, J;
-        blk_coords(b, I, J);
-        for (int k0 = 16 * I; k0 < Lp; k0 += 4) {
-          const int k = k0 + lq;
-          const float2 wi = WS[k * Lp + 16 * I + l16];   // A[i][k] = conj(W[k][i])
-          const float2 wj = WS[k * Lp + 16 * J + l16];   // B[k][j] = W[k][j]
-          cmfma(make_float2(wi.x, -wi.y), wj, sir[q], sii[q]);
-        }
+    for (int s = 0; s < kWSlots; ++s)         // slots past the last entry hold no entry
+      if (s * THREADS < Td) WS[F.w_c[s] * P + F.w_i[s]] = F.wx[s];
+    for (int e = tid; e < Lb * 256; e += THREADS) {   // zero the upper parts of the diagonal blocks
+      const int I = e >> 8, ii = (e >> 4) & 15, cc = e & 15;
+      if (ii < cc) WS[(16 * I + cc) * P + 16 * I + ii] = make_float2(0.f, 0.f);
+    }
+    for (int e = tid; e < Lp * Lp; e += THREADS) {    // L[i][c] = raw * rs_c below the diagonal blocks
+      const int c = e / Lp, i = e - c * Lp;
+      if ((i >> 4) > (c >> 4)) {
+        const float2 v = WS[c * P + i];
+        const float r = rsv[c];
+        WS[c * P + i] = make_float2(v.x * r, v.y * r);
       }
     }
     __syncthreads();
+    // Off-diagonal blocks, right to left: W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ
+    for (int J = Lb - 2; J >= 0; --J) {
+      f4 rr = {0.f, 0.f, 0.f, 0.f}, ri = {0.f, 0.f, 0.f, 0.f};
+      const int I = J + 1 + wave;
+      if (I < Lb) {
+        f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
+        for (int K = J + 1; K <= I; ++K)
+          cblock_mma(WS + (16 * K) * P + 16 * I, WS + (16 * J) * P + 16 * K, P, l16, lq, tr, ti);
+        float2 *T = scr + wave * 256;          // column-major, pitch 16
 #pragma unroll
-    for (int q = 0; q < kMaxBlocksPerWave; ++q) {
-      const int b = wave + kWaves * q;
-      if (b < NB) {
-        int I, J;
-        blk_coords(b, I, J);
+        for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float2 ta[4], wb[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 16 * I + 4 * lq + v, j = 16 * J + l16;
-          if (i >= j) {
-            const float im = (i == j) ? 0.0f : sii[q][v];
-            WS[j * Lp + i] = make_float2(sir[q][v], im);
-            WS[i * Lp + j] = make_float2(sir[q][v], -im);
+        for (int ks = 0; ks < 4; ++ks) {
+          ta[ks] = T[(4 * ks + lq) * 16 + l16];
+          wb[ks] = WS[(16 * J + l16) * P + 16 * J + 4 * ks + lq];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(ta[ks], wb[ks], rr, ri);
+      }
+      __syncthreads();
+      if (I < Lb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) WS[(16 * J + l16) * P + 16 * I + 4 * lq + v] = make_float2(-rr[v], -ri[v]);
+      }
+      __syncthreads();
+    }
+
+    // ===== C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS ======
+    PSCA_MARK(it, 6);
+    {
+      f4 sir[kBlocksPerWave], sii[kBlocksPerWave];
+#pragma unroll
+      for (int q = 0; q < kBlocksPerWave; ++q) {
+        sir[q] = (f4){0.f, 0.f, 0.f, 0.f};
+        sii[q] = (f4){0.f, 0.f, 0.f, 0.f};
+        const int b = wave + kWaves * q;
+        if (b < NB) {
+          int I, J;
+          blk_coords(b, I, J);
+          for (int K = I; K < Lb; ++K) {       // A[i][k] = conj(W[k][i]), B[k][j] = W[k][j]
+            float2 a4[4], b4[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+              const int k = 16 * K + 4 * ks + lq;
+              const float2 wi = WS[(16 * I + l16) * P + k];
+              a4[ks] = make_float2(wi.x, -wi.y);
+              b4[ks] = WS[(16 * J + l16) * P + k];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], sir[q], sii[q]);
           }
         }
       }
-    }
-    __syncthreads();
-
-    // ===== C3. B = Sigma^-1 S_g and q ======================================
-    // SigmaHat fragments (A operand of D = SigmaHat B) for this wave's row
-    // blocks; the loads are issued here and consumed after GEMM 1.
-    float2 shf[kMaxRowBlocksPerWave][kMaxKSteps];
+      __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < kMaxRowBlocksPerWave; ++rb) {
-      const int I = wave + kWaves * rb;
+      for (int q = 0; q < kBlocksPerWave; ++q) {
+        const int b = wave + kWaves * q;
+        if (b < NB) {
+          int I, J;
+          blk_coords(b, I, J);
 #pragma unroll
-      for (int ks = 0; ks < kMaxKSteps; ++ks) {
-        const int i = 16 * I + l16, k = 4 * ks + lq;
-        shf[rb][ks] = (I < Lb && i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * lq + v, j = 16 * J + l16;
+            if (i >= j) {
+              const float im = (i == j) ? 0.0f : sii[q][v];
+              WS[j * P + i] = make_float2(sir[q][v], im);
+              WS[i * P + j] = make_float2(sir[q][v], -im);
+            }
+          }
+        }
       }
+      __syncthreads();
     }
+
+    // ===== C4. B = Sigma^-1 S_g and q;  D = SigmaHat B and r =================
+    PSCA_MARK(it, 7);
 #pragma unroll
-    for (int rb = 0; rb < kMaxRowBlocksPerWave; ++rb) {
+    for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
       const int I = wave + kWaves * rb;
       if (I < Lb) {
         for (int cb = 0; cb < A.ncb; ++cb) {
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-          for (int k0 = 0; k0 < Lp; k0 += 4) {
-            const int k = k0 + lq;
-            cmfma(WS[k * Lp + 16 * I + l16], St[k * PT + 16 * cb + l16], cr, ci);
-          }
+#pragma unroll
+          for (int K = 0; K < Lb; ++K)
+            cblock_mma_rm(WS + 16 * I, P, St + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
           float qp = 0.0f;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int i = 16 * I + 4 * lq + v, j = 16 * cb + l16;
-            const float2 s = St[i * PT + j];
-            qp += s.x * cr[v] + s.y * ci[v];
+            const float2 sv = St[i * PT + j];
+            qp += sv.x * cr[v] + sv.y * ci[v];
             Bt[i * PT + j] = make_float2(cr[v], ci[v]);
           }
           qp += __shfl_xor(qp, 16);
@@ -549,19 +770,29 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
       }
     }
     __syncthreads();
-
-    // ===== C4. D = SigmaHat B and r ========================================
+    PSCA_MARK(it, 8);
 #pragma unroll
-    for (int rb = 0; rb < kMaxRowBlocksPerWave; ++rb) {
+    for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
       const int I = wave + kWaves * rb;
       if (I < Lb) {
         for (int cb = 0; cb < A.ncb; ++cb) {
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+          if constexpr (kShLds) {
 #pragma unroll
-          for (int ks = 0; ks < kMaxKSteps; ++ks) {
-            if (4 * ks < Lp) {
-              const int k = 4 * ks + lq;
-              cmfma(shf[rb][ks], Bt[k * PT + 16 * cb + l16], cr, ci);
+            for (int K = 0; K < Lb; ++K)
+              cblock_mma_rm(ShL + 16 * I, P, Bt + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
+          } else {
+#pragma unroll
+            for (int K = 0; K < Lb; ++K) {
+              float2 a4[4], b4[4];
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) {
+                const int i = 16 * I + l16, k = 16 * K + 4 * ks + lq;
+                a4[ks] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+                b4[ks] = Bt[k * PT + 16 * cb + l16];
+              }
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
             }
           }
           float rp = 0.0f;
@@ -580,6 +811,7 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
     __syncthreads();
 
     // ===== C5. coordinate step and update ==================================
+    PSCA_MARK(it, 9);
     float rho;
     if (A.rho_fixed >= 0.0f) rho = A.rho_fixed;
     else if (A.rho_dev) rho = A.rho_dev[it];
@@ -605,6 +837,7 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
       }
     }
     __syncthreads();
+    PSCA_MARK(it, 10);
   }
 
   // ---- results --------------------------------------------------------------
@@ -640,11 +873,11 @@ __global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restric
   Sh[j + (size_t)i * L] = make_float2(acc.x, -acc.y);
 }
 
-// Reset the barrier and abort words before a launch of k_psca.
-__global__ void k_prepare(unsigned *bar, int32_t *abort_flag, int32_t *status) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    bar[0] = 0u;
-    bar[1] = 0u;
+// Reset the barrier words, the abort word and the status before a launch of k_psca.
+__global__ void k_prepare(unsigned *arrive, int G, unsigned *release, int32_t *abort_flag, int32_t *status) {
+  for (int w = threadIdx.x; w < G; w += blockDim.x) arrive[w * 16] = 0u;
+  if (threadIdx.x == 0) {
+    *release = 0u;
     *abort_flag = 0;
     if (status) *status = PSCA_OK;
   }
@@ -765,12 +998,18 @@ int launch_ok() { return hipGetLastError() == hipSuccess ? PSCA_OK : PSCA_EHIP; 
 struct KernelChoice {
   const void *fn;
   int threads;
+  int lpmax;
 };
 
 KernelChoice pick_kernel(int Lp) {
-  if (Lp <= 32) return {(const void *)k_psca<32, 256>, 256};
-  if (Lp <= 64) return {(const void *)k_psca<64, 256>, 256};
-  return {(const void *)k_psca<96, 512>, 512};
+  switch (Lp) {
+    case 16: return {(const void *)k_psca<16, 256>, 256, 16};
+    case 32: return {(const void *)k_psca<32, 256>, 256, 32};
+    case 48: return {(const void *)k_psca<48, 256>, 256, 48};
+    case 64: return {(const void *)k_psca<64, 256>, 256, 64};
+    case 80: return {(const void *)k_psca<80, 512>, 512, 80};
+    default: return {(const void *)k_psca<96, 512>, 512, 96};
+  }
 }
 
 // Workgroups of `kc` that fit on the device at once with `lds` bytes of LDS.
@@ -802,7 +1041,7 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
     if (ncb > kMaxNcb) return PSCA_ENOTSUP;
     const int NT = 16 * ncb;
     G = (N + NT - 1) / NT;
-    lds = lds_bytes(Lp, NT, Lb);
+    lds = lds_bytes(Lp, NT, kc.threads / 64);
     const int cap = max_coresident(ctx, kc, lds);
     if (cap <= 0) return PSCA_ENOTSUP;
     if (G <= cap) break;
@@ -812,7 +1051,8 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
   size_t off = 0;
   const size_t o_part = off; off = align_up(off + (size_t)G * E * sizeof(float2));
   const size_t o_sig = off;  off = align_up(off + (size_t)E * sizeof(float2));
-  const size_t o_bar = off;  off = align_up(off + 4 * sizeof(unsigned));
+  const size_t o_arr = off;  off = align_up(off + (size_t)G * 16 * sizeof(unsigned));
+  const size_t o_rel = off;  off = align_up(off + sizeof(unsigned));
   const size_t o_abt = off;  off = align_up(off + sizeof(int32_t));
   const size_t o_st = off;   off = align_up(off + sizeof(int32_t));
   int rc = ensure_ws(ctx, off);
@@ -824,9 +1064,6 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
   a.Sh = Sh;
   a.L = L;
   a.N = N;
-  a.Lp = Lp;
-  a.Lb = Lb;
-  a.NB = NB;
   a.G = G;
   a.ncb = ncb;
   a.NT = NT;
@@ -845,14 +1082,15 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
   a.status = status ? status : (int32_t *)(base + o_st);
   a.partials = (float2 *)(base + o_part);
   a.sigma = (float2 *)(base + o_sig);
-  a.bar = (unsigned *)(base + o_bar);
-  a.abort_flag = (int32_t *)(base + o_abt);
+  a.bar.arrive = (unsigned *)(base + o_arr);
+  a.bar.release = (unsigned *)(base + o_rel);
+  a.bar.abort_flag = (int32_t *)(base + o_abt);
 
-  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(64), 0, st, a.bar, a.abort_flag, a.status);
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.bar.arrive, G, a.bar.release, a.bar.abort_flag,
+                     a.status);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
   void *args[] = {&a};
-  if (hipLaunchCooperativeKernel(kc.fn, dim3(G), dim3(kc.threads), args, (unsigned)lds, st) !=
-      hipSuccess) {
+  if (hipLaunchCooperativeKernel(kc.fn, dim3(G), dim3(kc.threads), args, (unsigned)lds, st) != hipSuccess) {
     (void)hipGetLastError();
     return PSCA_EHIP;
   }
@@ -967,6 +1205,23 @@ int psca_iterate(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, in
   return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, 1, rho, x_in, x_out, q_out,
                     r_out, xt_out, status, as_stream(stream));
 }
+
+#ifdef PSCA_PHASE_TRACE
+// Profiling builds only: copy the phase stamps (kTraceIters x kTraceMarks) to host.
+int psca_sub_trace(unsigned long long *host) {
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_sub_trace), sizeof(unsigned long long) * 512) == hipSuccess
+             ? PSCA_OK : PSCA_EHIP;
+}
+int psca_step_trace(unsigned long long *host) {
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_step_trace), sizeof(unsigned long long) * 128) == hipSuccess
+             ? PSCA_OK : PSCA_EHIP;
+}
+int psca_phase_trace(unsigned long long *host, int count) {
+  if (!host || count < kTraceIters * kTraceMarks) return PSCA_EINVAL;
+  return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_phase_trace), sizeof(unsigned long long) * kTraceIters * kTraceMarks) ==
+                 hipSuccess ? PSCA_OK : PSCA_EHIP;
+}
+#endif
 
 int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *stream) {
   if (!x || !support || N < 1) return PSCA_EINVAL;
