@@ -33,18 +33,32 @@ POOL = 8           # distinct instances resident on the GPU
 EPS = 0.01         # MAP-UR Hermite width (noise-normalised units)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per k_psca launch from the FETCH_SIZE and WRITE_SIZE counter
+# passes, each scaled by the copy-kernel calibration (null when the kernel
+# changed after the counters were taken).
+# Measured for k_psca<64, 256> at N=1000, L=64, 100 iterations (profile
+# k_psca_single_N1000_L64_traffic.md): 172.4 MB fetched + 134.8 MB written.
+TRAFFIC_BYTES_PER_LAUNCH = 307144808
 
 
-def algorithmic_flops(N, L, M, iters):
-    """Real flops the method needs: SigmaHat (Hermitian, 4 L^2 M) once; per
-    iteration Sigma (Hermitian, 4 N L^2), B = Sigma^-1 S and D = SigmaHat B
-    (16 N L^2), quadratic forms (8 N L), factor/inverse ((4/3) L^3)."""
-    return 4.0 * L * L * M + iters * (20.0 * N * L * L + 8.0 * N * L + (4.0 / 3.0) * L ** 3)
+def iteration_flops(N, L):
+    """Real flops of one PSCA iteration that the method needs: Sigma
+    (Hermitian, 4 N L^2), B = Sigma^-1 S and Sigma^-1 SigmaHat B (16 N L^2),
+    the quadratic forms (8 N L) and the O(L^3) factor/inverse work, counted
+    as 24 L^3.  Redundant per-workgroup copies of the factorisation are not
+    counted."""
+    return 20.0 * N * L * L + 8.0 * N * L + 24.0 * L ** 3
 
 
-def algorithmic_bytes(N, L, M, iters):
-    """HBM bytes the method must move at least once: Y, S, g/p, x."""
-    return 8.0 * L * M + 8.0 * N * L + 3 * 4.0 * N
+def sample_cov_flops(L, M):
+    """SigmaHat = Y Y^H / M, Hermitian: 4 L^2 M real flops."""
+    return 4.0 * L * L * M
+
+
+def launch_bytes(N, L):
+    """HBM bytes one detection launch must move at least once: S, SigmaHat,
+    g and p in, x out."""
+    return 8.0 * N * L + 8.0 * L * L + 3 * 4.0 * N
 
 
 # ---------------------------------------------------------------------------
@@ -66,7 +80,7 @@ def _oracle_task(args):
     return variant, index, dt, x
 
 
-def cpu_baseline(n_per_variant=2):
+def cpu_baseline(n_per_variant=4):
     tasks = [(v, i) for i in range(n_per_variant) for v in range(4)]
     try:
         cores = len(os.sched_getaffinity(0))
@@ -113,6 +127,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, run one plain copy kernel of this many MiB (profiler calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -158,16 +174,19 @@ def main():
             row.append(P.Params(**kw))
         params.append(row)
     outs = [[torch.empty(N, dtype=torch.float32, device=dev) for _ in range(4)] for _ in range(POOL)]
+    shs = [torch.empty((L, L), dtype=torch.complex64, device=dev).mT for _ in range(4)]
     status = torch.zeros(4, dtype=torch.int32, device=dev)
     ctxs = [P.Context(0) for _ in range(4)]
     stream = torch.cuda.current_stream(dev)
 
     def one_step(s, events=None):
+        """Four detections, one per estimator: SigmaHat from Y, then Algorithm 1."""
         for v in range(4):
             i = (4 * s + v) % POOL
+            P.sample_cov(Ys[i], ctx=ctxs[v], out=shs[v])
             if events is not None:
                 events[v][0].record(stream)
-            P.detect_y(Ys[i], Ss[i], params[i][v], ctx=ctxs[v], out=outs[i][v], status=status[v:v + 1])
+            P.detect(shs[v], Ss[i], params[i][v], ctx=ctxs[v], out=outs[i][v], status=status[v:v + 1])
             if events is not None:
                 events[v][1].record(stream)
 
@@ -188,12 +207,21 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
-    per_variant_ms = [float(np.mean([ev[s][v][0].elapsed_time(ev[s][v][1]) for s in range(args.steps)]))
-                      for v in range(4)]
+    launch_ms = np.array([[ev[s][v][0].elapsed_time(ev[s][v][1]) for v in range(4)] for s in range(args.steps)])
+    per_variant_ms = launch_ms.mean(axis=0)
     assert int(status.abs().sum().item()) == 0, "device reported a factorisation failure"
 
     ms_per_step = total_ms / args.steps
     value = 4.0 * args.steps / (total_ms / 1e3)
+
+    if args.copy_probe_mib > 0:
+        # a plain copy kernel of known size (read n bytes, write n bytes), for
+        # scaling the HBM byte counters of a profiler pass
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
 
     # detection quality at the equal-error point, one pass over the pool
     eer = {}
@@ -227,20 +255,22 @@ def main():
             worst[name] = {key: max(err, worst.get(name, {}).get(key, 0.0))}
         parity = worst
 
-    flops = algorithmic_flops(N, L, M, iters)
-    # the detection chain of one estimator is the unit timed by the per-call events
-    avg_call_s = float(np.mean(per_variant_ms)) / 1e3
-    achieved = flops / avg_call_s / 1e12
+    # dominant kernel: k_psca, one launch per detection (the events bracket
+    # it and its 1-block barrier-reset kernel)
+    flops = iters * iteration_flops(N, L)
+    avg_launch_s = float(launch_ms.mean()) / 1e3
+    achieved = flops / avg_launch_s / 1e12
     roofline = {
         "bound": "mfma",
         "achieved": round(achieved, 4),
         "peak": PEAK_FP32_MFMA_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6),
-        "traffic": None,
-        "kernel": "psca_detect_y chain (sample covariance + 100 iterations)",
+        "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+        "kernel": "k_psca (persistent detection, %d iterations)" % iters,
         "flops_per_launch": flops,
-        "avg_launch_ms": round(avg_call_s * 1e3, 4),
+        "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+        "algorithmic_bytes_per_launch": launch_bytes(N, L),
     }
 
     line = {

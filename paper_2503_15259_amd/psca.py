@@ -123,13 +123,20 @@ class Params:
                 raise ValueError("rho must hold `iters` contiguous float32 step sizes")
 
 
-def sample_cov(Y: torch.Tensor, ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
-    """SigmaHat = Y Y^H / M on the GPU (psca_sample_cov)."""
+def sample_cov(Y: torch.Tensor, ctx: Optional[Context] = None, stream=None,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """SigmaHat = Y Y^H / M on the GPU (psca_sample_cov).  `out`, if given,
+    is a column-major complex64 L x L tensor that receives it."""
     ctx = ctx or default_context(Y.device)
     _need(Y, torch.complex64, ctx.device, "Y")
     Y = colmajor(Y)
     L, M = Y.shape
-    out = torch.empty((L, L), dtype=torch.complex64, device=ctx.device).mT
+    if out is None:
+        out = torch.empty((L, L), dtype=torch.complex64, device=ctx.device).mT
+    else:
+        _need(out, torch.complex64, ctx.device, "out")
+        if out.shape != (L, L) or out.stride() != (1, L):
+            raise ValueError("out must be a column-major L x L complex64 tensor")
     N.check(ctx._lib.psca_sample_cov(ctx.handle, _ptr(Y), L, M, _ptr(out), _stream(ctx.device, stream)),
             "psca_sample_cov")
     return out
