@@ -412,3 +412,25 @@ def error_rate(scores: np.ndarray, truth: np.ndarray, theta: float) -> float:
     """Average error rate ||alpha_hat - alpha||_1 / (N I)."""
     det = threshold(scores, theta)
     return float(np.mean(np.abs(det.astype(np.int64) - np.asarray(truth).astype(np.int64))))
+
+
+# ---------------------------------------------------------------------------
+# Branch sensitivity of the MAP-UR prior (a property of eq. peps, used to
+# qualify parity checks at finite precision)
+# ---------------------------------------------------------------------------
+
+def branch_margin(prob: Problem, hist) -> np.ndarray:
+    """Per device, the smallest relative distance of its iterates x^(k) and
+    x^(k+1) over a recorded trajectory to a branch point of p^eps
+    (eps, g_l - eps, g_l).  The prior's gradient term has poles at eps from
+    below and at g_l - eps from above and jumps at g_l, so a trajectory that
+    passes within the working precision of one of them is not a continuous
+    function of the inputs there."""
+    pr = prob.prior
+    pts = np.array([pr.eps, pr.g_l - pr.eps, pr.g_l])
+    m = np.full(prob.N, np.inf)
+    for rec in hist:
+        for arr in (rec.x, rec.x_next):
+            d = np.min(np.abs(arr[:, None] - pts[None, :]) / pts[None, :], axis=1)
+            m = np.minimum(m, d)
+    return m

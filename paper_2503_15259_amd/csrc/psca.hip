@@ -252,9 +252,9 @@ struct CoopArgs {
 __host__ __device__ inline size_t lds_bytes(int Lp, int NT, int waves) {
   const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
   const bool sh_lds = Lp <= 64;
-  const size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256 + 32 +
-                    (size_t)waves * 64;
-  const size_t f4b = 3 * (size_t)NT + 2 * Lb * NT + (size_t)Lp;   // floats
+  const size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256 +
+                    Lb * 256 + 16;
+  const size_t f4b = 3 * (size_t)NT + 2 * Lb * NT;   // floats
   return f2 * sizeof(float2) + f4b * 4;
 }
 
@@ -290,144 +290,70 @@ __device__ __forceinline__ void cblock_mma_rm(const float2 *A, int lda, const fl
 }
 
 // ---------------------------------------------------------------------------
-// Factorisation state and the compile-time pivot schedule
+// Sigma^-1 by a blocked Hermitian sweep (Gauss-Jordan on an HPD matrix)
 // ---------------------------------------------------------------------------
-// Thread tid's slot s holds packed entry s * THREADS + tid of the Cholesky
-// triangle (column-packed) and of the diagonal 16x16 blocks of W = L^-1
-// (block by block, row-packed), so slot s of all threads covers one
-// contiguous range of entries whose columns / rows are known at compile time.
-// Every pivot step is generated for its k: it touches only the slots still
-// holding entries to update, with fixed LDS offsets and no bookkeeping.
-template <int LP, int THREADS>
-struct FactorGeom {
-  static constexpr int Tp = LP * (LP + 1) / 2;
-  static constexpr int Td = (LP / 16) * 136;
-  static constexpr int kSlots = (Tp + THREADS - 1) / THREADS;
-  static constexpr int kWSlots = (Td + THREADS - 1) / THREADS;
-  static constexpr int P = LP + 1;
-  static constexpr int col_of(int e) {   // column of column-packed entry e
-    int j = 0, st = 0;
-    while (st + (LP - j) <= e) { st += LP - j; ++j; }
-    return j;
-  }
-  static constexpr int c_lo(int s) { return col_of(s * THREADS); }
-  static constexpr int c_hi(int s) { return col_of(s * THREADS + THREADS - 1 < Tp ? s * THREADS + THREADS - 1 : Tp - 1); }
-  static constexpr int w_e0(int s) { return s * THREADS; }
-  static constexpr int w_e1(int s) { return s * THREADS + THREADS - 1 < Td ? s * THREADS + THREADS - 1 : Td - 1; }
-  // W slot s holds rows >= k of the diagonal block containing k
-  static constexpr bool w_act(int s, int k) {
-    return w_e0(s) <= (k / 16) * 136 + 135 && w_e1(s) >= (k / 16) * 136 + (k % 16) * (k % 16 + 1) / 2;
-  }
-};
-
-template <int LP, int THREADS>
-struct FactorState {
-  using Geo = FactorGeom<LP, THREADS>;
-  float2 av[Geo::kSlots], wx[Geo::kWSlots];
-  int c_i8[Geo::kSlots], c_j8[Geo::kSlots];   // LDS byte offsets row*8 / column*8
-  int w_i[Geo::kWSlots], w_c[Geo::kWSlots];   // (row, column) of the W entry
-  float2 *WS, *wbuf, *dummy;
-  float *rsv;
-  int tid;
-  float rs_prev;
-  bool failed;
-};
-
-template <int LP, int THREADS, int S>
-__device__ __forceinline__ void fstep_load(FactorState<LP, THREADS> &F, int k, const char *colk, float2 *cu,
-                                           float2 *cv) {
-  using Geo = FactorGeom<LP, THREADS>;
-  if (Geo::c_hi(S) > k) {   // uniform: slot S still holds trailing entries
-    cu[S] = *(const float2 *)(colk + F.c_i8[S]);
-    cv[S] = *(const float2 *)(colk + F.c_j8[S]);
-  }
+// Sweeping pivot k of a Hermitian matrix D with p = D[k][k] > 0 replaces D by
+//   D[i][j] - D[i][k] conj(D[j][k]) / p   (i, j != k),
+//   D[i][k] / p,  conj(D[j][k]) / p       (row and column k),
+//   -1 / p                                (the pivot);
+// sweeping every pivot of an HPD matrix leaves -D^-1, and every pivot is a
+// Schur-complement diagonal, so D is positive definite iff all pivots are > 0.
+// With e = column k with e_k replaced by -1, all four rules are one rank-1
+// update of D with row and column k cleared: D' - e e^H / p.
+//
+// leaf_sweep: one wavefront sweeps a 16x16 block (column-major at D, pitch
+// ld) in registers.  Lane l holds row i = l % 16 of columns q, q+4, q+8, q+12
+// (q = l / 16); column k travels through 16 words of LDS (`col`), written and
+// read by the same wavefront, so no workgroup barrier is needed.  Returns
+// false if some pivot is not positive and finite.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int LP, int THREADS, int S>
-__device__ __forceinline__ void fstep_wload(FactorState<LP, THREADS> &F, int k, const char *colp,
-                                            const float2 *wprev, float2 *wl, float2 *ww) {
-  using Geo = FactorGeom<LP, THREADS>;
-  if ((k & 15) != 0 && Geo::w_act(S, k)) {
-    wl[S] = *(const float2 *)(colp + 8 * F.w_i[S]);
-    ww[S] = wprev[F.w_c[S] & 15];
-  }
-}
-
-template <int LP, int THREADS, int S>
-__device__ __forceinline__ void fstep_wupd(FactorState<LP, THREADS> &F, int k, const float2 *wl,
-                                           const float2 *ww, float rs, float2 *wnew) {
-  using Geo = FactorGeom<LP, THREADS>;
-  if (Geo::w_act(S, k)) {
-    if ((k & 15) != 0) {   // X[i][c] -= L[i][k-1] W[k-1][c], rows i >= k, columns c < k of k's block
-      const float m = ((F.w_i[S] >> 4) == (k >> 4) && F.w_i[S] >= k && F.w_c[S] < k) ? F.rs_prev : 0.0f;
-      const float2 t = cmul(wl[S], ww[S]);
-      F.wx[S].x -= t.x * m;
-      F.wx[S].y -= t.y * m;
-    }
-    const bool fin = (F.w_i[S] == k);   // row k is final: W[k][c] = X[k][c] / L[k][k]
-    const float f = fin ? rs : 1.0f;
-    F.wx[S].x *= f;
-    F.wx[S].y *= f;
-    *(fin ? &wnew[F.w_c[S] & 15] : &F.dummy[F.tid]) = F.wx[S];
-  }
-}
-
-template <int LP, int THREADS, int S>
-__device__ __forceinline__ void fstep_upd(FactorState<LP, THREADS> &F, int k, const float2 *cu,
-                                          const float2 *cv, float invd) {
-  using Geo = FactorGeom<LP, THREADS>;
-  if (Geo::c_hi(S) > k) {   // A[i][j] -= A[i][k] conj(A[j][k]) / A[k][k]
-    const float2 t = cmul_conj(cu[S], cv[S]);
-    F.av[S].x -= t.x * invd;
-    F.av[S].y -= t.y * invd;
-    if (Geo::c_lo(S) <= k + 1) {   // publish column k+1
-      const bool pub = (F.c_j8[S] == 8 * (k + 1));
-      *(pub ? &F.WS[(k + 1) * Geo::P + (F.c_i8[S] >> 3)] : &F.dummy[F.tid]) = F.av[S];
+__device__ __forceinline__ bool leaf_sweep(float2 *D, int ld, float2 *col, int lane) {
+  const int i = lane & 15, q = lane >> 4;
+  float2 d[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) d[m] = D[(q + 4 * m) * ld + i];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (q == (k & 3)) col[i] = d[k >> 2];   // the owners of column k publish it
+    wave_lds_sync();
+    const float2 ci = col[i];
+    float2 cj[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) cj[m] = col[q + 4 * m];
+    const float p = col[k].x;
+    wave_lds_sync();
+    ok = ok && (p > 0.0f) && (p < INFINITY);
+    float rp = __builtin_amdgcn_rcpf(p);
+    rp = rp * (2.0f - p * rp);   // one Newton step
+    const float2 ei = (i == k) ? make_float2(-1.0f, 0.0f) : ci;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bool jk = (q + 4 * m == k);
+      const float2 ej = jk ? make_float2(-1.0f, 0.0f) : cj[m];
+      const float2 v = (i == k || jk) ? make_float2(0.0f, 0.0f) : d[m];
+      const float2 t = cmul_conj(ei, ej);
+      d[m] = make_float2(v.x - t.x * rp, v.y - t.y * rp);
     }
   }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) D[(q + 4 * m) * ld + i] = d[m];
+  return ok;
 }
 
-// One right-looking step k: read the raw pivot column k (published in LDS
-// after step k-1), update the trailing entries, publish column k+1; the
-// diagonal W block of k advances one step behind (row k-1 updates rows >= k,
-// then row k is scaled by 1 / L[k][k] and published).  The slot loops are
-// unrolled, so each slot's column range is a constant and the tests against
-// k are uniform scalar branches.
-template <int LP, int THREADS, int... Ss, int... Ws>
-__device__ __forceinline__ void fstep(FactorState<LP, THREADS> &F, int k, std::integer_sequence<int, Ss...>,
-                                      std::integer_sequence<int, Ws...>) {
-  using Geo = FactorGeom<LP, THREADS>;
-  constexpr int P = Geo::P;
-  __syncthreads();
-  const char *colk = (const char *)(F.WS + k * P);                           // raw pivot column k
-  const char *colp = (const char *)(F.WS + ((k & 15) ? k - 1 : k) * P);      // raw column k-1
-  const float2 *wprev = F.wbuf + ((k + 1) & 1) * 16;                          // row k-1 of the W block
-  float2 cu[Geo::kSlots], cv[Geo::kSlots], wl[Geo::kWSlots], ww[Geo::kWSlots];
-  (fstep_load<LP, THREADS, Ss>(F, k, colk, cu, cv), ...);
-  (fstep_wload<LP, THREADS, Ws>(F, k, colp, wprev, wl, ww), ...);
-  const float d = ((const float2 *)colk)[k].x;
-  if (!(d > 0.0f) || !(d < INFINITY)) {   // uniform: every thread reads the same pivot
-    F.failed = true;
-    return;
-  }
-  float rs = __builtin_amdgcn_rsqf(d);
-  rs = rs * (1.5f - 0.5f * d * rs * rs);   // one Newton step
-  const float invd = rs * rs;
-  if (F.tid == 0) F.rsv[k] = rs;
-  float2 *wnew = F.wbuf + (k & 1) * 16;
-  (fstep_wupd<LP, THREADS, Ws>(F, k, wl, ww, rs, wnew), ...);
-  (fstep_upd<LP, THREADS, Ss>(F, k, cu, cv, invd), ...);
-  F.rs_prev = rs;
-}
-
-template <int LP, int THREADS>
-__device__ __forceinline__ void factor_all(FactorState<LP, THREADS> &F) {
-  using Geo = FactorGeom<LP, THREADS>;
-#pragma unroll 1
-  for (int k = 0; k < LP; ++k) {
-    fstep(F, k, std::make_integer_sequence<int, Geo::kSlots>{}, std::make_integer_sequence<int, Geo::kWSlots>{});
-    if (F.failed) break;   // uniform
-  }
+// Operand loaders for a 16x16 block of the sweep.  Only lower blocks (I >= J)
+// are stored (column-major in WS, pitch P); block (I, J) of the Hermitian
+// matrix with I < J is the conjugate transpose of stored block (J, I).
+// a_elem returns X[r][c] of block (I, J) for any I, J.
+__device__ __forceinline__ float2 blk_elem(const float2 *WS, int P, int I, int J, int r, int c) {
+  if (I >= J) return WS[(16 * J + c) * P + 16 * I + r];
+  const float2 v = WS[(16 * I + r) * P + 16 * J + c];
+  return make_float2(v.x, -v.y);
 }
 
 template <int LPMAX, int THREADS>
@@ -436,29 +362,23 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
   constexpr int Lp = LPMAX, Lb = LPMAX / kBlk, NB = Lb * (Lb + 1) / 2;   // padded pilot length
   constexpr int P = Lp + 1;                                             // pitch of the L x L LDS matrix
   constexpr bool kShLds = LPMAX <= 64;                                  // SigmaHat resident in LDS
-  constexpr int Tp = Lp * (Lp + 1) / 2;                                 // lower-triangle entries
-  constexpr int kSlots = (Tp + THREADS - 1) / THREADS;                  // Cholesky entries per thread
-  constexpr int Td = Lb * 136;                                          // entries of the diagonal W blocks
-  constexpr int kWSlots = (Td + THREADS - 1) / THREADS;
   constexpr int kRowBlocksPerWave = (Lb + kWaves - 1) / kWaves;
   constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
-  static_assert(kSlots <= 20, "Duff dispatch covers 20 slots");
   extern __shared__ float4 smem_raw[];
-  __shared__ int s_ok;
+  __shared__ int s_ok, s_pd;
   const int NT = A.NT, PT = A.NT + 1;
   float2 *St = (float2 *)smem_raw;          // [Lp][PT]  S tile, row i at i * PT
   float2 *Bt = St + Lp * PT;                // [Lp][PT]  B tile (also reduction scratch)
   float2 *WS = Bt + Lp * PT;                // [Lp][P]   column-major: Cholesky columns, W, Sigma^-1
   float2 *ShL = WS + Lp * P;                // [Lp][P]   SigmaHat, column-major (kShLds)
   float2 *scr = ShL + (kShLds ? Lp * P : 0);// [kWaves][256] per-wave 16x16 scratch
-  float2 *wbuf = scr + kWaves * 256;        // [2][16]   published rows of a diagonal W block
-  float2 *dummy = wbuf + 32;                // [THREADS] write sink of the factorisation step
-  float *xs = (float *)(dummy + THREADS);   // [NT] iterate of the tile
+  float2 *TP = scr + kWaves * 256;          // [Lb][256] panel blocks of the current sweep step
+  float2 *colb = TP + Lb * 256;             // [16]      column exchange of the leaf sweep
+  float *xs = (float *)(colb + 16);         // [NT] iterate of the tile
   float *gs = xs + NT;                      // [NT] pathloss
   float *ls = gs + NT;                      // [NT] log(p / (1 - p))
   float *red_q = ls + NT;                   // [Lb][NT]
   float *red_r = red_q + Lb * NT;           // [Lb][NT]
-  float *rsv = red_r + Lb * NT;             // [Lp] 1 / L[k][k]
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -491,36 +411,6 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
       const int k = e / Lp, i = e - k * Lp;
       ShL[k * P + i] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
     }
-  }
-
-  // ---- ownership of the factorisation's entries ---------------------------
-  // Cholesky: lower-triangle entries in column-packed order.  W: entries of
-  // the 16x16 diagonal blocks of L^-1, block by block, row-packed inside a
-  // block.  Thread tid's slot s holds entry s * THREADS + tid; threads past
-  // the last entry alias the last entry (Lp-1, Lp-1) and repeat its
-  // arithmetic exactly.
-  FactorState<Lp, THREADS> F;
-  F.WS = WS;
-  F.wbuf = wbuf;
-  F.dummy = dummy;
-  F.rsv = rsv;
-  F.tid = tid;
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const int e = min(s * THREADS + tid, Tp - 1);
-    int j = 0, st = 0;
-    while (st + (Lp - j) <= e) { st += Lp - j; ++j; }
-    F.c_j8[s] = j * 8;
-    F.c_i8[s] = (j + (e - st)) * 8;
-  }
-#pragma unroll
-  for (int s = 0; s < kWSlots; ++s) {
-    const int e = min(s * THREADS + tid, Td - 1);
-    const int I = e / 136, r = e - I * 136;
-    int ii = 0;
-    while ((ii + 1) * (ii + 2) / 2 <= r) ++ii;
-    F.w_i[s] = 16 * I + ii;
-    F.w_c[s] = 16 * I + (r - ii * (ii + 1) / 2);
   }
 
   double rho_d = A.rho0;
@@ -624,125 +514,145 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
     PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, gen, &s_ok)) { aborted = true; break; }
 
-    // ===== C1. Cholesky Sigma = L L^H, with the diagonal blocks of W = L^-1 ==
-    // Right-looking: at step k every thread reads the raw pivot column k from
-    // WS (published there by the owners of its entries after step k-1) and
-    // updates its trailing entries; the owners of column k+1 publish it into
-    // WS.  The diagonal 16x16 blocks of W advance one step behind inside their
-    // block: row k-1 of W_II updates rows >= k, then row k is scaled by
-    // 1 / L[k][k] and published.  One workgroup barrier per step.
+    // ===== C1-C3. Sigma^-1 by the blocked Hermitian sweep ====================
+    // Every workgroup inverts the same Sigma (no further grid barrier).  For
+    // each diagonal block J: wavefront 0 sweeps block (J, J) in registers,
+    // giving Q = -(A_JJ)^-1, while the other wavefronts write back the panel of
+    // step J-1; then, on MFMA, every lower block (I, K) with I, K != J takes
+    // A_IK += A_IJ Q A_JK and the panel blocks take A_IJ Q, staged in TP
+    // because the updates still read the old panel.  After the last block WS
+    // holds -Sigma^-1 in its lower blocks.
     PSCA_MARK(it, 4);
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) F.av[s] = A.sigma[bp_offset(F.c_i8[s] >> 3, F.c_j8[s] >> 3)];
-#pragma unroll
-    for (int s = 0; s < kWSlots; ++s) F.wx[s] = make_float2(F.w_i[s] == F.w_c[s] ? 1.0f : 0.0f, 0.0f);
-    for (int e = tid; e < Lp * P; e += THREADS) WS[e] = make_float2(0.f, 0.f);
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s)          // publish column 0
-      if (F.c_j8[s] == 0) WS[F.c_i8[s] >> 3] = F.av[s];
-    F.rs_prev = 0.0f;
-    F.failed = false;
-    factor_all(F);
-    failed = F.failed;
-    PSCA_MARK(it, 5);
-    if (failed) break;   // uniform: every workgroup factors the same Sigma
-    __syncthreads();
-
-    // ===== C2. W = L^-1 in WS: diagonal blocks, scaled L below them =========
-#pragma unroll
-    for (int s = 0; s < kWSlots; ++s)         // slots past the last entry hold no entry
-      if (s * THREADS < Td) WS[F.w_c[s] * P + F.w_i[s]] = F.wx[s];
-    for (int e = tid; e < Lb * 256; e += THREADS) {   // zero the upper parts of the diagonal blocks
-      const int I = e >> 8, ii = (e >> 4) & 15, cc = e & 15;
-      if (ii < cc) WS[(16 * I + cc) * P + 16 * I + ii] = make_float2(0.f, 0.f);
-    }
-    for (int e = tid; e < Lp * Lp; e += THREADS) {    // L[i][c] = raw * rs_c below the diagonal blocks
-      const int c = e / Lp, i = e - c * Lp;
-      if ((i >> 4) > (c >> 4)) {
-        const float2 v = WS[c * P + i];
-        const float r = rsv[c];
-        WS[c * P + i] = make_float2(v.x * r, v.y * r);
-      }
+    for (int e = tid; e < E; e += THREADS) {
+      const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+      int I, J;
+      blk_coords(b, I, J);
+      WS[(16 * J + jj) * P + 16 * I + ii] = A.sigma[e];
     }
     __syncthreads();
-    // Off-diagonal blocks, right to left: W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ
-    for (int J = Lb - 2; J >= 0; --J) {
-      f4 rr = {0.f, 0.f, 0.f, 0.f}, ri = {0.f, 0.f, 0.f, 0.f};
-      const int I = J + 1 + wave;
-      if (I < Lb) {
-        f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
-        for (int K = J + 1; K <= I; ++K)
-          cblock_mma(WS + (16 * K) * P + 16 * I, WS + (16 * J) * P + 16 * K, P, l16, lq, tr, ti);
-        float2 *T = scr + wave * 256;          // column-major, pitch 16
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float2 ta[4], wb[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          ta[ks] = T[(4 * ks + lq) * 16 + l16];
-          wb[ks] = WS[(16 * J + l16) * P + 16 * J + 4 * ks + lq];
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(ta[ks], wb[ks], rr, ri);
-      }
-      __syncthreads();
-      if (I < Lb) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) WS[(16 * J + l16) * P + 16 * I + 4 * lq + v] = make_float2(-rr[v], -ri[v]);
-      }
-      __syncthreads();
-    }
-
-    // ===== C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS ======
-    PSCA_MARK(it, 6);
     {
-      f4 sir[kBlocksPerWave], sii[kBlocksPerWave];
+      constexpr int nt = (Lb - 1) * Lb / 2, np = Lb - 1;
+      for (int J = 0; J < Lb; ++J) {
+        if (wave == 0) {
+          const bool ok = leaf_sweep(WS + 16 * J * P + 16 * J, P, colb, lane);
+          if (lane == 0) s_pd = ok ? 1 : 0;
+        } else if (J > 0) {
+          const int Jp = J - 1;
+          for (int e = tid - 64; e < np * 256; e += THREADS - 64) {
+            const int t = e >> 8, c = (e >> 4) & 15, r = e & 15;
+            const int I = t + (t >= Jp);
+            const float2 v = TP[I * 256 + c * 16 + r];
+            if (I > Jp) WS[(16 * Jp + c) * P + 16 * I + r] = v;
+            else WS[(16 * I + c) * P + 16 * Jp + r] = v;
+          }
+        }
+        __syncthreads();
+        if (!s_pd) {   // uniform: every workgroup sweeps the same Sigma
+          failed = true;
+          break;
+        }
+        const float2 *Q = WS + 16 * J * P + 16 * J;
+        for (int t = 0; t < nt + np; ++t) {
+          int owner;
+          if (t < nt) owner = t % kWaves;
+          else owner = (nt < kWaves) ? kWaves - 1 - (t - nt) % (kWaves - nt) : t % kWaves;
+          if (owner != wave) continue;
+          if (t < nt) {
+            // lower block (I, K) of the Sigma without block row/column J
+            int ii = 0;
+            while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+            const int kk = t - ii * (ii + 1) / 2;
+            const int I = ii + (ii >= J), K = kk + (kk >= J);
+            f4 vr = {0.f, 0.f, 0.f, 0.f}, vi = {0.f, 0.f, 0.f, 0.f};
+            {
+              float2 a4[4], b4[4];
 #pragma unroll
-      for (int q = 0; q < kBlocksPerWave; ++q) {
-        sir[q] = (f4){0.f, 0.f, 0.f, 0.f};
-        sii[q] = (f4){0.f, 0.f, 0.f, 0.f};
-        const int b = wave + kWaves * q;
-        if (b < NB) {
-          int I, J;
-          blk_coords(b, I, J);
-          for (int K = I; K < Lb; ++K) {       // A[i][k] = conj(W[k][i]), B[k][j] = W[k][j]
+              for (int ks = 0; ks < 4; ++ks) {   // V = Q A_JK
+                const int k = 4 * ks + lq;
+                a4[ks] = Q[k * P + l16];
+                b4[ks] = blk_elem(WS, P, J, K, k, l16);
+              }
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], vr, vi);
+            }
+            float2 *T = scr + wave * 256;   // V, column-major, pitch 16
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(vr[v], vi[v]);
+            wave_lds_sync();
+            f4 cr, ci;
+            float2 *dst = WS + (16 * K + l16) * P + 16 * I + 4 * lq;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              cr[v] = dst[v].x;
+              ci[v] = dst[v].y;
+            }
+            {
+              float2 a4[4], b4[4];
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) {   // A_IK += A_IJ V
+                const int k = 4 * ks + lq;
+                a4[ks] = blk_elem(WS, P, I, J, l16, k);
+                b4[ks] = T[l16 * 16 + k];
+              }
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[v] = make_float2(cr[v], ci[v]);
+            wave_lds_sync();   // T is reused by this wavefront's next task
+          } else {
+            // panel: lower storage of pair {I, J} becomes A_IJ P = -A_IJ Q (I > J)
+            // or P A_JI = -Q A_JI (I < J)
+            const int tp = t - nt, I = tp + (tp >= J);
+            f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
             float2 a4[4], b4[4];
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-              const int k = 16 * K + 4 * ks + lq;
-              const float2 wi = WS[(16 * I + l16) * P + k];
-              a4[ks] = make_float2(wi.x, -wi.y);
-              b4[ks] = WS[(16 * J + l16) * P + k];
+              const int k = 4 * ks + lq;
+              if (I > J) {
+                a4[ks] = WS[(16 * J + k) * P + 16 * I + l16];
+                b4[ks] = Q[l16 * P + k];
+              } else {
+                a4[ks] = Q[k * P + l16];
+                b4[ks] = WS[(16 * I + l16) * P + 16 * J + k];
+              }
             }
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], sir[q], sii[q]);
+            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) TP[I * 256 + l16 * 16 + 4 * lq + v] = make_float2(-cr[v], -ci[v]);
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < kBlocksPerWave; ++q) {
-        const int b = wave + kWaves * q;
-        if (b < NB) {
-          int I, J;
-          blk_coords(b, I, J);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * lq + v, j = 16 * J + l16;
-            if (i >= j) {
-              const float im = (i == j) ? 0.0f : sii[q][v];
-              WS[j * P + i] = make_float2(sir[q][v], im);
-              WS[i * P + j] = make_float2(sir[q][v], -im);
-            }
-          }
-        }
-      }
-      __syncthreads();
     }
+    PSCA_MARK(it, 5);
+    if (failed) break;
+    {   // write back the last panel
+      const int Jp = Lb - 1;
+      for (int e = tid; e < (Lb - 1) * 256; e += THREADS) {
+        const int t = e >> 8, c = (e >> 4) & 15, r = e & 15;
+        const int I = t + (t >= Jp);
+        const float2 v = TP[I * 256 + c * 16 + r];
+        if (I > Jp) WS[(16 * Jp + c) * P + 16 * I + r] = v;
+        else WS[(16 * I + c) * P + 16 * Jp + r] = v;
+      }
+    }
+    __syncthreads();
+    PSCA_MARK(it, 6);
+    for (int e = tid; e < E; e += THREADS) {   // Sigma^-1, full and exactly Hermitian
+      const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+      int I, J;
+      blk_coords(b, I, J);
+      const int i = 16 * I + ii, j = 16 * J + jj;
+      if (i >= j) {
+        const float2 v = WS[j * P + i];
+        const float im = (i == j) ? 0.0f : -v.y;
+        WS[j * P + i] = make_float2(-v.x, im);
+        WS[i * P + j] = make_float2(-v.x, -im);
+      }
+    }
+    __syncthreads();
 
     // ===== C4. B = Sigma^-1 S_g and q;  D = SigmaHat B and r =================
     PSCA_MARK(it, 7);
@@ -1003,10 +913,10 @@ struct KernelChoice {
 
 KernelChoice pick_kernel(int Lp) {
   switch (Lp) {
-    case 16: return {(const void *)k_psca<16, 256>, 256, 16};
-    case 32: return {(const void *)k_psca<32, 256>, 256, 32};
-    case 48: return {(const void *)k_psca<48, 256>, 256, 48};
-    case 64: return {(const void *)k_psca<64, 256>, 256, 64};
+    case 16: return {(const void *)k_psca<16, 512>, 512, 16};
+    case 32: return {(const void *)k_psca<32, 512>, 512, 32};
+    case 48: return {(const void *)k_psca<48, 512>, 512, 48};
+    case 64: return {(const void *)k_psca<64, 512>, 512, 64};
     case 80: return {(const void *)k_psca<80, 512>, 512, 80};
     default: return {(const void *)k_psca<96, 512>, 512, 96};
   }

@@ -85,6 +85,22 @@ class Instance:
     def gamma(self) -> np.ndarray:
         return self.alpha * self.g
 
+    def fp32_inputs(self) -> "Instance":
+        """The same instance with every input of the detector rounded to
+        single precision (and held in FP64 again): the values an FP32
+        device path actually receives.  The true activity is unchanged."""
+        def r32(a):
+            return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+        def c32(a):
+            return np.asarray(a, dtype=np.complex128).astype(np.complex64).astype(np.complex128)
+
+        return Instance(S=c32(self.S), Y=c32(self.Y), g=r32(self.g), alpha=self.alpha.copy(), d=self.d.copy(),
+                        p=float(np.float32(self.p)), sigma2=float(np.float32(self.sigma2)),
+                        d_lo=float(np.float32(self.d_lo)), d_hi=float(np.float32(self.d_hi)),
+                        pl_c0=float(np.float32(self.pl_c0)), pl_beta=float(np.float32(self.pl_beta)),
+                        seed=self.seed)
+
 
 def _cn(rng: np.random.Generator, shape) -> np.ndarray:
     """i.i.d. CN(0, 1): independent N(0, 1/2) real and imaginary parts."""

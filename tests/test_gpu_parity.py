@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [O.ML_K, O.MAP_K, O.ML_UD, O.MAP_UR]
-EPS = 0.01
+EPS = float(np.float32(0.01))   # the value the FP32 parameter block carries
 
 
 @pytest.fixture(scope="module")
@@ -60,7 +60,7 @@ def label(inst, variant, iters):
 
 def test_sample_covariance(P):
     for (N, L, M) in [(10, 1, 1), (30, 13, 7), (100, 64, 128), (50, 96, 256)]:
-        inst = I.make_instance(7, L, N, L, M, 0.2)
+        inst = I.make_instance(7, L, N, L, M, 0.2).fp32_inputs()
         print(f"sample_cov L={L} M={M}", flush=True)
         got = P.sample_cov(c64(inst.Y))
         torch.cuda.synchronize()
@@ -72,7 +72,7 @@ def test_sample_covariance(P):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_first_iteration_from_zero(P, variant):
-    inst = I.workload_instance("small", 1)
+    inst = I.workload_instance("small", 1).fp32_inputs()
     prob = O.problem_from_instance(inst, variant, eps=EPS)
     rec = O.psca_iteration(prob, np.zeros(inst.N), 0.5)
     Sh = P.sample_cov(c64(inst.Y))
@@ -87,7 +87,7 @@ def test_first_iteration_from_zero(P, variant):
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_iteration_from_a_mid_trajectory_point(P, variant):
     """Factorisation of a realistic Sigma (iterate 15 of the oracle)."""
-    inst = I.workload_instance("single", 2)
+    inst = I.workload_instance("single", 2).fp32_inputs()
     prob = O.problem_from_instance(inst, variant, eps=EPS)
     x15 = O.psca(prob, 15)
     rho = float(O.step_sizes(16)[15])
@@ -103,7 +103,7 @@ def test_iteration_from_a_mid_trajectory_point(P, variant):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_detect_small_workload(P, variant):
-    inst = I.workload_instance("small", 0)
+    inst = I.workload_instance("small", 0).fp32_inputs()
     iters = 100
     ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
     got = run_gpu(P, inst, variant, iters)
@@ -114,7 +114,7 @@ def test_detect_small_workload(P, variant):
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_detect_single_instance_workload(P, variant):
     """Full-size single-instance workload: N = 1000, L = 64, M = 128, 100 iterations."""
-    inst = I.workload_instance("single", 0)
+    inst = I.workload_instance("single", 0).fp32_inputs()
     iters = 100
     ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
     print(label(inst, variant, iters), flush=True)
@@ -126,7 +126,7 @@ def test_detect_single_instance_workload(P, variant):
 @pytest.mark.parametrize("N,L,M", [(1, 1, 4), (1, 8, 16), (65, 13, 9), (129, 3, 40), (200, 96, 64),
                                    (300, 96, 256), (64, 64, 64), (1000, 33, 128)])
 def test_detect_ragged_and_edge_shapes(P, N, L, M):
-    inst = I.make_instance(5, N * 1000 + L, N, L, M, 0.2)
+    inst = I.make_instance(5, N * 1000 + L, N, L, M, 0.2).fp32_inputs()
     for variant in (O.ML_K, O.ML_UD):
         iters = 30
         ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
@@ -136,13 +136,13 @@ def test_detect_ragged_and_edge_shapes(P, N, L, M):
 
 
 def test_zero_iterations_returns_zero(P):
-    inst = I.make_instance(5, 1, 70, 8, 16, 0.2)
+    inst = I.make_instance(5, 1, 70, 8, 16, 0.2).fp32_inputs()
     got = run_gpu(P, inst, O.ML_UD, 0)
     assert np.array_equal(got, np.zeros(inst.N, np.float32))
 
 
 def test_explicit_step_sizes_match_schedule(P):
-    inst = I.workload_instance("small", 2)
+    inst = I.workload_instance("small", 2).fp32_inputs()
     iters = 12
     rho = f32(O.step_sizes(iters))
     prm = params_for(P, inst, O.ML_K, iters)
@@ -165,7 +165,7 @@ def test_threshold_bit_exact(P):
 def test_not_positive_definite_is_reported_and_iterate_held(P):
     """A negative iterate makes Sigma indefinite; the device reports it and
     leaves x unchanged (forced from the host: no fault, every kernel exits)."""
-    inst = I.make_instance(5, 2, 80, 8, 16, 0.2)
+    inst = I.make_instance(5, 2, 80, 8, 16, 0.2).fp32_inputs()
     Sh = P.sample_cov(c64(inst.Y))
     x_in = f32(np.full(inst.N, -10.0))
     status = torch.zeros(1, dtype=torch.int32, device=dev())
@@ -181,7 +181,7 @@ def test_not_positive_definite_is_reported_and_iterate_held(P):
 
 
 def test_host_validation_errors(P):
-    inst = I.make_instance(5, 3, 20, 8, 16, 0.2)
+    inst = I.make_instance(5, 3, 20, 8, 16, 0.2).fp32_inputs()
     Y, S = c64(inst.Y), c64(inst.S)
     with pytest.raises(P.PscaError) as e:
         P.detect_y(Y, S, P.Params(variant=O.ML_K, iters=5, M=16))          # g missing
@@ -192,7 +192,7 @@ def test_host_validation_errors(P):
         P.detect_y(Y, S, P.Params(variant=O.ML_UD, iters=5, M=16, rho0=1.5))
     with pytest.raises(P.PscaError):
         P.detect_y(Y, S, P.Params(variant=O.MAP_UR, iters=5, M=16, eps=100.0))   # 2 eps >= g_l
-    big = I.make_instance(5, 4, 20, 97, 8, 0.2)
+    big = I.make_instance(5, 4, 20, 97, 8, 0.2).fp32_inputs()
     with pytest.raises(P.PscaError) as e:
         P.detect_y(c64(big.Y), c64(big.S), P.Params(variant=O.ML_UD, iters=5, M=8))
     assert e.value.code == -5

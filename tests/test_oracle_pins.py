@@ -449,3 +449,27 @@ def test_equal_error_rate_small_example():
     eer, theta, _, _ = O.equal_error_rate(np.array([0.1, 0.2, 0.7, 0.9]), truth)
     assert eer == 0.0 and theta == 0.7
     assert O.error_rate(scores, truth, 0.4) == 0.5
+
+
+def test_map_ur_trajectories_can_pass_through_a_pole_of_the_prior():
+    """Eq. peps has poles of p^eps'/p^eps at eps (from below) and g_l - eps
+    (from above).  On the N=1000, L=64 instance 2, rounding only the inputs
+    to single precision moves one device's final gamma by more than half,
+    and that device's trajectory passes within 1e-4 (relative) of a branch
+    point: no FP32 path can match such an instance element by element.
+    Instance 0, the full-size MAP-UR parity case, moves by less than 1e-5."""
+    from paper_2503_15259_amd import instances as I
+
+    def rel_change(inst):
+        prob = O.problem_from_instance(inst, O.MAP_UR, eps=0.01)
+        x, hist = O.psca(prob, 100, record=True)
+        x32 = O.psca(O.problem_from_instance(inst.fp32_inputs(), O.MAP_UR, eps=0.01), 100)
+        big = np.abs(x) >= 1e-3 * np.abs(x).max()
+        rel = np.where(big, np.abs(x32 - x) / np.maximum(np.abs(x), 1e-300), 0.0)
+        return rel, O.branch_margin(prob, hist)
+
+    rel, m = rel_change(I.workload_instance("single", 2))
+    n = int(np.argmax(rel))
+    assert rel[n] > 0.5 and m[n] < 1e-4
+    rel0, _ = rel_change(I.workload_instance("single", 0))
+    assert rel0.max() < 1e-5
