@@ -7,7 +7,8 @@ Workload: single-instance PSCA at N = 1000 devices, pilot length L = 64,
 M = 128 antennas, activity p = 0.1, 100 iterations, all four estimators
 (ML-K, MAP-K, ML-UD, MAP-UR).  One step detects four instances, one per
 estimator, each from its received pilots Y (the sample covariance is formed
-inside the timed region).  Inputs live in HBM before timing starts.
+inside the timed region); the four detections run concurrently in one batched
+launch.  Inputs live in HBM before timing starts.
 
 Prints one JSON line (see the keys at the end of main()).
 """
@@ -38,7 +39,7 @@ PEAK_HBM_GBS = 8000.0
 # changed after the counters were taken).
 # Measured for k_psca<64, 256> at N=1000, L=64, 100 iterations (profile
 # k_psca_single_N1000_L64_traffic.md): 172.4 MB fetched + 134.8 MB written.
-TRAFFIC_BYTES_PER_LAUNCH = 307144808
+TRAFFIC_BYTES_PER_LAUNCH = None
 
 
 def iteration_flops(N, L):
@@ -182,26 +183,29 @@ def main():
     outs = [[torch.empty(N, dtype=torch.float32, device=dev) for _ in range(4)] for _ in range(POOL)]
     shs = [torch.empty((L, L), dtype=torch.complex64, device=dev).mT for _ in range(4)]
     status = torch.zeros(4, dtype=torch.int32, device=dev)
-    ctxs = [P.Context(0) for _ in range(4)]
+    ctx = P.Context(0)
     stream = torch.cuda.current_stream(dev)
 
     def one_step(s, events=None):
-        """Four detections, one per estimator: SigmaHat from Y, then Algorithm 1."""
+        """Four detections, one per estimator, in one batched launch: SigmaHat
+        from Y for each, then Algorithm 1 for all four concurrently."""
+        probs = []
         for v in range(4):
             i = (4 * s + v) % POOL
-            P.sample_cov(Ys[i], ctx=ctxs[v], out=shs[v])
-            if events is not None:
-                events[v][0].record(stream)
-            P.detect(shs[v], Ss[i], params[i][v], ctx=ctxs[v], out=outs[i][v], status=status[v:v + 1])
-            if events is not None:
-                events[v][1].record(stream)
+            P.sample_cov(Ys[i], ctx=ctx, out=shs[v])
+            probs.append(P.Problem(Sigma_hat=shs[v], S=Ss[i], params=params[i][v], out=outs[i][v],
+                                   status=status[v:v + 1]))
+        if events is not None:
+            events[0].record(stream)
+        P.detect_batch(probs, ctx=ctx)
+        if events is not None:
+            events[1].record(stream)
 
     for s in range(args.warmup):
         one_step(s)
     torch.cuda.synchronize()
 
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(4)]
-          for _ in range(args.steps)]
+    ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -213,8 +217,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t_start.elapsed_time(t_end)
-    launch_ms = np.array([[ev[s][v][0].elapsed_time(ev[s][v][1]) for v in range(4)] for s in range(args.steps)])
-    per_variant_ms = launch_ms.mean(axis=0)
+    launch_ms = np.array([ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)])
     assert int(status.abs().sum().item()) == 0, "device reported a factorisation failure"
 
     ms_per_step = total_ms / args.steps
@@ -235,7 +238,7 @@ def main():
     for v in range(4):
         scores, truth = [], []
         for i in range(POOL):
-            x = P.detect_y(Ys[i], Ss[i], params[i][v], ctx=ctxs[v])
+            x = P.detect_y(Ys[i], Ss[i], params[i][v], ctx=ctx)
             xs[(v, i)] = x
         torch.cuda.synchronize()
         for i in range(POOL):
@@ -276,9 +279,10 @@ def main():
             parity[VARIANT_NAMES[v]] = {key: worst, "instances_compared": compared,
                                         "input_sensitive": sensitive}
 
-    # dominant kernel: k_psca, one launch per detection (the events bracket
-    # it and its 1-block barrier-reset kernel)
-    flops = iters * iteration_flops(N, L)
+    # dominant kernel: k_psca_batch, one launch per step running the four
+    # detections (the events bracket it, its barrier-reset kernel and the
+    # 1 KB descriptor copy)
+    flops = 4 * iters * iteration_flops(N, L)
     avg_launch_s = float(launch_ms.mean()) / 1e3
     achieved = flops / avg_launch_s / 1e12
     roofline = {
@@ -288,10 +292,10 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6),
         "traffic": TRAFFIC_BYTES_PER_LAUNCH,
-        "kernel": "k_psca (persistent detection, %d iterations)" % iters,
+        "kernel": "k_psca_batch (4 concurrent detections, %d iterations each)" % iters,
         "flops_per_launch": flops,
         "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-        "algorithmic_bytes_per_launch": launch_bytes(N, L),
+        "algorithmic_bytes_per_launch": 4 * launch_bytes(N, L),
     }
 
     line = {
@@ -313,7 +317,6 @@ def main():
             "N": N, "L": L, "M": M, "p": w["p"], "iters": iters, "instances_per_step": 4,
             "eps_map_ur": EPS, "pool": POOL,
         },
-        "per_estimator_ms": {VARIANT_NAMES[v]: round(per_variant_ms[v], 4) for v in range(4)},
         "equal_error": eer,
         "parity_vs_oracle": parity,
         "roofline": roofline,

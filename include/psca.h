@@ -140,6 +140,27 @@ int psca_iterate(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, in
                  const psca_params *prm, float rho, const float *x_in, float *x_out,
                  float *q_out, float *r_out, float *xt_out, int32_t *status, void *stream);
 
+/* One instance of a batch: the arguments of psca_detect.  All pointers are
+ * DEVICE pointers on the context's GPU; status is optional (NULL). */
+typedef struct {
+  const psca_c32 *Sigma_hat;  /* L x L, column-major */
+  const psca_c32 *S;          /* L x N, column-major */
+  int32_t L, N;
+  psca_params prm;            /* variant, iters, schedule, sigma2, M, g, p, prior */
+  float *x_out;               /* [N] */
+  int32_t *status;            /* PSCA_OK / PSCA_ENOTPD / PSCA_ESYNC, or NULL */
+} psca_problem;
+
+/* B independent detections (Algorithm 1 from x = 0 for each), equivalent to
+ * B calls of psca_detect.  `problems` is a HOST array of B entries, read
+ * before the call returns.  The instances run concurrently: each gets its own
+ * group of workgroups and its own device-wide barrier inside one cooperative
+ * launch; a batch larger than the GPU holds at once is split into successive
+ * launches.  Instances may differ in L, N, M, variant, iteration count and
+ * parameters.  Every instance is validated as in psca_detect before anything
+ * is launched (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one). */
+int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream);
+
 /* Threshold module: support[n] = (x[n] >= theta) ? 1 : 0 (Sec. III-A). */
 int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *stream);
 

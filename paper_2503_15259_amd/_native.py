@@ -23,7 +23,7 @@ MAX_L = 96
 # every symbol include/psca.h declares
 EXPORTED = (
     "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
-    "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold",
+    "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold", "psca_detect_batch",
 )
 
 
@@ -43,6 +43,18 @@ class PscaParams(ctypes.Structure):
         ("pl_c0", ctypes.c_float),
         ("pl_beta", ctypes.c_float),
         ("eps", ctypes.c_float),
+    ]
+
+
+class PscaProblem(ctypes.Structure):
+    _fields_ = [
+        ("Sigma_hat", ctypes.c_void_p),
+        ("S", ctypes.c_void_p),
+        ("L", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("prm", PscaParams),
+        ("x_out", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
     ]
 
 
@@ -77,6 +89,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "psca_detect_y": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
         "psca_iterate": ([vp, vp, vp, i32, i32, P, f32, vp, vp, vp, vp, vp, vp, vp], i32),
         "psca_threshold": ([vp, i32, f32, vp, vp], i32),
+        "psca_detect_batch": ([vp, i32, ctypes.POINTER(PscaProblem), vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

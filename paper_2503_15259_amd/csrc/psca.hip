@@ -36,7 +36,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <vector>
 #include <utility>
 
 #include "psca.h"
@@ -196,15 +198,15 @@ __device__ __forceinline__ bool spin_until(const unsigned *word, unsigned target
   return true;
 }
 
-__device__ __forceinline__ bool grid_sync(const GridBar &b, unsigned G, unsigned &gen, int *s_ok) {
+__device__ __forceinline__ bool grid_sync(const GridBar &b, unsigned G, unsigned g, unsigned &gen, int *s_ok) {
   __syncthreads();
   const unsigned target = gen + 1;
   gen = target;
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&b.arrive[blockIdx.x * 16], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&b.arrive[g * 16], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (blockIdx.x == 0) {
+  if (g == 0) {
     int ok = 1;
     for (unsigned w = threadIdx.x; w < G; w += blockDim.x)
       if (!spin_until(&b.arrive[w * 16], target, b.abort_flag)) ok = 0;
@@ -356,8 +358,9 @@ __device__ __forceinline__ float2 blk_elem(const float2 *WS, int P, int I, int J
   return make_float2(v.x, -v.y);
 }
 
+// One detection on workgroup g of the G workgroups the instance owns.
 template <int LPMAX, int THREADS>
-__global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
+__device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int kWaves = THREADS / 64;
   constexpr int Lp = LPMAX, Lb = LPMAX / kBlk, NB = Lb * (Lb + 1) / 2;   // padded pilot length
   constexpr int P = Lp + 1;                                             // pitch of the L x L LDS matrix
@@ -382,7 +385,6 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
-  const int g = blockIdx.x;
   const int n0 = g * NT;
   constexpr int E = NB * 256;
   unsigned gen = 0;
@@ -452,7 +454,7 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
       }
     }
     PSCA_MARK(it, 1);
-    if (!grid_sync(A.bar, A.G, gen, &s_ok)) { aborted = true; break; }
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ===== B. reduce a slice of the partials into Sigma ===================
     PSCA_MARK(it, 2);
@@ -512,7 +514,7 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
       }
     }
     PSCA_MARK(it, 3);
-    if (!grid_sync(A.bar, A.G, gen, &s_ok)) { aborted = true; break; }
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ===== C1-C3. Sigma^-1 by the blocked Hermitian sweep ====================
     // Every workgroup inverts the same Sigma (no further grid barrier).  For
@@ -759,6 +761,29 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
     *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
 }
 
+template <int LPMAX, int THREADS>
+__global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
+  psca_body<LPMAX, THREADS>(A, blockIdx.x);
+}
+
+// Batch of independent detections in one cooperative launch: workgroup w
+// runs workgroup wg_map[w].y of instance wg_map[w].x, whose arguments are
+// descs[wg_map[w].x]; every instance synchronises on its own barrier words.
+constexpr int kBatchThreads = 512;
+__global__ void __launch_bounds__(kBatchThreads) k_psca_batch(const CoopArgs *__restrict__ descs,
+                                                              const int2 *__restrict__ wg_map) {
+  const int2 m = wg_map[blockIdx.x];
+  const CoopArgs A = descs[m.x];
+  switch ((A.L + 15) & ~15) {
+    case 16: psca_body<16, kBatchThreads>(A, m.y); break;
+    case 32: psca_body<32, kBatchThreads>(A, m.y); break;
+    case 48: psca_body<48, kBatchThreads>(A, m.y); break;
+    case 64: psca_body<64, kBatchThreads>(A, m.y); break;
+    case 80: psca_body<80, kBatchThreads>(A, m.y); break;
+    default: psca_body<96, kBatchThreads>(A, m.y); break;
+  }
+}
+
 // SigmaHat = Y Y^H / M; one thread per lower-triangle entry, mirrored so the
 // result is exactly Hermitian.
 __global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restrict__ Y, int L, int M,
@@ -793,6 +818,17 @@ __global__ void k_prepare(unsigned *arrive, int G, unsigned *release, int32_t *a
   }
 }
 
+// The same for every instance of a batch launch: block b resets instance b.
+__global__ void k_prepare_batch(const CoopArgs *__restrict__ descs) {
+  const CoopArgs &A = descs[blockIdx.x];
+  for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
+  if (threadIdx.x == 0) {
+    *A.bar.release = 0u;
+    *A.bar.abort_flag = 0;
+    *A.status = PSCA_OK;
+  }
+}
+
 __global__ void k_threshold(const float *__restrict__ x, int N, float theta, uint8_t *__restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n < N) out[n] = x[n] >= theta ? 1 : 0;
@@ -815,6 +851,12 @@ struct psca_ctx {
   const void *occ_fn;
   size_t occ_lds;
   int occ_per_cu;
+  // batch launches: instance descriptors and the workgroup map, staged in
+  // pinned host memory and copied on the caller's stream
+  void *hdesc, *ddesc;
+  size_t desc_bytes;
+  hipEvent_t desc_done;   // the last copy out of hdesc
+  bool desc_pending;
 };
 
 namespace {
@@ -938,45 +980,57 @@ int max_coresident(psca_ctx *ctx, const KernelChoice &kc, size_t lds) {
   return ctx->occ_per_cu * ctx->n_cu;
 }
 
-// Runs k_psca for `iters` iterations from x_in (null: zeros).
-int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
-               int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
-               float *xt_out, int32_t *status, hipStream_t st) {
-  const int Lp = (L + 15) & ~15, Lb = Lp / 16, NB = Lb * (Lb + 1) / 2;
-  const int E = NB * 256;
-  const KernelChoice kc = pick_kernel(Lp);
-  int ncb = 1, G = 0;
-  size_t lds = 0;
-  for (;; ++ncb) {
-    if (ncb > kMaxNcb) return PSCA_ENOTSUP;
-    const int NT = 16 * ncb;
-    G = (N + NT - 1) / NT;
-    lds = lds_bytes(Lp, NT, kc.threads / 64);
-    const int cap = max_coresident(ctx, kc, lds);
-    if (cap <= 0) return PSCA_ENOTSUP;
-    if (G <= cap) break;
-  }
-  const int NT = 16 * ncb;
-  // workspace: partials, Sigma, barrier words
-  size_t off = 0;
-  const size_t o_part = off; off = align_up(off + (size_t)G * E * sizeof(float2));
-  const size_t o_sig = off;  off = align_up(off + (size_t)E * sizeof(float2));
-  const size_t o_arr = off;  off = align_up(off + (size_t)G * 16 * sizeof(unsigned));
-  const size_t o_rel = off;  off = align_up(off + sizeof(unsigned));
-  const size_t o_abt = off;  off = align_up(off + sizeof(int32_t));
-  const size_t o_st = off;   off = align_up(off + sizeof(int32_t));
-  int rc = ensure_ws(ctx, off);
-  if (rc != PSCA_OK) return rc;
-  char *base = (char *)ctx->ws;
+// Launch plan of one instance: 16-column blocks per workgroup, workgroups,
+// LDS bytes and workspace bytes.
+struct InstPlan {
+  int Lp, ncb, NT, G;
+  size_t lds, ws;
+};
 
-  CoopArgs a;
+size_t ws_bytes_of(int Lp, int G) {
+  const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
+  return align_up((size_t)G * E * sizeof(float2)) + align_up(E * sizeof(float2)) +
+         align_up((size_t)G * 16 * sizeof(unsigned)) + 3 * align_up(sizeof(unsigned));
+}
+
+// The smallest column tile whose workgroups all fit `cap` co-resident slots.
+int plan_instance(int L, int N, int threads, int cap, InstPlan &p) {
+  p.Lp = (L + 15) & ~15;
+  for (int ncb = 1; ncb <= kMaxNcb; ++ncb) {
+    const int NT = 16 * ncb, G = (N + NT - 1) / NT;
+    if (G > cap) continue;
+    p.ncb = ncb;
+    p.NT = NT;
+    p.G = G;
+    p.lds = lds_bytes(p.Lp, NT, threads / 64);
+    p.ws = ws_bytes_of(p.Lp, G);
+    return PSCA_OK;
+  }
+  return PSCA_ENOTSUP;
+}
+
+// Point the instance's work buffers into `base` (laid out as ws_bytes_of).
+void bind_ws(CoopArgs &a, char *base, const InstPlan &p) {
+  const size_t E = (size_t)(p.Lp / 16) * (p.Lp / 16 + 1) / 2 * 256;
+  size_t off = 0;
+  a.partials = (float2 *)(base + off); off += align_up((size_t)p.G * E * sizeof(float2));
+  a.sigma = (float2 *)(base + off);    off += align_up(E * sizeof(float2));
+  a.bar.arrive = (unsigned *)(base + off); off += align_up((size_t)p.G * 16 * sizeof(unsigned));
+  a.bar.release = (unsigned *)(base + off); off += align_up(sizeof(unsigned));
+  a.bar.abort_flag = (int32_t *)(base + off); off += align_up(sizeof(unsigned));
+  if (!a.status) a.status = (int32_t *)(base + off);
+}
+
+void fill_args(CoopArgs &a, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm, int iters,
+               float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out, float *xt_out,
+               int32_t *status, const InstPlan &p) {
   a.S = S;
   a.Sh = Sh;
   a.L = L;
   a.N = N;
-  a.G = G;
-  a.ncb = ncb;
-  a.NT = NT;
+  a.G = p.G;
+  a.ncb = p.ncb;
+  a.NT = p.NT;
   a.iters = iters;
   a.rho0 = prm->rho0;
   a.rho_decay = prm->rho_decay;
@@ -989,21 +1043,74 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
   a.q_out = q_out;
   a.r_out = r_out;
   a.xt_out = xt_out;
-  a.status = status ? status : (int32_t *)(base + o_st);
-  a.partials = (float2 *)(base + o_part);
-  a.sigma = (float2 *)(base + o_sig);
-  a.bar.arrive = (unsigned *)(base + o_arr);
-  a.bar.release = (unsigned *)(base + o_rel);
-  a.bar.abort_flag = (int32_t *)(base + o_abt);
+  a.status = status;
+}
 
-  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.bar.arrive, G, a.bar.release, a.bar.abort_flag,
+// Runs k_psca for `iters` iterations from x_in (null: zeros).
+int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
+               int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
+               float *xt_out, int32_t *status, hipStream_t st) {
+  const int Lp = (L + 15) & ~15;
+  const KernelChoice kc = pick_kernel(Lp);
+  InstPlan p{};
+  for (int ncb = 1;; ++ncb) {   // occupancy depends on the tile's LDS
+    if (ncb > kMaxNcb) return PSCA_ENOTSUP;
+    const int NT = 16 * ncb, G = (N + NT - 1) / NT;
+    const size_t lds = lds_bytes(Lp, NT, kc.threads / 64);
+    const int cap = max_coresident(ctx, kc, lds);
+    if (cap <= 0) return PSCA_ENOTSUP;
+    if (G <= cap) {
+      p = InstPlan{Lp, ncb, NT, G, lds, ws_bytes_of(Lp, G)};
+      break;
+    }
+  }
+  int rc;
+  if ((rc = ensure_ws(ctx, p.ws)) != PSCA_OK) return rc;
+  CoopArgs a;
+  fill_args(a, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
+  bind_ws(a, (char *)ctx->ws, p);
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.bar.arrive, p.G, a.bar.release, a.bar.abort_flag,
                      a.status);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
   void *args[] = {&a};
-  if (hipLaunchCooperativeKernel(kc.fn, dim3(G), dim3(kc.threads), args, (unsigned)lds, st) != hipSuccess) {
+  if (hipLaunchCooperativeKernel(kc.fn, dim3(p.G), dim3(kc.threads), args, (unsigned)p.lds, st) != hipSuccess) {
     (void)hipGetLastError();
     return PSCA_EHIP;
   }
+  return PSCA_OK;
+}
+
+// Stage `bytes` of launch descriptors: returns the pinned host buffer to fill;
+// the previous copy out of it has completed.
+int stage_desc(psca_ctx *ctx, size_t bytes, char **host) {
+  if (ctx->desc_pending) {
+    if (hipEventSynchronize(ctx->desc_done) != hipSuccess) return PSCA_EHIP;
+    ctx->desc_pending = false;
+  }
+  if (bytes > ctx->desc_bytes) {
+    if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
+    ctx->hdesc = nullptr;
+    if (ctx->ddesc) {
+      if (hipDeviceSynchronize() != hipSuccess) return PSCA_EHIP;
+      (void)hipFree(ctx->ddesc);
+      ctx->ddesc = nullptr;
+    }
+    ctx->desc_bytes = 0;
+    const size_t want = bytes + bytes / 2;
+    if (hipHostMalloc(&ctx->hdesc, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->hdesc = nullptr;
+      return PSCA_ENOMEM;
+    }
+    if (hipMalloc(&ctx->ddesc, want) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(ctx->hdesc);
+      ctx->hdesc = ctx->ddesc = nullptr;
+      return PSCA_ENOMEM;
+    }
+    ctx->desc_bytes = want;
+  }
+  *host = (char *)ctx->hdesc;
   return PSCA_OK;
 }
 
@@ -1045,6 +1152,16 @@ int psca_create(psca_ctx **ctx, int device) {
   c->occ_fn = nullptr;
   c->occ_lds = (size_t)-1;
   c->occ_per_cu = 0;
+  c->hdesc = c->ddesc = nullptr;
+  c->desc_bytes = 0;
+  c->desc_pending = false;
+  {
+    DeviceGuard g(device);
+    if (!g.ok || hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming) != hipSuccess) {
+      delete c;
+      return PSCA_EHIP;
+    }
+  }
   *ctx = c;
   return PSCA_OK;
 }
@@ -1052,11 +1169,14 @@ int psca_create(psca_ctx **ctx, int device) {
 int psca_destroy(psca_ctx *ctx) {
   if (!ctx) return PSCA_OK;
   int rc = PSCA_OK;
-  if (ctx->ws || ctx->sh) {
+  {
     DeviceGuard g(ctx->device);
     if (hipDeviceSynchronize() != hipSuccess) rc = PSCA_EHIP;
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->sh) (void)hipFree(ctx->sh);
+    if (ctx->ddesc) (void)hipFree(ctx->ddesc);
+    if (ctx->hdesc) (void)hipHostFree(ctx->hdesc);
+    (void)hipEventDestroy(ctx->desc_done);
   }
   delete ctx;
   return rc;
@@ -1114,6 +1234,114 @@ int psca_iterate(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, in
   if (!g.ok) return PSCA_EHIP;
   return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, 1, rho, x_in, x_out, q_out,
                     r_out, xt_out, status, as_stream(stream));
+}
+
+int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream) {
+  if (!ctx || B < 0 || (B > 0 && !problems)) return PSCA_EINVAL;
+  for (int b = 0; b < B; ++b) {
+    const psca_problem &q = problems[b];
+    if (!q.Sigma_hat || !q.S || !q.x_out) return PSCA_EINVAL;
+    const int rc = validate_params(&q.prm, q.L, q.N, true);
+    if (rc != PSCA_OK) return rc;
+  }
+  if (B == 0) return PSCA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return PSCA_EHIP;
+  hipStream_t st = as_stream(stream);
+  const void *fn = (const void *)k_psca_batch;
+
+  // co-resident capacity at the largest LDS any instance needs, then plans
+  std::vector<InstPlan> plan(B);
+  size_t lds_max = 0;
+  int cap = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 0) {
+      for (int b = 0; b < B; ++b)
+        lds_max = std::max(lds_max, lds_bytes((problems[b].L + 15) & ~15, 16, kBatchThreads / 64));
+    }
+    const KernelChoice kc{fn, kBatchThreads, 96};
+    cap = max_coresident(ctx, kc, lds_max);
+    if (cap <= 0) return PSCA_ENOTSUP;
+    size_t need = 0;
+    for (int b = 0; b < B; ++b) {
+      const int rc = plan_instance(problems[b].L, problems[b].N, kBatchThreads, cap, plan[b]);
+      if (rc != PSCA_OK) return rc;
+      need = std::max(need, plan[b].lds);
+    }
+    if (need <= lds_max) break;
+    lds_max = need;
+  }
+
+  // rounds: instances ordered by size, packed first-fit into cap workgroups
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (size_t)plan[x].G * plan[x].Lp * plan[x].Lp > (size_t)plan[y].G * plan[y].Lp * plan[y].Lp;
+  });
+  std::vector<int> round_first, round_count, round_wgs;
+  std::vector<size_t> round_ws;
+  for (int k = 0; k < B; ++k) {
+    const InstPlan &pk = plan[order[k]];
+    if (round_first.empty() || round_wgs.back() + pk.G > cap) {
+      round_first.push_back(k);
+      round_count.push_back(0);
+      round_wgs.push_back(0);
+      round_ws.push_back(0);
+    }
+    round_count.back() += 1;
+    round_wgs.back() += pk.G;
+    round_ws.back() += pk.ws;
+  }
+  size_t ws_need = 0, wgs_total = 0;
+  for (size_t r = 0; r < round_first.size(); ++r) {
+    ws_need = std::max(ws_need, round_ws[r]);
+    wgs_total += round_wgs[r];
+  }
+  int rc = ensure_ws(ctx, ws_need);
+  if (rc != PSCA_OK) return rc;
+  const size_t desc_off = 0, map_off = align_up((size_t)B * sizeof(CoopArgs));
+  char *host = nullptr;
+  if ((rc = stage_desc(ctx, map_off + wgs_total * sizeof(int2), &host)) != PSCA_OK) return rc;
+  CoopArgs *hd = (CoopArgs *)(host + desc_off);
+  int2 *hm = (int2 *)(host + map_off);
+  size_t map_pos = 0;
+  for (size_t r = 0; r < round_first.size(); ++r) {
+    size_t ws_pos = 0;
+    for (int j = 0; j < round_count[r]; ++j) {
+      const int k = round_first[r] + j, b = order[k];
+      const psca_problem &q = problems[b];
+      CoopArgs &a = hd[k];
+      fill_args(a, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, q.prm.iters, -1.0f,
+                nullptr, q.x_out, nullptr, nullptr, nullptr, q.status, plan[b]);
+      bind_ws(a, (char *)ctx->ws + ws_pos, plan[b]);
+      ws_pos += plan[b].ws;
+      for (int w = 0; w < plan[b].G; ++w) hm[map_pos++] = make_int2(j, w);
+    }
+  }
+  if (hipMemcpyAsync(ctx->ddesc, host, map_off + wgs_total * sizeof(int2), hipMemcpyHostToDevice, st) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  if (hipEventRecord(ctx->desc_done, st) != hipSuccess) return PSCA_EHIP;
+  ctx->desc_pending = true;
+  const CoopArgs *dd = (const CoopArgs *)((char *)ctx->ddesc + desc_off);
+  const int2 *dm = (const int2 *)((char *)ctx->ddesc + map_off);
+  map_pos = 0;
+  for (size_t r = 0; r < round_first.size(); ++r) {
+    const CoopArgs *descs = dd + round_first[r];
+    const int2 *wg_map = dm + map_pos;
+    hipLaunchKernelGGL(k_prepare_batch, dim3(round_count[r]), dim3(256), 0, st, descs);
+    if ((rc = launch_ok()) != PSCA_OK) return rc;
+    void *args[] = {(void *)&descs, (void *)&wg_map};
+    if (hipLaunchCooperativeKernel(fn, dim3(round_wgs[r]), dim3(kBatchThreads), args, (unsigned)lds_max, st) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return PSCA_EHIP;
+    }
+    map_pos += round_wgs[r];
+  }
+  return PSCA_OK;
 }
 
 #ifdef PSCA_PHASE_TRACE

@@ -182,6 +182,52 @@ def detect_y(Y: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Con
     return x
 
 
+@dataclass
+class Problem:
+    """One instance of a batch (psca_problem): SigmaHat, S, parameters and the
+    output vector (allocated by detect_batch when None)."""
+    Sigma_hat: torch.Tensor
+    S: torch.Tensor
+    params: Params
+    out: Optional[torch.Tensor] = None
+    status: Optional[torch.Tensor] = None
+
+
+def detect_batch(problems, ctx: Optional[Context] = None, stream=None):
+    """psca_detect_batch: independent detections in one launch.  Returns the
+    list of x vectors (each problem's `out`)."""
+    if not problems:
+        return []
+    ctx = ctx or default_context(problems[0].S.device)
+    arr = (N.PscaProblem * len(problems))()
+    keep = []
+    outs = []
+    for k, pb in enumerate(problems):
+        _need(pb.S, torch.complex64, ctx.device, "S")
+        _need(pb.Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
+        S = colmajor(pb.S)
+        Sh = colmajor(pb.Sigma_hat)
+        L, n = S.shape
+        if Sh.shape != (L, L):
+            raise ValueError("Sigma_hat must be L x L")
+        pb.params.check_tensors(ctx.device, n)
+        x = torch.empty(n, dtype=torch.float32, device=ctx.device) if pb.out is None else pb.out
+        if x.numel() != n or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("out must be a contiguous float32 vector of length N")
+        keep += [S, Sh]
+        outs.append(x)
+        e = arr[k]
+        e.Sigma_hat = Sh.data_ptr()
+        e.S = S.data_ptr()
+        e.L, e.N = L, n
+        e.prm = pb.params.to_c()
+        e.x_out = x.data_ptr()
+        e.status = None if pb.status is None else pb.status.data_ptr()
+    N.check(ctx._lib.psca_detect_batch(ctx.handle, len(problems), arr, _stream(ctx.device, stream)),
+            "psca_detect_batch")
+    return outs
+
+
 def iterate(Sigma_hat: torch.Tensor, S: torch.Tensor, x: torch.Tensor, rho: float, params: Params,
             ctx: Optional[Context] = None, stream=None, status: Optional[torch.Tensor] = None):
     """One iteration (psca_iterate).  Returns (x_next, q, r, x_tilde)."""

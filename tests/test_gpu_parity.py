@@ -196,3 +196,63 @@ def test_host_validation_errors(P):
     with pytest.raises(P.PscaError) as e:
         P.detect_y(c64(big.Y), c64(big.S), P.Params(variant=O.ML_UD, iters=5, M=8))
     assert e.value.code == -5
+
+
+def test_batch_mixed_instances_match_oracle_and_single_calls(P):
+    """psca_detect_batch over instances of different L, N, M, variant and
+    iteration count: each result meets the oracle bar and agrees with the
+    same instance run alone."""
+    cases = [(O.ML_K, I.workload_instance("single", 0).fp32_inputs(), 40),
+             (O.MAP_K, I.make_instance(5, 11, 300, 20, 16, 0.15).fp32_inputs(), 25),
+             (O.ML_UD, I.make_instance(5, 12, 700, 96, 64, 0.1).fp32_inputs(), 20),
+             (O.MAP_UR, I.workload_instance("small", 0).fp32_inputs(), 60),
+             (O.ML_UD, I.make_instance(5, 13, 17, 5, 8, 0.3).fp32_inputs(), 10)]
+    probs, refs, singles = [], [], []
+    for variant, inst, iters in cases:
+        Sh = P.sample_cov(c64(inst.Y))
+        prm = params_for(P, inst, variant, iters)
+        probs.append(P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=prm,
+                               status=torch.full((1,), 7, dtype=torch.int32, device=dev())))
+        singles.append(P.detect(Sh, c64(inst.S), prm))
+        refs.append(O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters))
+    outs = P.detect_batch(probs)
+    torch.cuda.synchronize()
+    for (variant, inst, iters), pb, x, xs, ref in zip(cases, probs, outs, singles, refs):
+        assert int(pb.status.item()) == 0
+        got = x.cpu().numpy().astype(np.float64)
+        assert_parity(got, ref, variant, "batch " + label(inst, variant, iters))
+        one = xs.cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - one)) <= 1e-6 * max(1.0, np.max(np.abs(one)))
+
+
+def test_batch_larger_than_the_gpu_runs_in_rounds(P):
+    """Seven N=2000 instances need 7 x 125 workgroups, more than are
+    co-resident: the batch runs in successive launches, each result exact to
+    the oracle bar."""
+    probs, refs, insts = [], [], []
+    for k in range(7):
+        inst = I.make_instance(5, 100 + k, 2000, 32, 64, 0.1).fp32_inputs()
+        variant = (O.ML_K, O.ML_UD)[k % 2]
+        prm = params_for(P, inst, variant, 15)
+        probs.append(P.Problem(Sigma_hat=P.sample_cov(c64(inst.Y)), S=c64(inst.S), params=prm,
+                               status=torch.full((1,), 7, dtype=torch.int32, device=dev())))
+        refs.append((variant, O.psca(O.problem_from_instance(inst, variant, eps=EPS), 15)))
+        insts.append(inst)
+    print("[batch 7 x N=2000 L=32 M=64 iters=15]", flush=True)
+    outs = P.detect_batch(probs)
+    torch.cuda.synchronize()
+    for pb, x, (variant, ref), inst in zip(probs, outs, refs, insts):
+        assert int(pb.status.item()) == 0
+        assert_parity(x.cpu().numpy().astype(np.float64), ref, variant, "rounds " + label(inst, variant, 15))
+
+
+def test_batch_validation_and_empty(P):
+    inst = I.make_instance(5, 3, 20, 8, 16, 0.2).fp32_inputs()
+    Sh = P.sample_cov(c64(inst.Y))
+    assert P.detect_batch([]) == []
+    bad = params_for(P, inst, O.ML_K, 5)
+    bad.g = None
+    with pytest.raises(P.PscaError) as e:
+        P.detect_batch([P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, O.ML_UD, 5)),
+                        P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=bad)])
+    assert e.value.code == -1
