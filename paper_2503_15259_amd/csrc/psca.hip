@@ -177,20 +177,23 @@ __device__ __forceinline__ float coordinate_step(float x, float q, float r, floa
 
 // ---------------------------------------------------------------------------
 // Grid barrier (agent scope).  Each workgroup raises its own arrival word
-// (64-byte stride, no contended atomics); workgroup 0 gathers them and
-// publishes the generation.  Every wait is bounded by kSpinLimit polls: a
-// waiter that gives up raises *abort, and all waiters also watch *abort, so a
-// missing workgroup cannot hang the grid.
+// (64-byte stride, no contended atomics) and waits until it has seen every
+// arrival word of its instance reach the generation: one round trip through
+// memory.  Every wait is bounded by kSpinLimit polls: a waiter that gives up
+// raises *abort, and all waiters also watch *abort, so a missing workgroup
+// cannot hang the grid.
 // ---------------------------------------------------------------------------
 struct GridBar {
   unsigned *arrive;    // [G * 16]
-  unsigned *release;   // generation published by workgroup 0
+  unsigned *release;   // unused (kept zero)
   int32_t *abort_flag;
 };
 
+// Waits until *word has reached generation `target` (generations only grow;
+// the difference is taken modulo 2^32).
 __device__ __forceinline__ bool spin_until(const unsigned *word, unsigned target, const int32_t *abort_flag) {
   unsigned spins = 0;
-  while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+  while ((int)(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
     if (++spins > kSpinLimit) return false;
     if ((spins & 255u) == 0 && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return false;
@@ -206,20 +209,11 @@ __device__ __forceinline__ bool grid_sync(const GridBar &b, unsigned G, unsigned
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __hip_atomic_store(&b.arrive[g * 16], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (g == 0) {
-    int ok = 1;
-    for (unsigned w = threadIdx.x; w < G; w += blockDim.x)
-      if (!spin_until(&b.arrive[w * 16], target, b.abort_flag)) ok = 0;
-    ok = __syncthreads_and(ok);
-    if (threadIdx.x == 0) {
-      if (!ok) __hip_atomic_store(b.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      __hip_atomic_store(b.release, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  int ok = 1;
+  for (unsigned w = threadIdx.x; w < G; w += blockDim.x)
+    if (!spin_until(&b.arrive[w * 16], target, b.abort_flag)) ok = 0;
+  ok = __syncthreads_and(ok);
   if (threadIdx.x == 0) {
-    int ok = spin_until(b.release, target, b.abort_flag) ? 1 : 0;
-    if (__hip_atomic_load(b.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
     if (!ok) __hip_atomic_store(b.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *s_ok = ok;
@@ -254,8 +248,7 @@ struct CoopArgs {
 __host__ __device__ inline size_t lds_bytes(int Lp, int NT, int waves) {
   const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
   const bool sh_lds = Lp <= 64;
-  const size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256 +
-                    Lb * 256 + 16;
+  const size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256;
   const size_t f4b = 3 * (size_t)NT + 2 * Lb * NT;   // floats
   return f2 * sizeof(float2) + f4b * 4;
 }
@@ -292,73 +285,134 @@ __device__ __forceinline__ void cblock_mma_rm(const float2 *A, int lda, const fl
 }
 
 // ---------------------------------------------------------------------------
-// Sigma^-1 by a blocked Hermitian sweep (Gauss-Jordan on an HPD matrix)
+// Sigma^-1 by a blocked Cholesky factorisation Sigma = L L^H, W = L^-1 and
+// Sigma^-1 = W^H W
 // ---------------------------------------------------------------------------
-// Sweeping pivot k of a Hermitian matrix D with p = D[k][k] > 0 replaces D by
-//   D[i][j] - D[i][k] conj(D[j][k]) / p   (i, j != k),
-//   D[i][k] / p,  conj(D[j][k]) / p       (row and column k),
-//   -1 / p                                (the pivot);
-// sweeping every pivot of an HPD matrix leaves -D^-1, and every pivot is a
-// Schur-complement diagonal, so D is positive definite iff all pivots are > 0.
-// With e = column k with e_k replaced by -1, all four rules are one rank-1
-// update of D with row and column k cleared: D' - e e^H / p.
-//
-// leaf_sweep: one wavefront sweeps a 16x16 block (column-major at D, pitch
-// ld) in registers.  Lane l holds row i = l % 16 of columns q, q+4, q+8, q+12
-// (q = l / 16); column k travels through 16 words of LDS (`col`), written and
-// read by the same wavefront, so no workgroup barrier is needed.  Returns
-// false if some pivot is not positive and finite.
+// Orders this wavefront's LDS writes before its later LDS reads.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ bool leaf_sweep(float2 *D, int ld, float2 *col, int lane) {
-  const int i = lane & 15, q = lane >> 4;
-  float2 d[4];
+template <int K>
+__device__ __forceinline__ float row_bcast(float v) {   // lane K of each 16-lane row
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xf, 0xf, false));
+}
+
+// leaf_chol: one wavefront factors a 16x16 HPD block A = L L^H held in
+// registers and builds W = L^-1 alongside.  Lane l holds column j = l % 16
+// of rows r, r+4, r+8, r+12 (r = l / 16) of A (both triangles) and of the
+// running X (starting from I).  Step k: the pivot comes by readlane, column
+// k on the lane's rows by a DPP row broadcast (lane k of its 16-lane row),
+// row k on the lane's column (A[k][j] = conj(A[j][k]) and X[k][j]) by a lane
+// permute; row k of W is X[k][.] / L[k][k], then rows i > k take
+// X[i][.] -= L[i][k] W[k][.] and the trailing A[i][j] -= A[i][k] A[k][j] / A[k][k].
+// No LDS and no barrier.  ok turns false if a pivot is not positive and finite.
+template <int K>
+__device__ __forceinline__ void chol_step(float2 (&a)[4], float2 (&x)[4], int j, int r, bool &ok) {
+  const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[K >> 2].x), K + 16 * (K & 3)));
+  ok = ok && (p > 0.0f) && (p < INFINITY);
+  float rs = __builtin_amdgcn_rsqf(p);
+  rs = rs * (1.5f - 0.5f * p * rs * rs);   // one Newton step
+  const float invd = rs * rs;
+  float2 ck[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) d[m] = D[(q + 4 * m) * ld + i];
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    if (q == (k & 3)) col[i] = d[k >> 2];   // the owners of column k publish it
-    wave_lds_sync();
-    const float2 ci = col[i];
-    float2 cj[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) cj[m] = col[q + 4 * m];
-    const float p = col[k].x;
-    wave_lds_sync();
-    ok = ok && (p > 0.0f) && (p < INFINITY);
-    float rp = __builtin_amdgcn_rcpf(p);
-    rp = rp * (2.0f - p * rp);   // one Newton step
-    const float2 ei = (i == k) ? make_float2(-1.0f, 0.0f) : ci;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const bool jk = (q + 4 * m == k);
-      const float2 ej = jk ? make_float2(-1.0f, 0.0f) : cj[m];
-      const float2 v = (i == k || jk) ? make_float2(0.0f, 0.0f) : d[m];
-      const float2 t = cmul_conj(ei, ej);
-      d[m] = make_float2(v.x - t.x * rp, v.y - t.y * rp);
-    }
+  for (int m = 0; m < 4; ++m) ck[m] = make_float2(row_bcast<K>(a[m].x), row_bcast<K>(a[m].y));
+  const int src = j + 16 * (K & 3);
+  const float2 rk = make_float2(__shfl(a[K >> 2].x, src), __shfl(a[K >> 2].y, src));   // A[K][j]
+  float2 wk = make_float2(__shfl(x[K >> 2].x, src), __shfl(x[K >> 2].y, src));         // X[K][j]
+  wk.x *= rs;
+  wk.y *= rs;   // W[K][j]
+  if (r == (K & 3)) {   // row K of W is final
+    x[K >> 2].x *= rs;
+    x[K >> 2].y *= rs;
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) D[(q + 4 * m) * ld + i] = d[m];
+  for (int m = 0; m < 4; ++m) {
+    if (r + 4 * m > K) {
+      const float2 lik = make_float2(ck[m].x * rs, ck[m].y * rs);   // L[i][K]
+      const float2 t = cmul(lik, wk);
+      x[m].x -= t.x;
+      x[m].y -= t.y;
+      if (j > K) {
+        const float2 u = cmul(ck[m], rk);
+        a[m].x -= u.x * invd;
+        a[m].y -= u.y * invd;
+      }
+    }
+  }
+}
+
+template <int... Ks>
+__device__ __forceinline__ bool chol_steps(float2 (&a)[4], float2 (&x)[4], int j, int r,
+                                           std::integer_sequence<int, Ks...>) {
+  bool ok = true;
+  (chol_step<Ks>(a, x, j, r, ok), ...);
   return ok;
 }
 
-// Operand loaders for a 16x16 block of the sweep.  Only lower blocks (I >= J)
-// are stored (column-major in WS, pitch P); block (I, J) of the Hermitian
-// matrix with I < J is the conjugate transpose of stored block (J, I).
-// a_elem returns X[r][c] of block (I, J) for any I, J.
-__device__ __forceinline__ float2 blk_elem(const float2 *WS, int P, int I, int J, int r, int c) {
-  if (I >= J) return WS[(16 * J + c) * P + 16 * I + r];
-  const float2 v = WS[(16 * I + r) * P + 16 * J + c];
-  return make_float2(v.x, -v.y);
+// Factors the 16x16 block at D (column-major, pitch ld, both triangles) and
+// overwrites it with W = L^-1 (zeros above the diagonal).
+__device__ __forceinline__ bool leaf_chol(float2 *D, int ld, int lane) {
+  const int j = lane & 15, r = lane >> 4;
+  float2 a[4], x[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    a[m] = D[j * ld + r + 4 * m];
+    x[m] = make_float2(r + 4 * m == j ? 1.0f : 0.0f, 0.0f);
+  }
+  const bool ok = chol_steps(a, x, j, r, std::make_integer_sequence<int, 16>{});
+#pragma unroll
+  for (int m = 0; m < 4; ++m) D[j * ld + r + 4 * m] = x[m];
+  return ok;
 }
 
-// One detection on workgroup g of the G workgroups the instance owns.
+// MFMA tasks of block step J of the factorisation (one wavefront each; WS
+// column-major with pitch P, lower blocks hold A and then L).
+// Panel: L_IJ = A_IJ W_JJ^H (W_JJ in the diagonal block J).
+__device__ __forceinline__ void chol_panel(float2 *WS, int P, int J, int I, int l16, int lq) {
+  f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+  float2 a4[4], b4[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + lq;
+    a4[ks] = WS[(16 * J + k) * P + 16 * I + l16];
+    const float2 w = WS[(16 * J + k) * P + 16 * J + l16];   // W_JJ[l16][k]
+    b4[ks] = make_float2(w.x, -w.y);
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+  wave_lds_sync();
+  float2 *dst = WS + (16 * J + l16) * P + 16 * I + 4 * lq;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) dst[v] = make_float2(cr[v], ci[v]);
+}
+
+// Trailing: A_IK -= L_IJ L_KJ^H, J < K <= I.
+__device__ __forceinline__ void chol_trail(float2 *WS, int P, int J, int I, int K, int l16, int lq) {
+  float2 *dst = WS + (16 * K + l16) * P + 16 * I + 4 * lq;
+  f4 cr, ci;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    cr[v] = dst[v].x;
+    ci[v] = dst[v].y;
+  }
+  float2 a4[4], b4[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + lq;
+    const float2 l = WS[(16 * J + k) * P + 16 * I + l16];   // L_IJ[l16][k]
+    a4[ks] = make_float2(-l.x, -l.y);
+    const float2 m = WS[(16 * J + k) * P + 16 * K + l16];   // L_KJ[l16][k]
+    b4[ks] = make_float2(m.x, -m.y);                        // L_KJ^H[k][l16]
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) dst[v] = make_float2(cr[v], ci[v]);
+}
+
 template <int LPMAX, int THREADS>
 __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int kWaves = THREADS / 64;
@@ -368,16 +422,14 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int kRowBlocksPerWave = (Lb + kWaves - 1) / kWaves;
   constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
   extern __shared__ float4 smem_raw[];
-  __shared__ int s_ok, s_pd;
+  __shared__ int s_ok, s_pd[LPMAX / 16];
   const int NT = A.NT, PT = A.NT + 1;
   float2 *St = (float2 *)smem_raw;          // [Lp][PT]  S tile, row i at i * PT
   float2 *Bt = St + Lp * PT;                // [Lp][PT]  B tile (also reduction scratch)
   float2 *WS = Bt + Lp * PT;                // [Lp][P]   column-major: Cholesky columns, W, Sigma^-1
   float2 *ShL = WS + Lp * P;                // [Lp][P]   SigmaHat, column-major (kShLds)
   float2 *scr = ShL + (kShLds ? Lp * P : 0);// [kWaves][256] per-wave 16x16 scratch
-  float2 *TP = scr + kWaves * 256;          // [Lb][256] panel blocks of the current sweep step
-  float2 *colb = TP + Lb * 256;             // [16]      column exchange of the leaf sweep
-  float *xs = (float *)(colb + 16);         // [NT] iterate of the tile
+  float *xs = (float *)(scr + kWaves * 256);   // [NT] iterate of the tile
   float *gs = xs + NT;                      // [NT] pathloss
   float *ls = gs + NT;                      // [NT] log(p / (1 - p))
   float *red_q = ls + NT;                   // [Lb][NT]
@@ -516,14 +568,12 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
-    // ===== C1-C3. Sigma^-1 by the blocked Hermitian sweep ====================
-    // Every workgroup inverts the same Sigma (no further grid barrier).  For
-    // each diagonal block J: wavefront 0 sweeps block (J, J) in registers,
-    // giving Q = -(A_JJ)^-1, while the other wavefronts write back the panel of
-    // step J-1; then, on MFMA, every lower block (I, K) with I, K != J takes
-    // A_IK += A_IJ Q A_JK and the panel blocks take A_IJ Q, staged in TP
-    // because the updates still read the old panel.  After the last block WS
-    // holds -Sigma^-1 in its lower blocks.
+    // ===== C1. Blocked Cholesky Sigma = L L^H, diagonal blocks of W = L^-1 ==
+    // Every workgroup factors the same Sigma (no further grid barrier).  Block
+    // step J: wavefront 0 has factored diagonal block J in registers and left
+    // W_JJ in its place; the panel L_IJ = A_IJ W_JJ^H follows on MFMA, then
+    // the trailing updates A_IK -= L_IJ L_KJ^H, during which wavefront 0
+    // updates block J+1 first and factors it.
     PSCA_MARK(it, 4);
     for (int e = tid; e < E; e += THREADS) {
       const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
@@ -532,129 +582,113 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
       WS[(16 * J + jj) * P + 16 * I + ii] = A.sigma[e];
     }
     __syncthreads();
-    {
-      constexpr int nt = (Lb - 1) * Lb / 2, np = Lb - 1;
-      for (int J = 0; J < Lb; ++J) {
-        if (wave == 0) {
-          const bool ok = leaf_sweep(WS + 16 * J * P + 16 * J, P, colb, lane);
-          if (lane == 0) s_pd = ok ? 1 : 0;
-        } else if (J > 0) {
-          const int Jp = J - 1;
-          for (int e = tid - 64; e < np * 256; e += THREADS - 64) {
-            const int t = e >> 8, c = (e >> 4) & 15, r = e & 15;
-            const int I = t + (t >= Jp);
-            const float2 v = TP[I * 256 + c * 16 + r];
-            if (I > Jp) WS[(16 * Jp + c) * P + 16 * I + r] = v;
-            else WS[(16 * I + c) * P + 16 * Jp + r] = v;
-          }
-        }
-        __syncthreads();
-        if (!s_pd) {   // uniform: every workgroup sweeps the same Sigma
-          failed = true;
-          break;
-        }
-        const float2 *Q = WS + 16 * J * P + 16 * J;
-        for (int t = 0; t < nt + np; ++t) {
-          int owner;
-          if (t < nt) owner = t % kWaves;
-          else owner = (nt < kWaves) ? kWaves - 1 - (t - nt) % (kWaves - nt) : t % kWaves;
-          if (owner != wave) continue;
-          if (t < nt) {
-            // lower block (I, K) of the Sigma without block row/column J
-            int ii = 0;
-            while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-            const int kk = t - ii * (ii + 1) / 2;
-            const int I = ii + (ii >= J), K = kk + (kk >= J);
-            f4 vr = {0.f, 0.f, 0.f, 0.f}, vi = {0.f, 0.f, 0.f, 0.f};
-            {
-              float2 a4[4], b4[4];
-#pragma unroll
-              for (int ks = 0; ks < 4; ++ks) {   // V = Q A_JK
-                const int k = 4 * ks + lq;
-                a4[ks] = Q[k * P + l16];
-                b4[ks] = blk_elem(WS, P, J, K, k, l16);
-              }
-#pragma unroll
-              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], vr, vi);
-            }
-            float2 *T = scr + wave * 256;   // V, column-major, pitch 16
-#pragma unroll
-            for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(vr[v], vi[v]);
-            wave_lds_sync();
-            f4 cr, ci;
-            float2 *dst = WS + (16 * K + l16) * P + 16 * I + 4 * lq;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              cr[v] = dst[v].x;
-              ci[v] = dst[v].y;
-            }
-            {
-              float2 a4[4], b4[4];
-#pragma unroll
-              for (int ks = 0; ks < 4; ++ks) {   // A_IK += A_IJ V
-                const int k = 4 * ks + lq;
-                a4[ks] = blk_elem(WS, P, I, J, l16, k);
-                b4[ks] = T[l16 * 16 + k];
-              }
-#pragma unroll
-              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dst[v] = make_float2(cr[v], ci[v]);
-            wave_lds_sync();   // T is reused by this wavefront's next task
-          } else {
-            // panel: lower storage of pair {I, J} becomes A_IJ P = -A_IJ Q (I > J)
-            // or P A_JI = -Q A_JI (I < J)
-            const int tp = t - nt, I = tp + (tp >= J);
-            f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-            float2 a4[4], b4[4];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-              const int k = 4 * ks + lq;
-              if (I > J) {
-                a4[ks] = WS[(16 * J + k) * P + 16 * I + l16];
-                b4[ks] = Q[l16 * P + k];
-              } else {
-                a4[ks] = Q[k * P + l16];
-                b4[ks] = WS[(16 * I + l16) * P + 16 * J + k];
-              }
-            }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) TP[I * 256 + l16 * 16 + 4 * lq + v] = make_float2(-cr[v], -ci[v]);
-          }
-        }
-        __syncthreads();
+    if (wave == 0) {
+      const bool ok = leaf_chol(WS, P, lane);
+      if (lane == 0) s_pd[0] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    for (int J = 0; J < Lb; ++J) {
+      PSCA_SUB_MARK(it, J, 0);
+      if (!s_pd[J]) {   // uniform: every workgroup factors the same Sigma
+        failed = true;
+        break;
       }
+      if (J + 1 == Lb) break;
+      for (int I = J + 1 + wave; I < Lb; I += kWaves) chol_panel(WS, P, J, I, l16, lq);
+      __syncthreads();
+      PSCA_SUB_MARK(it, J, 1);
+      if (wave == 0) {
+        chol_trail(WS, P, J, J + 1, J + 1, l16, lq);
+        wave_lds_sync();
+        const bool ok = leaf_chol(WS + 16 * (J + 1) * P + 16 * (J + 1), P, lane);
+        if (lane == 0) s_pd[J + 1] = ok ? 1 : 0;
+      } else {
+        int q = 0;
+        for (int I = J + 2; I < Lb; ++I)
+          for (int K = J + 1; K <= I; ++K)
+            if (q++ % (kWaves - 1) == wave - 1) chol_trail(WS, P, J, I, K, l16, lq);
+      }
+      __syncthreads();
     }
     PSCA_MARK(it, 5);
     if (failed) break;
-    {   // write back the last panel
-      const int Jp = Lb - 1;
-      for (int e = tid; e < (Lb - 1) * 256; e += THREADS) {
-        const int t = e >> 8, c = (e >> 4) & 15, r = e & 15;
-        const int I = t + (t >= Jp);
-        const float2 v = TP[I * 256 + c * 16 + r];
-        if (I > Jp) WS[(16 * Jp + c) * P + 16 * I + r] = v;
-        else WS[(16 * I + c) * P + 16 * Jp + r] = v;
+
+    // ===== C2. Off-diagonal blocks of W, right to left ======================
+    // W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ, written over L_IJ.
+    for (int J = Lb - 2; J >= 0; --J) {
+      f4 rr = {0.f, 0.f, 0.f, 0.f}, ri = {0.f, 0.f, 0.f, 0.f};
+      const int I = J + 1 + wave;
+      if (I < Lb) {
+        f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
+        for (int K = J + 1; K <= I; ++K)
+          cblock_mma(WS + (16 * K) * P + 16 * I, WS + (16 * J) * P + 16 * K, P, l16, lq, tr, ti);
+        float2 *T = scr + wave * 256;          // column-major, pitch 16
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
+        wave_lds_sync();
+        float2 ta[4], wb[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          ta[ks] = T[(4 * ks + lq) * 16 + l16];
+          wb[ks] = WS[(16 * J + l16) * P + 16 * J + 4 * ks + lq];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(ta[ks], wb[ks], rr, ri);
       }
+      __syncthreads();
+      if (I < Lb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) WS[(16 * J + l16) * P + 16 * I + 4 * lq + v] = make_float2(-rr[v], -ri[v]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+
+    // ===== C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS ======
     PSCA_MARK(it, 6);
-    for (int e = tid; e < E; e += THREADS) {   // Sigma^-1, full and exactly Hermitian
-      const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
-      int I, J;
-      blk_coords(b, I, J);
-      const int i = 16 * I + ii, j = 16 * J + jj;
-      if (i >= j) {
-        const float2 v = WS[j * P + i];
-        const float im = (i == j) ? 0.0f : -v.y;
-        WS[j * P + i] = make_float2(-v.x, im);
-        WS[i * P + j] = make_float2(-v.x, -im);
+    {
+      f4 sir[kBlocksPerWave], sii[kBlocksPerWave];
+#pragma unroll
+      for (int q = 0; q < kBlocksPerWave; ++q) {
+        sir[q] = (f4){0.f, 0.f, 0.f, 0.f};
+        sii[q] = (f4){0.f, 0.f, 0.f, 0.f};
+        const int b = wave + kWaves * q;
+        if (b < NB) {
+          int I, J;
+          blk_coords(b, I, J);
+          for (int K = I; K < Lb; ++K) {       // A[i][k] = conj(W[k][i]), B[k][j] = W[k][j]
+            float2 a4[4], b4[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+              const int k = 16 * K + 4 * ks + lq;
+              const float2 wi = WS[(16 * I + l16) * P + k];
+              a4[ks] = make_float2(wi.x, -wi.y);
+              b4[ks] = WS[(16 * J + l16) * P + k];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], sir[q], sii[q]);
+          }
+        }
       }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kBlocksPerWave; ++q) {
+        const int b = wave + kWaves * q;
+        if (b < NB) {
+          int I, J;
+          blk_coords(b, I, J);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * lq + v, j = 16 * J + l16;
+            if (i >= j) {
+              const float im = (i == j) ? 0.0f : sii[q][v];
+              WS[j * P + i] = make_float2(sir[q][v], im);
+              WS[i * P + j] = make_float2(sir[q][v], -im);
+            }
+          }
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
 
     // ===== C4. B = Sigma^-1 S_g and q;  D = SigmaHat B and r =================
     PSCA_MARK(it, 7);
