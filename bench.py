@@ -125,6 +125,126 @@ def cpu_baseline(n_per_variant=4):
 
 
 # ---------------------------------------------------------------------------
+# Uneven batch: independent ML-UD instances of mixed N, L, M in one launch
+# ---------------------------------------------------------------------------
+UNEVEN_POOL = 64       # distinct instances resident on the GPU, cycled through the batch
+UNEVEN_ITERS = 100
+
+
+def _uneven_oracle_task(index):
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    import oracle as O
+    from paper_2503_15259_amd import instances as I
+    inst = I.make_uneven_instance(I.WORKLOAD_IDS["uneven"], index).fp32_inputs()
+    t0 = time.perf_counter()
+    x = O.psca(O.problem_from_instance(inst, O.ML_UD, eps=EPS), UNEVEN_ITERS)
+    return index, time.perf_counter() - t0, x
+
+
+def run_uneven(args):
+    import numpy as np
+    import torch
+    from paper_2503_15259_amd import instances as I
+    from paper_2503_15259_amd import psca as P
+
+    cpu_info, cpu_x = None, {}
+    if not args.no_cpu_baseline:
+        sample = 16
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            cores = os.cpu_count() or 1
+        workers = max(1, min(sample, cores, 16))
+        os.environ["OPENBLAS_NUM_THREADS"] = "1"
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(workers) as pool:
+            res = pool.map(_uneven_oracle_task, range(sample))
+        wall = time.perf_counter() - t0
+        cpu_x = {r[0]: r[2] for r in res}
+        cpu_info = {"value": sample / wall, "unit": "instances/s", "cores": workers, "kind": "oracle",
+                    "sample": f"{sample} instances of the uneven batch (ML-UD, {UNEVEN_ITERS} iterations), FP64 "
+                              f"NumPy oracle, one single-threaded process per instance",
+                    "wall_s": wall}
+
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    wid = I.WORKLOAD_IDS["uneven"]
+    pool_insts = [I.make_uneven_instance(wid, i) for i in range(UNEVEN_POOL)]
+    Ss = [P.colmajor(torch.from_numpy(x.S.astype(np.complex64)).to(dev)) for x in pool_insts]
+    Ys = [P.colmajor(torch.from_numpy(x.Y.astype(np.complex64)).to(dev)) for x in pool_insts]
+    ctx = P.Context(0)
+    Shs = [P.sample_cov(Y, ctx=ctx) for Y in Ys]
+    B = args.instances
+    probs = []
+    for b in range(B):
+        k = b % UNEVEN_POOL
+        inst = pool_insts[k]
+        prm = P.Params(variant=P.ML_UD, iters=UNEVEN_ITERS, sigma2=inst.sigma2, M=inst.M)
+        probs.append(P.Problem(Sigma_hat=Shs[k], S=Ss[k], params=prm))
+    tuned = P.autotune_batch(probs, tune_iters=4, ctx=ctx) if args.autotune else None
+    plan = P.Plan(probs, ctx=ctx)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(args.warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    wall0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        plan.launch()
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    ms = float(launch_ms.mean())
+    value = B / (ms / 1e3)
+    flops = sum(UNEVEN_ITERS * iteration_flops(pool_insts[b % UNEVEN_POOL].N, pool_insts[b % UNEVEN_POOL].L)
+                for b in range(B))
+    achieved = flops / (ms / 1e3) / 1e12
+    parity = None
+    if cpu_x:
+        worst = 0.0
+        for i, xr in cpu_x.items():
+            if i < UNEVEN_POOL:
+                xg = plan.outs[i].cpu().numpy().astype(np.float64)
+                big = np.abs(xr) >= 1e-3 * np.max(np.abs(xr))
+                worst = max(worst, float(np.max(np.abs(xg - xr)[big] / np.abs(xr[big]))))
+        parity = {"ML-UD": {"max_rel_err_gamma": worst, "instances_compared": len(cpu_x)}}
+    Ns = [x.N for x in pool_insts]
+    Ls = [x.L for x in pool_insts]
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"uneven batch of {B} independent ML-UD detections ({UNEVEN_ITERS} iterations) "
+                               f"in one persistent launch; N ~ U{{200..2000}}, L in {{32,48,64,96}}, "
+                               f"M in {{64,128,256}}, p ~ U[0.05,0.2]; {UNEVEN_POOL} distinct instances cycled",
+                   "instances": B, "team_size": plan.team_size, "autotuned": tuned is not None,
+                   "mean_N": float(np.mean(Ns)), "L_mix": {str(l): Ls.count(l) for l in sorted(set(Ls))}},
+        "parity_vs_oracle": parity,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
+                     "kernel": "k_psca_teams (whole batch)", "flops_per_launch": flops,
+                     "avg_launch_ms": round(ms, 4)},
+        "cpu_baseline": cpu_info,
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
 # GPU leg
 # ---------------------------------------------------------------------------
 
@@ -136,6 +256,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain copy kernel of this many MiB (profiler calibration)")
+    ap.add_argument("--workload", choices=["single", "uneven"], default="single",
+                    help="single: the four estimators on N=1000, L=64 (default); uneven: a batch of "
+                         "independent ML-UD instances of mixed sizes in one persistent launch")
+    ap.add_argument("--instances", type=int, default=4096, help="uneven workload: instances per batch")
+    ap.add_argument("--autotune", action="store_true", help="uneven workload: autotune the team size first")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -145,6 +270,10 @@ def main():
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
         sys.exit("--steps must be >= 1 and --warmup >= 0")
+
+    if args.workload == "uneven":
+        run_uneven(args)
+        return
 
     cpu_info, cpu_x, cpu_x64 = (None, {}, {})
     if not args.no_cpu_baseline:

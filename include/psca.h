@@ -152,14 +152,41 @@ typedef struct {
 } psca_problem;
 
 /* B independent detections (Algorithm 1 from x = 0 for each), equivalent to
- * B calls of psca_detect.  `problems` is a HOST array of B entries, read
- * before the call returns.  The instances run concurrently: each gets its own
- * group of workgroups and its own device-wide barrier inside one cooperative
- * launch; a batch larger than the GPU holds at once is split into successive
- * launches.  Instances may differ in L, N, M, variant, iteration count and
- * parameters.  Every instance is validated as in psca_detect before anything
- * is launched (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one). */
+ * B calls of psca_detect, in ONE persistent launch.  `problems` is a HOST
+ * array of B entries, read before the call returns.  The grid is split into
+ * teams of T workgroups; every instance runs on one team (its own group of
+ * workgroups and device-wide barrier) and each team works through a list of
+ * instances, longest first.  Instances may differ in L, N, M, variant,
+ * iteration count and parameters.  T is the value psca_autotune_batch chose
+ * for a batch of the same (L, N) list, else a default (one team per instance
+ * when the batch fits the GPU at once, else the smallest teams).  Every
+ * instance is validated as in psca_detect before anything is launched
+ * (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one). */
 int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream);
+
+/* Autotuner for psca_detect_batch: times the batch with every candidate team
+ * size (each instance capped at tune_iters >= 1 iterations; candidates from
+ * the smallest feasible team to the whole GPU) and remembers the fastest in
+ * the context for batches with the same (L, N) list.  Synchronous; writes
+ * scratch results into the instances' x_out.  *team_size (optional)
+ * receives the choice. */
+int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int tune_iters, int *team_size,
+                        void *stream);
+
+/* A planned batch for repeated launches, e.g. inside a captured HIP graph:
+ * psca_plan_create does all allocation and host-to-device copying (tiles,
+ * team lists, descriptors; synchronous); psca_plan_launch only enqueues two
+ * kernels (barrier reset, persistent batch), so it may be captured.  The
+ * problems' device buffers must stay valid while the plan is used; their
+ * contents are read at each launch.  team_size 0 = tuned or default.
+ * Inside a capture the batch kernel is recorded as an ordinary kernel node,
+ * which relies on its grid (at most the device's co-resident capacity) being
+ * resident at once; the bounded device-wide waits report PSCA_ESYNC if not. */
+typedef struct psca_plan psca_plan;
+int psca_plan_create(psca_ctx *ctx, int B, const psca_problem *problems, int team_size, psca_plan **plan);
+int psca_plan_launch(psca_plan *plan, void *stream);
+int psca_plan_team_size(const psca_plan *plan);
+int psca_plan_destroy(psca_plan *plan);   /* waits for the device; NULL is a no-op */
 
 /* Threshold module: support[n] = (x[n] >= theta) ? 1 : 0 (Sec. III-A). */
 int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *stream);

@@ -24,6 +24,7 @@ MAX_L = 96
 EXPORTED = (
     "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
     "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold", "psca_detect_batch",
+    "psca_autotune_batch", "psca_plan_create", "psca_plan_launch", "psca_plan_team_size", "psca_plan_destroy",
 )
 
 
@@ -90,6 +91,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "psca_iterate": ([vp, vp, vp, i32, i32, P, f32, vp, vp, vp, vp, vp, vp, vp], i32),
         "psca_threshold": ([vp, i32, f32, vp, vp], i32),
         "psca_detect_batch": ([vp, i32, ctypes.POINTER(PscaProblem), vp], i32),
+        "psca_autotune_batch": ([vp, i32, ctypes.POINTER(PscaProblem), i32, ctypes.POINTER(i32), vp], i32),
+        "psca_plan_create": ([vp, i32, ctypes.POINTER(PscaProblem), i32, ctypes.POINTER(vp)], i32),
+        "psca_plan_launch": ([vp, vp], i32),
+        "psca_plan_team_size": ([vp], i32),
+        "psca_plan_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

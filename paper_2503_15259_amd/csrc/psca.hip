@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <new>
+#include <unordered_map>
 #include <vector>
 #include <utility>
 
@@ -239,7 +240,8 @@ struct CoopArgs {
   const float *x_in;    // [N] initial iterate or null (zeros)
   float *x_out, *q_out, *r_out, *xt_out;
   int32_t *status;
-  float2 *partials;     // [G][NB * 256]
+  float2 *partials;     // [G][pstride], workgroup g's packed partial of Sigma at g * pstride
+  size_t pstride;       // >= NB * 256
   float2 *sigma;        // [NB * 256]
   GridBar bar;
 };
@@ -248,7 +250,8 @@ struct CoopArgs {
 __host__ __device__ inline size_t lds_bytes(int Lp, int NT, int waves) {
   const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
   const bool sh_lds = Lp <= 64;
-  const size_t f2 = 2 * (size_t)Lp * pt + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256;
+  const size_t f2 = (size_t)Lp * pt + (size_t)Lp * 17 + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) +
+                    (size_t)waves * 256;
   const size_t f4b = 3 * (size_t)NT + 2 * Lb * NT;   // floats
   return f2 * sizeof(float2) + f4b * 4;
 }
@@ -297,7 +300,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 template <int K>
 __device__ __forceinline__ float row_bcast(float v) {   // lane K of each 16-lane row
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + K, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + K, 0xf, 0xf, true));
 }
 
 // leaf_chol: one wavefront factors a 16x16 HPD block A = L L^H held in
@@ -425,8 +428,9 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   __shared__ int s_ok, s_pd[LPMAX / 16];
   const int NT = A.NT, PT = A.NT + 1;
   float2 *St = (float2 *)smem_raw;          // [Lp][PT]  S tile, row i at i * PT
-  float2 *Bt = St + Lp * PT;                // [Lp][PT]  B tile (also reduction scratch)
-  float2 *WS = Bt + Lp * PT;                // [Lp][P]   column-major: Cholesky columns, W, Sigma^-1
+  constexpr int kPB = 17;                   // pitch of the B tile
+  float2 *Bt = St + Lp * PT;                // [Lp][kPB] B tile of one 16-column block
+  float2 *WS = Bt + Lp * kPB;               // [Lp][P]   column-major: Cholesky factor, W, Sigma^-1
   float2 *ShL = WS + Lp * P;                // [Lp][P]   SigmaHat, column-major (kShLds)
   float2 *scr = ShL + (kShLds ? Lp * P : 0);// [kWaves][256] per-wave 16x16 scratch
   float *xs = (float *)(scr + kWaves * 256);   // [NT] iterate of the tile
@@ -478,7 +482,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     __syncthreads();
     {
       const float *wv = red_q;
-      float2 *dst = A.partials + (size_t)g * E;
+      float2 *dst = A.partials + (size_t)g * A.pstride;
 #pragma unroll
       for (int q = 0; q < kBlocksPerWave; ++q) {
         const int b = wave + kWaves * q;
@@ -520,17 +524,17 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           const int e = start + tid % cnt, part = tid / cnt;
           float2 acc = make_float2(0.f, 0.f);
           for (int h = part; h < A.G; h += Pp) {
-            const float2 v = A.partials[(size_t)h * E + e];
+            const float2 v = A.partials[(size_t)h * A.pstride + e];
             acc.x += v.x;
             acc.y += v.y;
           }
-          Bt[tid] = acc;
+          scr[tid] = acc;
         }
         __syncthreads();
         if (tid < cnt) {
           float2 sm = make_float2(0.f, 0.f);
           for (int part = 0; part < Pp; ++part) {
-            const float2 v = Bt[part * cnt + tid];
+            const float2 v = scr[part * cnt + tid];
             sm.x += v.x;
             sm.y += v.y;
           }
@@ -549,7 +553,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
         for (int e = start + tid; e < end; e += THREADS) {
           float2 sm = make_float2(0.f, 0.f);
           for (int h = 0; h < A.G; ++h) {
-            const float2 v = A.partials[(size_t)h * E + e];
+            const float2 v = A.partials[(size_t)h * A.pstride + e];
             sm.x += v.x;
             sm.y += v.y;
           }
@@ -691,12 +695,13 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     }
 
     // ===== C4. B = Sigma^-1 S_g and q;  D = SigmaHat B and r =================
+    // One 16-column block of the tile at a time, so the B tile is Lp x 16.
     PSCA_MARK(it, 7);
+    for (int cb = 0; cb < A.ncb; ++cb) {
 #pragma unroll
-    for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
-      const int I = wave + kWaves * rb;
-      if (I < Lb) {
-        for (int cb = 0; cb < A.ncb; ++cb) {
+      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+        const int I = wave + kWaves * rb;
+        if (I < Lb) {
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int K = 0; K < Lb; ++K)
@@ -704,29 +709,25 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           float qp = 0.0f;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * lq + v, j = 16 * cb + l16;
-            const float2 sv = St[i * PT + j];
+            const int i = 16 * I + 4 * lq + v;
+            const float2 sv = St[i * PT + 16 * cb + l16];
             qp += sv.x * cr[v] + sv.y * ci[v];
-            Bt[i * PT + j] = make_float2(cr[v], ci[v]);
+            Bt[i * kPB + l16] = make_float2(cr[v], ci[v]);
           }
           qp += __shfl_xor(qp, 16);
           qp += __shfl_xor(qp, 32);
           if (lq == 0) red_q[I * NT + 16 * cb + l16] = qp;
         }
       }
-    }
-    __syncthreads();
-    PSCA_MARK(it, 8);
+      __syncthreads();
 #pragma unroll
-    for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
-      const int I = wave + kWaves * rb;
-      if (I < Lb) {
-        for (int cb = 0; cb < A.ncb; ++cb) {
+      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+        const int I = wave + kWaves * rb;
+        if (I < Lb) {
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
           if constexpr (kShLds) {
 #pragma unroll
-            for (int K = 0; K < Lb; ++K)
-              cblock_mma_rm(ShL + 16 * I, P, Bt + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
+            for (int K = 0; K < Lb; ++K) cblock_mma_rm(ShL + 16 * I, P, Bt, kPB, 16 * K, l16, lq, cr, ci);
           } else {
 #pragma unroll
             for (int K = 0; K < Lb; ++K) {
@@ -735,7 +736,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
               for (int ks = 0; ks < 4; ++ks) {
                 const int i = 16 * I + l16, k = 16 * K + 4 * ks + lq;
                 a4[ks] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
-                b4[ks] = Bt[k * PT + 16 * cb + l16];
+                b4[ks] = Bt[k * kPB + l16];
               }
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
@@ -744,8 +745,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           float rp = 0.0f;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * lq + v, j = 16 * cb + l16;
-            const float2 bv = Bt[i * PT + j];
+            const float2 bv = Bt[(16 * I + 4 * lq + v) * kPB + l16];
             rp += bv.x * cr[v] + bv.y * ci[v];
           }
           rp += __shfl_xor(rp, 16);
@@ -753,8 +753,8 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           if (lq == 0) red_r[I * NT + 16 * cb + l16] = rp;
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
 
     // ===== C5. coordinate step and update ==================================
     PSCA_MARK(it, 9);
@@ -800,21 +800,31 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
   psca_body<LPMAX, THREADS>(A, blockIdx.x);
 }
 
-// Batch of independent detections in one cooperative launch: workgroup w
-// runs workgroup wg_map[w].y of instance wg_map[w].x, whose arguments are
-// descs[wg_map[w].x]; every instance synchronises on its own barrier words.
+// Batch of independent detections in one persistent launch.  The grid is
+// split into teams of T workgroups; team t runs the instances
+// lists[offsets[t] .. offsets[t+1]) one after the other, and workgroup g of
+// the team takes part in instance b iff g < descs[b].G.  Every instance
+// synchronises on its own barrier words, so team members that finish an
+// instance early simply wait at the next one's first barrier.
 constexpr int kBatchThreads = 512;
-__global__ void __launch_bounds__(kBatchThreads) k_psca_batch(const CoopArgs *__restrict__ descs,
-                                                              const int2 *__restrict__ wg_map) {
-  const int2 m = wg_map[blockIdx.x];
-  const CoopArgs A = descs[m.x];
-  switch ((A.L + 15) & ~15) {
-    case 16: psca_body<16, kBatchThreads>(A, m.y); break;
-    case 32: psca_body<32, kBatchThreads>(A, m.y); break;
-    case 48: psca_body<48, kBatchThreads>(A, m.y); break;
-    case 64: psca_body<64, kBatchThreads>(A, m.y); break;
-    case 80: psca_body<80, kBatchThreads>(A, m.y); break;
-    default: psca_body<96, kBatchThreads>(A, m.y); break;
+__global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__restrict__ descs,
+                                                              const int *__restrict__ lists,
+                                                              const int *__restrict__ offsets, int T) {
+  const int t = blockIdx.x / T, g = blockIdx.x - t * T;
+  const int i1 = offsets[t + 1];
+  for (int idx = offsets[t]; idx < i1; ++idx) {
+    const CoopArgs A = descs[lists[idx]];
+    if (g < A.G) {
+      switch ((A.L + 15) & ~15) {
+        case 16: psca_body<16, kBatchThreads>(A, g); break;
+        case 32: psca_body<32, kBatchThreads>(A, g); break;
+        case 48: psca_body<48, kBatchThreads>(A, g); break;
+        case 64: psca_body<64, kBatchThreads>(A, g); break;
+        case 80: psca_body<80, kBatchThreads>(A, g); break;
+        default: psca_body<96, kBatchThreads>(A, g); break;
+      }
+    }
+    __syncthreads();   // the next instance reuses the LDS
   }
 }
 
@@ -891,6 +901,7 @@ struct psca_ctx {
   size_t desc_bytes;
   hipEvent_t desc_done;   // the last copy out of hdesc
   bool desc_pending;
+  std::unordered_map<uint64_t, int> tuned;   // batch signature -> team size (psca_autotune_batch)
 };
 
 namespace {
@@ -1027,26 +1038,11 @@ size_t ws_bytes_of(int Lp, int G) {
          align_up((size_t)G * 16 * sizeof(unsigned)) + 3 * align_up(sizeof(unsigned));
 }
 
-// The smallest column tile whose workgroups all fit `cap` co-resident slots.
-int plan_instance(int L, int N, int threads, int cap, InstPlan &p) {
-  p.Lp = (L + 15) & ~15;
-  for (int ncb = 1; ncb <= kMaxNcb; ++ncb) {
-    const int NT = 16 * ncb, G = (N + NT - 1) / NT;
-    if (G > cap) continue;
-    p.ncb = ncb;
-    p.NT = NT;
-    p.G = G;
-    p.lds = lds_bytes(p.Lp, NT, threads / 64);
-    p.ws = ws_bytes_of(p.Lp, G);
-    return PSCA_OK;
-  }
-  return PSCA_ENOTSUP;
-}
-
 // Point the instance's work buffers into `base` (laid out as ws_bytes_of).
 void bind_ws(CoopArgs &a, char *base, const InstPlan &p) {
   const size_t E = (size_t)(p.Lp / 16) * (p.Lp / 16 + 1) / 2 * 256;
   size_t off = 0;
+  a.pstride = E;
   a.partials = (float2 *)(base + off); off += align_up((size_t)p.G * E * sizeof(float2));
   a.sigma = (float2 *)(base + off);    off += align_up(E * sizeof(float2));
   a.bar.arrive = (unsigned *)(base + off); off += align_up((size_t)p.G * 16 * sizeof(unsigned));
@@ -1148,7 +1144,222 @@ int stage_desc(psca_ctx *ctx, size_t bytes, char **host) {
   return PSCA_OK;
 }
 
+// ---- batches: persistent teams ---------------------------------------------
+constexpr size_t kMaxLds = 159 * 1024;   // dynamic LDS per workgroup (160 KB on gfx950, less the static part)
+
+struct BatchPlan {
+  int B = 0, T = 0, n_teams = 0;
+  size_t lds = 0;
+  std::vector<psca_problem> probs;
+  std::vector<InstPlan> ip;
+  std::vector<int> iters;        // per instance (capped while tuning)
+  std::vector<int> team_of;
+  std::vector<int> lists, offsets;
+  std::vector<size_t> ws_off;    // per instance: Sigma, barrier words, status
+  size_t part_off = 0, part_stride = 0;   // per team partials: T ranks of E_max entries
+  size_t E_max = 0;
+  size_t ws_bytes = 0;
+};
+
+size_t packed_entries(int Lp) { return (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256; }
+
+size_t inst_ws_bytes(int Lp, int G) {
+  return align_up(packed_entries(Lp) * sizeof(float2)) + align_up((size_t)G * 16 * sizeof(unsigned)) +
+         3 * align_up(sizeof(unsigned));
+}
+
+// Largest column tile (multiple of 16, at most 64) whose LDS fits a workgroup.
+int max_tile(int Lp) {
+  for (int ncb = kMaxNcb; ncb >= 1; --ncb)
+    if (lds_bytes(Lp, 16 * ncb, kBatchThreads / 64) <= kMaxLds) return 16 * ncb;
+  return 0;
+}
+
+// Smallest team size that can run every instance of the batch.
+int min_team(int B, const psca_problem *pr) {
+  int T0 = 1;
+  for (int b = 0; b < B; ++b) {
+    const int nt = max_tile((pr[b].L + 15) & ~15);
+    if (nt == 0) return -1;
+    T0 = std::max(T0, (pr[b].N + nt - 1) / nt);
+  }
+  return T0;
+}
+
+// Default team size: one team per instance, as large as useful, when the
+// batch fits the GPU at once; otherwise the smallest teams (most concurrency).
+int default_team(int B, const psca_problem *pr, int cap) {
+  const int T0 = min_team(B, pr);
+  if (T0 < 0 || T0 > cap) return -1;
+  if ((long long)B * T0 <= cap) {
+    int want = 1;
+    for (int b = 0; b < B; ++b) want = std::max(want, (pr[b].N + 15) / 16);
+    return std::max(T0, std::min(cap / B, want));
+  }
+  return T0;
+}
+
+// Plans a batch on teams of T workgroups: tiles, longest-first assignment of
+// instances to teams (the estimated cost of an iteration grows with the
+// pivot blocks and with the tile's MFMA work) and the workspace layout.
+// iters_cap >= 0 caps every instance's iteration count (tuning runs).
+int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &plan, int iters_cap) {
+  if (T < 1 || T > cap) return PSCA_EINVAL;
+  plan = BatchPlan();
+  plan.B = B;
+  plan.T = T;
+  plan.n_teams = std::max(1, std::min(cap / T, B));
+  plan.probs.assign(pr, pr + B);
+  plan.ip.resize(B);
+  plan.iters.resize(B);
+  std::vector<double> cost(B);
+  size_t E_max = 0;
+  for (int b = 0; b < B; ++b) {
+    InstPlan &q = plan.ip[b];
+    q.Lp = (pr[b].L + 15) & ~15;
+    const int per = (pr[b].N + T - 1) / T;
+    q.NT = std::max(16, (per + 15) & ~15);
+    if (q.NT > max_tile(q.Lp)) return PSCA_ENOTSUP;
+    q.ncb = q.NT / 16;
+    q.G = (pr[b].N + q.NT - 1) / q.NT;
+    q.lds = lds_bytes(q.Lp, q.NT, kBatchThreads / 64);
+    q.ws = inst_ws_bytes(q.Lp, q.G);
+    plan.lds = std::max(plan.lds, q.lds);
+    plan.iters[b] = iters_cap >= 0 ? std::min(pr[b].prm.iters, iters_cap) : pr[b].prm.iters;
+    const double Lb = q.Lp / 16;
+    cost[b] = (double)plan.iters[b] * (3.0 * Lb + 0.05 * q.ncb * Lb * Lb + 8.0);
+    E_max = std::max(E_max, packed_entries(q.Lp));
+  }
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<double> load(plan.n_teams, 0.0);
+  std::vector<std::vector<int>> team(plan.n_teams);
+  plan.team_of.resize(B);
+  for (int b : order) {
+    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    team[t].push_back(b);
+    plan.team_of[b] = t;
+    load[t] += cost[b];
+  }
+  plan.offsets.push_back(0);
+  for (int t = 0; t < plan.n_teams; ++t) {
+    for (int b : team[t]) plan.lists.push_back(b);
+    plan.offsets.push_back((int)plan.lists.size());
+  }
+  size_t off = 0;
+  plan.ws_off.resize(B);
+  for (int b = 0; b < B; ++b) {
+    plan.ws_off[b] = off;
+    off += plan.ip[b].ws;
+  }
+  plan.part_off = off;
+  plan.E_max = E_max;
+  plan.part_stride = align_up((size_t)T * E_max * sizeof(float2));
+  plan.ws_bytes = off + plan.part_stride * plan.n_teams;
+  return PSCA_OK;
+}
+
+// Descriptors of `plan` with its workspace at `base`.
+void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
+  for (int b = 0; b < plan.B; ++b) {
+    const psca_problem &q = plan.probs[b];
+    const InstPlan &ip = plan.ip[b];
+    CoopArgs a;
+    fill_args(a, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, plan.iters[b], -1.0f,
+              nullptr, q.x_out, nullptr, nullptr, nullptr, q.status, ip);
+    char *w = base + plan.ws_off[b];
+    a.sigma = (float2 *)w;                w += align_up(packed_entries(ip.Lp) * sizeof(float2));
+    a.bar.arrive = (unsigned *)w;         w += align_up((size_t)ip.G * 16 * sizeof(unsigned));
+    a.bar.release = (unsigned *)w;        w += align_up(sizeof(unsigned));
+    a.bar.abort_flag = (int32_t *)w;      w += align_up(sizeof(unsigned));
+    if (!a.status) a.status = (int32_t *)w;
+    // every rank of a team owns the same slot for all of the team's instances:
+    // a rank that sits out an instance may start the next one early
+    a.partials = (float2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
+    a.pstride = plan.E_max;
+    out[b] = a;
+  }
+}
+
+// Host image of a plan's device arrays: descriptors, lists, offsets.
+size_t batch_image_bytes(const BatchPlan &plan) {
+  return align_up(plan.B * sizeof(CoopArgs)) + align_up(plan.lists.size() * sizeof(int)) +
+         align_up(plan.offsets.size() * sizeof(int));
+}
+
+void write_batch_image(const BatchPlan &plan, char *ws_base, char *img) {
+  bind_batch(plan, ws_base, (CoopArgs *)img);
+  char *p = img + align_up(plan.B * sizeof(CoopArgs));
+  memcpy(p, plan.lists.data(), plan.lists.size() * sizeof(int));
+  p += align_up(plan.lists.size() * sizeof(int));
+  memcpy(p, plan.offsets.data(), plan.offsets.size() * sizeof(int));
+}
+
+// Launches a planned batch whose device image is at `dimg`.
+int launch_batch(const BatchPlan &plan, const char *dimg, hipStream_t st) {
+  const CoopArgs *descs = (const CoopArgs *)dimg;
+  const int *lists = (const int *)(dimg + align_up(plan.B * sizeof(CoopArgs)));
+  const int *offsets = (const int *)((const char *)lists + align_up(plan.lists.size() * sizeof(int)));
+  int T = plan.T;
+  hipLaunchKernelGGL(k_prepare_batch, dim3(plan.B), dim3(256), 0, st, descs);
+  int rc = launch_ok();
+  if (rc != PSCA_OK) return rc;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return PSCA_EHIP;
+  const dim3 grid(plan.n_teams * plan.T), block(kBatchThreads);
+  if (cs == hipStreamCaptureStatusActive) {
+    // graph capture: a plain kernel node; the grid fits the device at once
+    hipLaunchKernelGGL(k_psca_teams, grid, block, plan.lds, st, descs, lists, offsets, T);
+    return launch_ok();
+  }
+  void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&T};
+  if (hipLaunchCooperativeKernel((const void *)k_psca_teams, grid, block, args, (unsigned)plan.lds, st) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  return PSCA_OK;
+}
+
+int batch_capacity(psca_ctx *ctx) {
+  const KernelChoice kc{(const void *)k_psca_teams, kBatchThreads, 96};
+  return max_coresident(ctx, kc, kMaxLds);
+}
+
+uint64_t batch_signature(int B, const psca_problem *pr) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix((uint64_t)B);
+  for (int b = 0; b < B; ++b) {
+    mix((uint64_t)pr[b].L);
+    mix((uint64_t)pr[b].N);
+  }
+  return h;
+}
+
+int validate_batch(int B, const psca_problem *pr) {
+  if (B < 0 || (B > 0 && !pr)) return PSCA_EINVAL;
+  for (int b = 0; b < B; ++b) {
+    const psca_problem &q = pr[b];
+    if (!q.Sigma_hat || !q.S || !q.x_out) return PSCA_EINVAL;
+    const int rc = validate_params(&q.prm, q.L, q.N, true);
+    if (rc != PSCA_OK) return rc;
+  }
+  return PSCA_OK;
+}
+
 }  // namespace
+
+struct psca_plan {
+  int device;
+  BatchPlan plan;
+  void *ws;     // the plan's own workspace
+  void *dimg;   // descriptors, team lists and offsets on the device
+};
 
 extern "C" {
 
@@ -1271,111 +1482,157 @@ int psca_iterate(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, in
 }
 
 int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream) {
-  if (!ctx || B < 0 || (B > 0 && !problems)) return PSCA_EINVAL;
-  for (int b = 0; b < B; ++b) {
-    const psca_problem &q = problems[b];
-    if (!q.Sigma_hat || !q.S || !q.x_out) return PSCA_EINVAL;
-    const int rc = validate_params(&q.prm, q.L, q.N, true);
-    if (rc != PSCA_OK) return rc;
-  }
-  if (B == 0) return PSCA_OK;
+  if (!ctx) return PSCA_EINVAL;
+  int rc = validate_batch(B, problems);
+  if (rc != PSCA_OK || B == 0) return rc;
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return PSCA_EHIP;
   hipStream_t st = as_stream(stream);
-  const void *fn = (const void *)k_psca_batch;
-
-  // co-resident capacity at the largest LDS any instance needs, then plans
-  std::vector<InstPlan> plan(B);
-  size_t lds_max = 0;
-  int cap = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 0) {
-      for (int b = 0; b < B; ++b)
-        lds_max = std::max(lds_max, lds_bytes((problems[b].L + 15) & ~15, 16, kBatchThreads / 64));
-    }
-    const KernelChoice kc{fn, kBatchThreads, 96};
-    cap = max_coresident(ctx, kc, lds_max);
-    if (cap <= 0) return PSCA_ENOTSUP;
-    size_t need = 0;
-    for (int b = 0; b < B; ++b) {
-      const int rc = plan_instance(problems[b].L, problems[b].N, kBatchThreads, cap, plan[b]);
-      if (rc != PSCA_OK) return rc;
-      need = std::max(need, plan[b].lds);
-    }
-    if (need <= lds_max) break;
-    lds_max = need;
-  }
-
-  // rounds: instances ordered by size, packed first-fit into cap workgroups
-  std::vector<int> order(B);
-  for (int b = 0; b < B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return (size_t)plan[x].G * plan[x].Lp * plan[x].Lp > (size_t)plan[y].G * plan[y].Lp * plan[y].Lp;
-  });
-  std::vector<int> round_first, round_count, round_wgs;
-  std::vector<size_t> round_ws;
-  for (int k = 0; k < B; ++k) {
-    const InstPlan &pk = plan[order[k]];
-    if (round_first.empty() || round_wgs.back() + pk.G > cap) {
-      round_first.push_back(k);
-      round_count.push_back(0);
-      round_wgs.push_back(0);
-      round_ws.push_back(0);
-    }
-    round_count.back() += 1;
-    round_wgs.back() += pk.G;
-    round_ws.back() += pk.ws;
-  }
-  size_t ws_need = 0, wgs_total = 0;
-  for (size_t r = 0; r < round_first.size(); ++r) {
-    ws_need = std::max(ws_need, round_ws[r]);
-    wgs_total += round_wgs[r];
-  }
-  int rc = ensure_ws(ctx, ws_need);
-  if (rc != PSCA_OK) return rc;
-  const size_t desc_off = 0, map_off = align_up((size_t)B * sizeof(CoopArgs));
+  const int cap = batch_capacity(ctx);
+  if (cap <= 0) return PSCA_ENOTSUP;
+  const auto hit = ctx->tuned.find(batch_signature(B, problems));
+  const int T = (hit != ctx->tuned.end()) ? hit->second : default_team(B, problems, cap);
+  if (T < 0) return PSCA_ENOTSUP;
+  BatchPlan plan;
+  if ((rc = make_batch_plan(B, problems, T, cap, plan, -1)) != PSCA_OK) return rc;
+  if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) return rc;
+  const size_t bytes = batch_image_bytes(plan);
   char *host = nullptr;
-  if ((rc = stage_desc(ctx, map_off + wgs_total * sizeof(int2), &host)) != PSCA_OK) return rc;
-  CoopArgs *hd = (CoopArgs *)(host + desc_off);
-  int2 *hm = (int2 *)(host + map_off);
-  size_t map_pos = 0;
-  for (size_t r = 0; r < round_first.size(); ++r) {
-    size_t ws_pos = 0;
-    for (int j = 0; j < round_count[r]; ++j) {
-      const int k = round_first[r] + j, b = order[k];
-      const psca_problem &q = problems[b];
-      CoopArgs &a = hd[k];
-      fill_args(a, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, q.prm.iters, -1.0f,
-                nullptr, q.x_out, nullptr, nullptr, nullptr, q.status, plan[b]);
-      bind_ws(a, (char *)ctx->ws + ws_pos, plan[b]);
-      ws_pos += plan[b].ws;
-      for (int w = 0; w < plan[b].G; ++w) hm[map_pos++] = make_int2(j, w);
-    }
-  }
-  if (hipMemcpyAsync(ctx->ddesc, host, map_off + wgs_total * sizeof(int2), hipMemcpyHostToDevice, st) !=
-      hipSuccess) {
+  if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) return rc;
+  write_batch_image(plan, (char *)ctx->ws, host);
+  if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
     (void)hipGetLastError();
     return PSCA_EHIP;
   }
   if (hipEventRecord(ctx->desc_done, st) != hipSuccess) return PSCA_EHIP;
   ctx->desc_pending = true;
-  const CoopArgs *dd = (const CoopArgs *)((char *)ctx->ddesc + desc_off);
-  const int2 *dm = (const int2 *)((char *)ctx->ddesc + map_off);
-  map_pos = 0;
-  for (size_t r = 0; r < round_first.size(); ++r) {
-    const CoopArgs *descs = dd + round_first[r];
-    const int2 *wg_map = dm + map_pos;
-    hipLaunchKernelGGL(k_prepare_batch, dim3(round_count[r]), dim3(256), 0, st, descs);
-    if ((rc = launch_ok()) != PSCA_OK) return rc;
-    void *args[] = {(void *)&descs, (void *)&wg_map};
-    if (hipLaunchCooperativeKernel(fn, dim3(round_wgs[r]), dim3(kBatchThreads), args, (unsigned)lds_max, st) !=
-        hipSuccess) {
-      (void)hipGetLastError();
-      return PSCA_EHIP;
-    }
-    map_pos += round_wgs[r];
+  return launch_batch(plan, (const char *)ctx->ddesc, st);
+}
+
+int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int tune_iters, int *team_size,
+                        void *stream) {
+  if (!ctx || tune_iters < 1) return PSCA_EINVAL;
+  int rc = validate_batch(B, problems);
+  if (rc != PSCA_OK) return rc;
+  if (B == 0) return PSCA_EINVAL;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return PSCA_EHIP;
+  hipStream_t st = as_stream(stream);
+  const int cap = batch_capacity(ctx);
+  const int T0 = min_team(B, problems);
+  if (cap <= 0 || T0 < 0 || T0 > cap) return PSCA_ENOTSUP;
+  std::vector<int> cand = {T0, default_team(B, problems, cap)};
+  for (int t : {8, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+    if (t >= T0 && t <= cap) cand.push_back(t);
+  if ((long long)B * T0 <= cap) cand.push_back(cap / B);
+  std::sort(cand.begin(), cand.end());
+  cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return PSCA_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return PSCA_EHIP;
   }
+  int best = -1;
+  float best_ms = 0.0f;
+  for (int T : cand) {
+    if (T < T0) continue;
+    BatchPlan plan;
+    if (make_batch_plan(B, problems, T, cap, plan, tune_iters) != PSCA_OK) continue;
+    if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) break;
+    const size_t bytes = batch_image_bytes(plan);
+    char *host = nullptr;
+    if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) break;
+    write_batch_image(plan, (char *)ctx->ws, host);
+    if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(ctx->desc_done, st) != hipSuccess) {
+      rc = PSCA_EHIP;
+      break;
+    }
+    ctx->desc_pending = true;
+    float ms = 0.0f;
+    if ((rc = launch_batch(plan, (const char *)ctx->ddesc, st)) != PSCA_OK ||   // warm-up
+        hipEventRecord(e0, st) != hipSuccess || (rc = launch_batch(plan, (const char *)ctx->ddesc, st)) != PSCA_OK ||
+        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      if (rc == PSCA_OK) rc = PSCA_EHIP;
+      break;
+    }
+    if (best < 0 || ms < best_ms) {
+      best = T;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PSCA_OK) return rc;
+  if (best < 0) return PSCA_ENOTSUP;
+  ctx->tuned[batch_signature(B, problems)] = best;
+  if (team_size) *team_size = best;
   return PSCA_OK;
+}
+
+int psca_plan_create(psca_ctx *ctx, int B, const psca_problem *problems, int team_size, psca_plan **out) {
+  if (!ctx || !out || team_size < 0) return PSCA_EINVAL;
+  *out = nullptr;
+  int rc = validate_batch(B, problems);
+  if (rc != PSCA_OK) return rc;
+  if (B == 0) return PSCA_EINVAL;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return PSCA_EHIP;
+  const int cap = batch_capacity(ctx);
+  if (cap <= 0) return PSCA_ENOTSUP;
+  int T = team_size;
+  if (T == 0) {
+    const auto hit = ctx->tuned.find(batch_signature(B, problems));
+    T = (hit != ctx->tuned.end()) ? hit->second : default_team(B, problems, cap);
+  }
+  if (T < 0) return PSCA_ENOTSUP;
+  if (T < min_team(B, problems) || T > cap) return PSCA_EINVAL;
+  psca_plan *p = new (std::nothrow) psca_plan;
+  if (!p) return PSCA_ENOMEM;
+  p->device = ctx->device;
+  p->ws = p->dimg = nullptr;
+  if ((rc = make_batch_plan(B, problems, T, cap, p->plan, -1)) != PSCA_OK) {
+    delete p;
+    return rc;
+  }
+  const size_t bytes = batch_image_bytes(p->plan);
+  std::vector<char> img(bytes);
+  if (hipMalloc(&p->ws, p->plan.ws_bytes) != hipSuccess || hipMalloc(&p->dimg, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
+    return PSCA_ENOMEM;
+  }
+  write_batch_image(p->plan, (char *)p->ws, img.data());
+  if (hipMemcpy(p->dimg, img.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->ws);
+    (void)hipFree(p->dimg);
+    delete p;
+    return PSCA_EHIP;
+  }
+  *out = p;
+  return PSCA_OK;
+}
+
+int psca_plan_launch(psca_plan *plan, void *stream) {
+  if (!plan) return PSCA_EINVAL;
+  DeviceGuard guard(plan->device);
+  if (!guard.ok) return PSCA_EHIP;
+  return launch_batch(plan->plan, (const char *)plan->dimg, as_stream(stream));
+}
+
+int psca_plan_team_size(const psca_plan *plan) { return plan ? plan->plan.T : PSCA_EINVAL; }
+
+int psca_plan_destroy(psca_plan *plan) {
+  if (!plan) return PSCA_OK;
+  DeviceGuard guard(plan->device);
+  int rc = (hipDeviceSynchronize() == hipSuccess) ? PSCA_OK : PSCA_EHIP;
+  (void)hipFree(plan->ws);
+  (void)hipFree(plan->dimg);
+  delete plan;
+  return rc;
 }
 
 #ifdef PSCA_PHASE_TRACE

@@ -193,15 +193,11 @@ class Problem:
     status: Optional[torch.Tensor] = None
 
 
-def detect_batch(problems, ctx: Optional[Context] = None, stream=None):
-    """psca_detect_batch: independent detections in one launch.  Returns the
-    list of x vectors (each problem's `out`)."""
-    if not problems:
-        return []
-    ctx = ctx or default_context(problems[0].S.device)
+def _problem_array(problems, ctx):
+    """psca_problem[] for `problems`; allocates missing outputs.  Returns the
+    array, the output tensors and the tensors that must stay alive."""
     arr = (N.PscaProblem * len(problems))()
-    keep = []
-    outs = []
+    keep, outs = [], []
     for k, pb in enumerate(problems):
         _need(pb.S, torch.complex64, ctx.device, "S")
         _need(pb.Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
@@ -211,7 +207,9 @@ def detect_batch(problems, ctx: Optional[Context] = None, stream=None):
         if Sh.shape != (L, L):
             raise ValueError("Sigma_hat must be L x L")
         pb.params.check_tensors(ctx.device, n)
-        x = torch.empty(n, dtype=torch.float32, device=ctx.device) if pb.out is None else pb.out
+        if pb.out is None:
+            pb.out = torch.empty(n, dtype=torch.float32, device=ctx.device)
+        x = pb.out
         if x.numel() != n or x.dtype != torch.float32 or not x.is_contiguous():
             raise ValueError("out must be a contiguous float32 vector of length N")
         keep += [S, Sh]
@@ -223,9 +221,63 @@ def detect_batch(problems, ctx: Optional[Context] = None, stream=None):
         e.prm = pb.params.to_c()
         e.x_out = x.data_ptr()
         e.status = None if pb.status is None else pb.status.data_ptr()
+    return arr, outs, keep
+
+
+def detect_batch(problems, ctx: Optional[Context] = None, stream=None):
+    """psca_detect_batch: independent detections in one persistent launch.
+    Returns the list of x vectors (each problem's `out`)."""
+    if not problems:
+        return []
+    ctx = ctx or default_context(problems[0].S.device)
+    arr, outs, _keep = _problem_array(problems, ctx)
     N.check(ctx._lib.psca_detect_batch(ctx.handle, len(problems), arr, _stream(ctx.device, stream)),
             "psca_detect_batch")
     return outs
+
+
+def autotune_batch(problems, tune_iters: int = 4, ctx: Optional[Context] = None, stream=None) -> int:
+    """psca_autotune_batch: times the candidate team sizes for this batch and
+    remembers the fastest in the context.  Returns the chosen team size."""
+    ctx = ctx or default_context(problems[0].S.device)
+    arr, _outs, _keep = _problem_array(problems, ctx)
+    t = ctypes.c_int(0)
+    N.check(ctx._lib.psca_autotune_batch(ctx.handle, len(problems), arr, int(tune_iters), ctypes.byref(t),
+                                         _stream(ctx.device, stream)), "psca_autotune_batch")
+    return t.value
+
+
+class Plan:
+    """psca_plan: a batch planned once and launched many times (launches may be
+    captured into a CUDA/HIP graph).  Keep the problems' tensors alive."""
+
+    def __init__(self, problems, team_size: int = 0, ctx: Optional[Context] = None):
+        self.ctx = ctx or default_context(problems[0].S.device)
+        self.problems = problems
+        arr, self.outs, self._keep = _problem_array(problems, self.ctx)
+        h = ctypes.c_void_p()
+        N.check(self.ctx._lib.psca_plan_create(self.ctx.handle, len(problems), arr, int(team_size),
+                                               ctypes.byref(h)), "psca_plan_create")
+        self.handle = h
+
+    @property
+    def team_size(self) -> int:
+        return self.ctx._lib.psca_plan_team_size(self.handle)
+
+    def launch(self, stream=None):
+        N.check(self.ctx._lib.psca_plan_launch(self.handle, _stream(self.ctx.device, stream)), "psca_plan_launch")
+        return self.outs
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.ctx._lib.psca_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def iterate(Sigma_hat: torch.Tensor, S: torch.Tensor, x: torch.Tensor, rho: float, params: Params,

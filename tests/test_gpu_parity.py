@@ -201,7 +201,8 @@ def test_host_validation_errors(P):
 def test_batch_mixed_instances_match_oracle_and_single_calls(P):
     """psca_detect_batch over instances of different L, N, M, variant and
     iteration count: each result meets the oracle bar and agrees with the
-    same instance run alone."""
+    same instance run alone to the same bar (the batch may tile the devices
+    differently, which changes the summation order of Sigma)."""
     cases = [(O.ML_K, I.workload_instance("single", 0).fp32_inputs(), 40),
              (O.MAP_K, I.make_instance(5, 11, 300, 20, 16, 0.15).fp32_inputs(), 25),
              (O.ML_UD, I.make_instance(5, 12, 700, 96, 64, 0.1).fp32_inputs(), 20),
@@ -221,14 +222,14 @@ def test_batch_mixed_instances_match_oracle_and_single_calls(P):
         assert int(pb.status.item()) == 0
         got = x.cpu().numpy().astype(np.float64)
         assert_parity(got, ref, variant, "batch " + label(inst, variant, iters))
-        one = xs.cpu().numpy().astype(np.float64)
-        assert np.max(np.abs(got - one)) <= 1e-6 * max(1.0, np.max(np.abs(one)))
+        assert_parity(got, xs.cpu().numpy().astype(np.float64), variant, "batch vs single " + label(inst, variant, iters))
 
 
-def test_batch_larger_than_the_gpu_runs_in_rounds(P):
-    """Seven N=2000 instances need 7 x 125 workgroups, more than are
-    co-resident: the batch runs in successive launches, each result exact to
-    the oracle bar."""
+def test_batch_larger_than_the_gpu_shares_teams(P):
+    """Seven N=2000 instances at 16-column tiles would need 7 x 125
+    workgroups, more than are co-resident: the persistent launch gives them
+    smaller teams that work through several instances each, every result
+    to the oracle bar."""
     probs, refs, insts = [], [], []
     for k in range(7):
         inst = I.make_instance(5, 100 + k, 2000, 32, 64, 0.1).fp32_inputs()
@@ -256,3 +257,88 @@ def test_batch_validation_and_empty(P):
         P.detect_batch([P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, O.ML_UD, 5)),
                         P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=bad)])
     assert e.value.code == -1
+
+
+def _uneven_batch(P, count, iters, variant=O.ML_UD):
+    probs, refs, insts = [], [], []
+    for k in range(count):
+        inst = I.make_uneven_instance(I.WORKLOAD_IDS["uneven"], k).fp32_inputs()
+        prm = params_for(P, inst, variant, iters)
+        probs.append(P.Problem(Sigma_hat=P.sample_cov(c64(inst.Y)), S=c64(inst.S), params=prm,
+                               status=torch.full((1,), 7, dtype=torch.int32, device=dev())))
+        insts.append(inst)
+    for inst in insts:
+        refs.append(O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters))
+    return probs, refs, insts
+
+
+def test_uneven_batch_matches_oracle_for_every_team_size(P):
+    """Uneven batch (N ~ U{200..2000}, L in {32,48,64,96}, M in {64,128,256},
+    p ~ U[0.05, 0.2]) in one persistent launch, with the default team size and
+    with forced smallest and larger teams: every instance meets the oracle bar."""
+    probs, refs, insts = _uneven_batch(P, 12, 20)
+    print("[uneven batch 12 instances, ML-UD, 20 iterations]", flush=True)
+    outs = P.detect_batch(probs)
+    torch.cuda.synchronize()
+    results = {"default": [x.cpu().numpy().astype(np.float64) for x in outs]}
+    for pb in probs:
+        assert int(pb.status.item()) == 0
+    for T in (32, 80):
+        for pb in probs:
+            pb.out = None
+        plan = P.Plan(probs, team_size=T)
+        assert plan.team_size == T
+        print(f"[uneven batch, team size {T}]", flush=True)
+        outs = plan.launch()
+        torch.cuda.synchronize()
+        results[T] = [x.cpu().numpy().astype(np.float64) for x in outs]
+        plan.close()
+    for key, xs in results.items():
+        for inst, x, ref in zip(insts, xs, refs):
+            assert_parity(x, ref, O.ML_UD, f"team={key} " + label(inst, O.ML_UD, 20))
+
+
+def test_plan_replays_inside_a_captured_graph(P):
+    """A planned batch captured into a graph and replayed three times, with
+    eager work and synchronisation between replays: every replay reproduces
+    the eager launch exactly."""
+    probs, refs, insts = _uneven_batch(P, 6, 15)
+    plan = P.Plan(probs)
+    eager = [x.clone() for x in plan.launch()]
+    torch.cuda.synchronize()
+    for inst, x, ref in zip(insts, eager, refs):
+        assert_parity(x.cpu().numpy().astype(np.float64), ref, O.ML_UD, "eager plan " + label(inst, O.ML_UD, 15))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    print("[capture plan launch]", flush=True)
+    with torch.cuda.graph(graph):
+        plan.launch()
+    for rep in range(3):
+        for x in plan.outs:
+            x.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for x, e in zip(plan.outs, eager):
+            assert torch.equal(x, e), f"replay {rep}"
+        for pb in probs:
+            assert int(pb.status.item()) == 0
+    del graph
+    plan.close()
+
+
+def test_autotuner_choice_is_used_and_exact(P):
+    probs, refs, insts = _uneven_batch(P, 5, 12)
+    T = P.autotune_batch(probs, tune_iters=2)
+    assert 1 <= T <= 256
+    for pb in probs:
+        pb.out = None
+    outs = P.detect_batch(probs)
+    torch.cuda.synchronize()
+    for inst, x, ref in zip(insts, outs, refs):
+        assert_parity(x.cpu().numpy().astype(np.float64), ref, O.ML_UD, f"tuned T={T} " + label(inst, O.ML_UD, 12))
