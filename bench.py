@@ -177,12 +177,13 @@ def run_uneven(args):
     ctx = P.Context(0)
     Shs = [P.sample_cov(Y, ctx=ctx) for Y in Ys]
     B = args.instances
+    status = torch.zeros(B, dtype=torch.int32, device=dev)
     probs = []
     for b in range(B):
         k = b % UNEVEN_POOL
         inst = pool_insts[k]
         prm = P.Params(variant=P.ML_UD, iters=UNEVEN_ITERS, sigma2=inst.sigma2, M=inst.M)
-        probs.append(P.Problem(Sigma_hat=Shs[k], S=Ss[k], params=prm))
+        probs.append(P.Problem(Sigma_hat=Shs[k], S=Ss[k], params=prm, status=status[b:b + 1]))
     tuned = P.autotune_batch(probs, tune_iters=4, ctx=ctx) if args.autotune else None
     plan = P.Plan(probs, ctx=ctx)
     stream = torch.cuda.current_stream(dev)
@@ -200,6 +201,8 @@ def run_uneven(args):
     launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
     ms = float(launch_ms.mean())
     value = B / (ms / 1e3)
+    st = status.cpu().numpy()
+    failed = {int(c): int((st == c).sum()) for c in np.unique(st) if c != 0}
     flops = sum(UNEVEN_ITERS * iteration_flops(pool_insts[b % UNEVEN_POOL].N, pool_insts[b % UNEVEN_POOL].L)
                 for b in range(B))
     achieved = flops / (ms / 1e3) / 1e12
@@ -233,6 +236,7 @@ def run_uneven(args):
                    "instances": B, "team_size": plan.team_size, "autotuned": tuned is not None,
                    "mean_N": float(np.mean(Ns)), "L_mix": {str(l): Ls.count(l) for l in sorted(set(Ls))}},
         "parity_vs_oracle": parity,
+        "device_status_failures": failed,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
                      "kernel": "k_psca_teams (whole batch)", "flops_per_launch": flops,

@@ -803,9 +803,8 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
 // Batch of independent detections in one persistent launch.  The grid is
 // split into teams of T workgroups; team t runs the instances
 // lists[offsets[t] .. offsets[t+1]) one after the other, and workgroup g of
-// the team takes part in instance b iff g < descs[b].G.  Every instance
-// synchronises on its own barrier words, so team members that finish an
-// instance early simply wait at the next one's first barrier.
+// the team takes part in instance b iff g < descs[b].G (the planner sets
+// G = T).  Every instance synchronises on its own barrier words.
 constexpr int kBatchThreads = 512;
 __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__restrict__ descs,
                                                               const int *__restrict__ lists,
@@ -1221,7 +1220,10 @@ int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
     q.NT = std::max(16, (per + 15) & ~15);
     if (q.NT > max_tile(q.Lp)) return PSCA_ENOTSUP;
     q.ncb = q.NT / 16;
-    q.G = (pr[b].N + q.NT - 1) / q.NT;
+    // every member of the team takes part (tiles past N are empty), so a
+    // team moves through its list in step and no member waits at an
+    // instance for team mates still busy with earlier ones
+    q.G = T;
     q.lds = lds_bytes(q.Lp, q.NT, kBatchThreads / 64);
     q.ws = inst_ws_bytes(q.Lp, q.G);
     plan.lds = std::max(plan.lds, q.lds);

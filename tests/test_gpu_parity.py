@@ -342,3 +342,19 @@ def test_autotuner_choice_is_used_and_exact(P):
     torch.cuda.synchronize()
     for inst, x, ref in zip(insts, outs, refs):
         assert_parity(x.cpu().numpy().astype(np.float64), ref, O.ML_UD, f"tuned T={T} " + label(inst, O.ML_UD, 12))
+
+
+def test_long_team_lists_finish_without_barrier_timeouts(P):
+    """Forty uneven instances on 32-workgroup teams (each team works through
+    several instances of different sizes in one launch): every instance
+    reports OK and meets the oracle bar."""
+    probs, refs, insts = _uneven_batch(P, 40, 10)
+    plan = P.Plan(probs, team_size=32)
+    print("[40 uneven instances on teams of 32]", flush=True)
+    outs = plan.launch()
+    torch.cuda.synchronize()
+    for pb in probs:
+        assert int(pb.status.item()) == 0
+    for inst, x, ref in zip(insts, outs, refs):
+        assert_parity(x.cpu().numpy().astype(np.float64), ref, O.ML_UD, "team lists " + label(inst, O.ML_UD, 10))
+    plan.close()
