@@ -34,12 +34,12 @@ POOL = 8           # distinct instances resident on the GPU
 EPS = 0.01         # MAP-UR Hermite width (noise-normalised units)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per k_psca launch from the FETCH_SIZE and WRITE_SIZE counter
-# passes, each scaled by the copy-kernel calibration (null when the kernel
-# changed after the counters were taken).
-# Measured for k_psca<64, 256> at N=1000, L=64, 100 iterations (profile
-# k_psca_single_N1000_L64_traffic.md): 172.4 MB fetched + 134.8 MB written.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# HBM bytes per k_psca_teams launch of the default workload (four detections,
+# teams of 32 workgroups) from the FETCH_SIZE and WRITE_SIZE counter passes,
+# each scaled by the copy-kernel calibration (profile
+# k_psca_teams_single_N1000_L64_x4_traffic.md): 318.4 MB fetched + 315.2 MB
+# written.  Keyed by team size; other team sizes report null.
+TRAFFIC_BYTES_PER_LAUNCH = {32: 633660321}
 
 
 def iteration_flops(N, L):
@@ -184,8 +184,8 @@ def run_uneven(args):
         inst = pool_insts[k]
         prm = P.Params(variant=P.ML_UD, iters=UNEVEN_ITERS, sigma2=inst.sigma2, M=inst.M)
         probs.append(P.Problem(Sigma_hat=Shs[k], S=Ss[k], params=prm, status=status[b:b + 1]))
-    tuned = P.autotune_batch(probs, tune_iters=4, ctx=ctx) if args.autotune else None
-    plan = P.Plan(probs, ctx=ctx)
+    tuned = P.autotune_batch(probs, tune_iters=4, ctx=ctx) if (args.autotune and args.team_size == 0) else None
+    plan = P.Plan(probs, team_size=args.team_size, ctx=ctx)
     stream = torch.cuda.current_stream(dev)
     for _ in range(args.warmup):
         plan.launch()
@@ -264,7 +264,10 @@ def main():
                     help="single: the four estimators on N=1000, L=64 (default); uneven: a batch of "
                          "independent ML-UD instances of mixed sizes in one persistent launch")
     ap.add_argument("--instances", type=int, default=4096, help="uneven workload: instances per batch")
-    ap.add_argument("--autotune", action="store_true", help="uneven workload: autotune the team size first")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the team-size autotuner that runs before timing")
+    ap.add_argument("--team-size", type=int, default=0,
+                    help="workgroups per instance team (0: autotuned, or the library default with --no-autotune)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -319,18 +322,28 @@ def main():
     ctx = P.Context(0)
     stream = torch.cuda.current_stream(dev)
 
+    # the step's batches: step s detects instance (4s + v) % POOL with
+    # estimator v, so two problem sets alternate; each is planned once
+    def problems_of(s):
+        return [P.Problem(Sigma_hat=shs[v], S=Ss[(4 * s + v) % POOL], params=params[(4 * s + v) % POOL][v],
+                          out=outs[(4 * s + v) % POOL][v], status=status[v:v + 1]) for v in range(4)]
+
+    for v in range(4):
+        P.sample_cov(Ys[v], ctx=ctx, out=shs[v])
+    tuned = None
+    team = args.team_size
+    if team == 0 and args.autotune:   # outside the timed region
+        tuned = team = P.autotune_batch(problems_of(0), tune_iters=10, ctx=ctx)
+    plans = [P.Plan(problems_of(s), team_size=team, ctx=ctx) for s in range(2)]
+
     def one_step(s, events=None):
-        """Four detections, one per estimator, in one batched launch: SigmaHat
-        from Y for each, then Algorithm 1 for all four concurrently."""
-        probs = []
+        """Four detections, one per estimator, in one persistent launch:
+        SigmaHat from Y for each, then Algorithm 1 for all four concurrently."""
         for v in range(4):
-            i = (4 * s + v) % POOL
-            P.sample_cov(Ys[i], ctx=ctx, out=shs[v])
-            probs.append(P.Problem(Sigma_hat=shs[v], S=Ss[i], params=params[i][v], out=outs[i][v],
-                                   status=status[v:v + 1]))
+            P.sample_cov(Ys[(4 * s + v) % POOL], ctx=ctx, out=shs[v])
         if events is not None:
             events[0].record(stream)
-        P.detect_batch(probs, ctx=ctx)
+        plans[s % 2].launch()
         if events is not None:
             events[1].record(stream)
 
@@ -412,9 +425,8 @@ def main():
             parity[VARIANT_NAMES[v]] = {key: worst, "instances_compared": compared,
                                         "input_sensitive": sensitive}
 
-    # dominant kernel: k_psca_batch, one launch per step running the four
-    # detections (the events bracket it, its barrier-reset kernel and the
-    # 1 KB descriptor copy)
+    # dominant kernel: k_psca_teams, one launch per step running the four
+    # detections (the events bracket it and its barrier-reset kernel)
     flops = 4 * iters * iteration_flops(N, L)
     avg_launch_s = float(launch_ms.mean()) / 1e3
     achieved = flops / avg_launch_s / 1e12
@@ -424,8 +436,8 @@ def main():
         "peak": PEAK_FP32_MFMA_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6),
-        "traffic": TRAFFIC_BYTES_PER_LAUNCH,
-        "kernel": "k_psca_batch (4 concurrent detections, %d iterations each)" % iters,
+        "traffic": TRAFFIC_BYTES_PER_LAUNCH.get(plans[0].team_size),
+        "kernel": "k_psca_teams (4 concurrent detections, %d iterations each)" % iters,
         "flops_per_launch": flops,
         "avg_launch_ms": round(avg_launch_s * 1e3, 4),
         "algorithmic_bytes_per_launch": 4 * launch_bytes(N, L),
@@ -448,7 +460,8 @@ def main():
             "workload": f"single-instance PSCA detection N={N} L={L} M={M}, {iters} iterations, "
                         "one instance per estimator (ML-K, MAP-K, ML-UD, MAP-UR) per step",
             "N": N, "L": L, "M": M, "p": w["p"], "iters": iters, "instances_per_step": 4,
-            "eps_map_ur": EPS, "pool": POOL,
+            "eps_map_ur": EPS, "pool": POOL, "team_size": plans[0].team_size,
+            "team_size_autotuned": tuned is not None,
         },
         "equal_error": eer,
         "parity_vs_oracle": parity,
@@ -457,6 +470,8 @@ def main():
         "wall_s": round(wall, 3),
     }
     print(json.dumps(line), flush=True)
+    for pl in plans:
+        pl.close()
 
 
 if __name__ == "__main__":
