@@ -141,6 +141,14 @@ class PowerLawPrior:
         """Derivative of the continuous part (fourth case of eq. pepsd)."""
         return -2.0 * self.p / self.D * (self.dpsi(x) ** 2 + self.psi(x) * self.ddpsi(x))
 
+    def ddp_upsilon_cont(self, x):
+        """Second derivative of the continuous part (needs the third
+        derivative of psi for the power law)."""
+        b = 1.0 / self.beta
+        psi = self.psi(x)
+        d3 = -b * (b + 1.0) * (b + 2.0) * psi / x ** 3
+        return -2.0 * self.p / self.D * (3.0 * self.dpsi(x) * self.ddpsi(x) + psi * d3)
+
     def H1(self, x):
         e = self.eps
         return (1.0 - self.p) * (1.0 + 2.0 * x / e) * ((x - e) / e) ** 2
@@ -148,6 +156,10 @@ class PowerLawPrior:
     def dH1(self, x):
         e = self.eps
         return 6.0 * (1.0 - self.p) / e ** 3 * x * (x - e)
+
+    def ddH1(self, x):
+        e = self.eps
+        return 6.0 * (1.0 - self.p) / e ** 3 * (2.0 * x - e)
 
     def _AB(self):
         gl = self.g_l
@@ -168,6 +180,12 @@ class PowerLawPrior:
         e = self.eps
         u = x - self.g_l
         return -6.0 * A / e ** 3 * u * (u + e) + B / e ** 2 * (u + e) * (3.0 * u + e)
+
+    def ddH2(self, x):
+        A, B = self._AB()
+        e = self.eps
+        u = x - self.g_l
+        return -6.0 * A / e ** 3 * (2.0 * u + e) + B / e ** 2 * (6.0 * u + 4.0 * e)
 
     def branch(self, x) -> int:
         """Which piece of eq. peps holds x: 0 H1, 1 gap, 2 H2, 3 density."""
@@ -200,6 +218,24 @@ class PowerLawPrior:
         if b == 2:
             return self.dH2(x)
         return self.dp_upsilon_cont(x)
+
+    def ddp_eps(self, x):
+        b = self.branch(x)
+        if b == 0:
+            return self.ddH1(x)
+        if b == 1:
+            return 0.0
+        if b == 2:
+            return self.ddH2(x)
+        return self.ddp_upsilon_cont(x)
+
+    def dlog_ratio(self, x):
+        """Derivative of p^eps'/p^eps: (p'' p - p'^2) / p^2; 0 in the gap."""
+        pe = self.p_eps(x)
+        if pe == 0.0:
+            return 0.0
+        d1 = self.dp_eps(x)
+        return (self.ddp_eps(x) * pe - d1 * d1) / (pe * pe)
 
     def log_ratio(self, x):
         """p^eps'(x) / p^eps(x), the prior term of eq. gradient_MAP_U;
@@ -434,3 +470,88 @@ def branch_margin(prob: Problem, hist) -> np.ndarray:
             d = np.min(np.abs(arr[:, None] - pts[None, :]) / pts[None, :], axis=1)
             m = np.minimum(m, d)
     return m
+
+
+# ---------------------------------------------------------------------------
+# The unrolled network (PSCA-Net, Sec. III-A / IV-A "-Net" subsections): K
+# layers, layer k is one iteration of Algorithm 1 with its own step size
+# rho_k; loss: binary cross-entropy of the last iterate (eqs. Loss_alpha,
+# Loss_gamma).  Gradients by the chain rule, written out per layer.
+# ---------------------------------------------------------------------------
+
+def net_forward(prob: Problem, rhos) -> list:
+    """x^(0) = 0, ..., x^(K): the iterates of the unrolled network."""
+    xs = [np.zeros(prob.N)]
+    for rho in rhos:
+        xs.append(psca_iteration(prob, xs[-1], float(rho)).x_next)
+    return xs
+
+
+def layer_vjp(prob: Problem, x: np.ndarray, rho: float, v: np.ndarray):
+    """Vector-Jacobian product of one layer x' = (1 - rho) x + rho x~(x):
+    returns (dL/dx, dL/drho) given v = dL/dx'.
+
+    With kappa = g (known pathloss) or 1, grad = kappa (q - r) - c(x) (c the
+    prior term, c' its derivative), curv = (kappa q)^2, pre = x - grad/curv,
+    x~ = clip(pre, lo, hi) and mask = [lo <= pre <= hi]:
+      d pre/dq = (2 grad - kappa q) / (kappa^2 q^3),  d pre/dr = 1 / (kappa q^2),
+      d pre/dx_n (own) = 1 + c'(x_n) / curv_n,
+    and, from d Sigma^-1 = -Sigma^-1 s_m s_m^H Sigma^-1 d w_m with w = kappa x,
+      dq_n/dx_m = -kappa_m |s_n^H Sigma^-1 s_m|^2,
+      dr_n/dx_m = -2 kappa_m Re[(s_n^H Sigma^-1 s_m)(s_m^H Sigma^-1 SigmaHat Sigma^-1 s_n)]."""
+    N = prob.N
+    known = prob.variant in KNOWN_PATHLOSS
+    kappa = prob.g if known else np.ones(N)
+    Sigma = model_covariance(prob.S, prob.weights(x), prob.sigma2)
+    Si = np.linalg.inv(Sigma)
+    q, r = quadratic_forms(prob.S, Si, prob.Sigma_hat)
+    grad, curv = gradient_and_curvature(prob, x, q, r)
+    lo, hi = prob.bounds()
+    pre = x - grad / curv
+    xt = np.minimum(np.maximum(pre, lo), hi)
+    mask = ((pre >= lo) & (pre <= hi)).astype(np.float64)
+    dpre_dq = (2.0 * grad - kappa * q) / (kappa ** 2 * q ** 3)
+    dpre_dr = 1.0 / (kappa * q ** 2)
+    if prob.variant == MAP_UR:
+        cprime = np.array([prob.prior.dlog_ratio(float(xn)) for xn in x]) / prob.M
+    else:
+        cprime = np.zeros(N)
+    own = 1.0 + cprime / curv
+    d_rho = float(np.sum(v * (xt - x)))
+    a = rho * v * mask * dpre_dq
+    b = rho * v * mask * dpre_dr
+    Bm = Si @ prob.S                                  # columns Sigma^-1 s_m
+    Cm = Si @ prob.Sigma_hat @ Bm                     # columns Sigma^-1 SigmaHat Sigma^-1 s_m
+    P = prob.S.conj().T @ Bm                          # P[n, m] = s_n^H Sigma^-1 s_m
+    R = prob.S.conj().T @ Cm                          # R[n, m] = s_n^H Sigma^-1 SigmaHat Sigma^-1 s_m
+    dq = -(np.abs(P) ** 2) * kappa[None, :]           # dq_n/dx_m
+    dr = -2.0 * np.real(P * R.conj()) * kappa[None, :]  # dr_n/dx_m
+    dx = v * (1.0 - rho) + rho * v * mask * own + a @ dq + b @ dr
+    return dx, d_rho
+
+
+def bce_loss(prob: Problem, x: np.ndarray, alpha: np.ndarray, g: np.ndarray, clamp: float = 1e-7):
+    """Binary cross-entropy of the detector output against the true activity
+    (eq. Loss_alpha on alpha~; eq. Loss_gamma on gamma~/g), averaged over
+    devices; the argument is clamped to [clamp, 1 - clamp] (the logarithms
+    are undefined at 0 and 1).  Returns (loss, dloss/dx)."""
+    known = prob.variant in KNOWN_PATHLOSS
+    z = x if known else x / g
+    zc = np.clip(z, clamp, 1.0 - clamp)
+    N = x.shape[0]
+    loss = -np.mean(alpha * np.log(zc) + (1.0 - alpha) * np.log(1.0 - zc))
+    inside = ((z >= clamp) & (z <= 1.0 - clamp)).astype(np.float64)
+    dz = -(alpha / zc - (1.0 - alpha) / (1.0 - zc)) / N * inside
+    dx = dz if known else dz / g
+    return float(loss), dx
+
+
+def net_loss_and_grad(prob: Problem, rhos, alpha: np.ndarray, g: np.ndarray):
+    """Loss of the unrolled network and its gradient with respect to every
+    step size, by reverse accumulation through layer_vjp."""
+    xs = net_forward(prob, rhos)
+    loss, v = bce_loss(prob, xs[-1], alpha, g)
+    d_rhos = np.zeros(len(rhos))
+    for k in range(len(rhos) - 1, -1, -1):
+        v, d_rhos[k] = layer_vjp(prob, xs[k], float(rhos[k]), v)
+    return loss, d_rhos
