@@ -416,6 +416,229 @@ __device__ __forceinline__ void chol_trail(float2 *WS, int P, int J, int I, int 
   for (int v = 0; v < 4; ++v) dst[v] = make_float2(cr[v], ci[v]);
 }
 
+// ---------------------------------------------------------------------------
+// Phases shared by the forward and the backward bodies
+// ---------------------------------------------------------------------------
+// Packed lower blocks of the tile's Gram matrix S_t diag(wv) S_t^H (MFMA,
+// complex product on the real 4-product split) into dst.  St: [Lp][PT] S tile.
+template <int LP, int THREADS>
+__device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, const float *wv, float2 *dst) {
+  constexpr int kWaves = THREADS / 64, Lb = LP / 16, NB = Lb * (Lb + 1) / 2;
+  constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < kBlocksPerWave; ++q) {
+    const int b = wave + kWaves * q;
+    if (b < NB) {
+      int I, J;
+      blk_coords(b, I, J);
+      f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+      for (int cb = 0; cb < ncb; ++cb) {
+        float2 av4[4], bv4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int c = 16 * cb + 4 * ks + lq;
+          const float2 s = St[(16 * J + l16) * PT + c];
+          const float w = wv[c];
+          av4[ks] = St[(16 * I + l16) * PT + c];
+          bv4[ks] = make_float2(w * s.x, -w * s.y);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(av4[ks], bv4[ks], cr, ci);
+      }
+      float4 *o = (float4 *)(dst + b * 256 + l16 * 16 + 4 * lq);
+      o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
+      o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
+    }
+  }
+}
+
+__device__ __forceinline__ void store_reduced(float2 *out, int e, float2 sm, bool add_diag, int L, float sigma2) {
+  if (add_diag) {
+    const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+    int I, J;
+    blk_coords(b, I, J);
+    if (I == J && ii == jj) {
+      const int i = 16 * I + ii;
+      sm.x += (i < L) ? sigma2 : 1.0f;
+      sm.y = 0.0f;
+    }
+  }
+  out[e] = sm;
+}
+
+// Workgroup g's 1/G slice of the sum over the G packed partials (rank h at
+// partials + h * pstride) into out; with add_diag, sigma2 is added to the
+// diagonal of rows < L and 1 to padded rows (isolated unit pivots), and the
+// diagonal is made real.  scr: THREADS float2 of LDS.
+template <int LP, int THREADS>
+__device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstride, int G, int g, float2 *out,
+                                             float2 *scr, bool add_diag, int L, float sigma2) {
+  constexpr int Lb = LP / 16, E = Lb * (Lb + 1) / 2 * 256;
+  const int tid = threadIdx.x;
+  const int per = (E + G - 1) / G;
+  const int start = g * per, end = min(E, start + per);
+  const int cnt = max(0, end - start);
+  if (cnt > 0 && cnt <= THREADS) {
+    const int Pp = THREADS / cnt;   // threads per element
+    if (tid < cnt * Pp) {
+      const int e = start + tid % cnt, part = tid / cnt;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int h = part; h < G; h += Pp) {
+        const float2 v = partials[(size_t)h * pstride + e];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      scr[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < cnt) {
+      float2 sm = make_float2(0.f, 0.f);
+      for (int part = 0; part < Pp; ++part) {
+        const float2 v = scr[part * cnt + tid];
+        sm.x += v.x;
+        sm.y += v.y;
+      }
+      store_reduced(out, start + tid, sm, add_diag, L, sigma2);
+    }
+  } else {
+    for (int e = start + tid; e < end; e += THREADS) {
+      float2 sm = make_float2(0.f, 0.f);
+      for (int h = 0; h < G; ++h) {
+        const float2 v = partials[(size_t)h * pstride + e];
+        sm.x += v.x;
+        sm.y += v.y;
+      }
+      store_reduced(out, e, sm, add_diag, L, sigma2);
+    }
+  }
+}
+
+// Sigma^-1 of the packed HPD matrix `sigma`, full and exactly Hermitian,
+// column-major with pitch Lp + 1 in WS.  Returns false (uniformly across
+// the workgroups of an instance) if a pivot is not positive and finite.
+// scr: per-wavefront 16x16 staging; s_pd: Lp / 16 ints of LDS.
+template <int LP, int THREADS>
+__device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, float2 *scr, int *s_pd, int it) {
+  constexpr int kWaves = THREADS / 64, Lb = LP / 16, NB = Lb * (Lb + 1) / 2, P = LP + 1, E = NB * 256;
+  constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lq = lane >> 4;
+  (void)it;
+  // C1. Blocked Cholesky Sigma = L L^H with the diagonal blocks of W = L^-1.
+  // Block step J: wavefront 0 has factored diagonal block J in registers
+  // and left W_JJ in its place; the panel L_IJ = A_IJ W_JJ^H follows on
+  // MFMA, then the trailing updates A_IK -= L_IJ L_KJ^H, during which
+  // wavefront 0 updates block J+1 first and factors it.
+  for (int e = tid; e < E; e += THREADS) {
+    const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+    int I, J;
+    blk_coords(b, I, J);
+    WS[(16 * J + jj) * P + 16 * I + ii] = sigma[e];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const bool ok = leaf_chol(WS, P, lane);
+    if (lane == 0) s_pd[0] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  for (int J = 0; J < Lb; ++J) {
+    PSCA_SUB_MARK(it, J, 0);
+    if (!s_pd[J]) return false;   // uniform: every workgroup factors the same Sigma
+    if (J + 1 == Lb) break;
+    for (int I = J + 1 + wave; I < Lb; I += kWaves) chol_panel(WS, P, J, I, l16, lq);
+    __syncthreads();
+    PSCA_SUB_MARK(it, J, 1);
+    if (wave == 0) {
+      chol_trail(WS, P, J, J + 1, J + 1, l16, lq);
+      wave_lds_sync();
+      const bool ok = leaf_chol(WS + 16 * (J + 1) * P + 16 * (J + 1), P, lane);
+      if (lane == 0) s_pd[J + 1] = ok ? 1 : 0;
+    } else {
+      int q = 0;
+      for (int I = J + 2; I < Lb; ++I)
+        for (int K = J + 1; K <= I; ++K)
+          if (q++ % (kWaves - 1) == wave - 1) chol_trail(WS, P, J, I, K, l16, lq);
+    }
+    __syncthreads();
+  }
+  PSCA_MARK(it, 5);
+  // C2. Off-diagonal blocks of W, right to left:
+  // W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ, written over L_IJ.
+  for (int J = Lb - 2; J >= 0; --J) {
+    f4 rr = {0.f, 0.f, 0.f, 0.f}, ri = {0.f, 0.f, 0.f, 0.f};
+    const int I = J + 1 + wave;
+    if (I < Lb) {
+      f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
+      for (int K = J + 1; K <= I; ++K)
+        cblock_mma(WS + (16 * K) * P + 16 * I, WS + (16 * J) * P + 16 * K, P, l16, lq, tr, ti);
+      float2 *T = scr + wave * 256;          // column-major, pitch 16
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
+      wave_lds_sync();
+      float2 ta[4], wb[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        ta[ks] = T[(4 * ks + lq) * 16 + l16];
+        wb[ks] = WS[(16 * J + l16) * P + 16 * J + 4 * ks + lq];
+      }
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) cmfma(ta[ks], wb[ks], rr, ri);
+    }
+    __syncthreads();
+    if (I < Lb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) WS[(16 * J + l16) * P + 16 * I + 4 * lq + v] = make_float2(-rr[v], -ri[v]);
+    }
+    __syncthreads();
+  }
+  // C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS.
+  PSCA_MARK(it, 6);
+  f4 sir[kBlocksPerWave], sii[kBlocksPerWave];
+#pragma unroll
+  for (int q = 0; q < kBlocksPerWave; ++q) {
+    sir[q] = (f4){0.f, 0.f, 0.f, 0.f};
+    sii[q] = (f4){0.f, 0.f, 0.f, 0.f};
+    const int b = wave + kWaves * q;
+    if (b < NB) {
+      int I, J;
+      blk_coords(b, I, J);
+      for (int K = I; K < Lb; ++K) {       // A[i][k] = conj(W[k][i]), B[k][j] = W[k][j]
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = 16 * K + 4 * ks + lq;
+          const float2 wi = WS[(16 * I + l16) * P + k];
+          a4[ks] = make_float2(wi.x, -wi.y);
+          b4[ks] = WS[(16 * J + l16) * P + k];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], sir[q], sii[q]);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kBlocksPerWave; ++q) {
+    const int b = wave + kWaves * q;
+    if (b < NB) {
+      int I, J;
+      blk_coords(b, I, J);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * I + 4 * lq + v, j = 16 * J + l16;
+        if (i >= j) {
+          const float im = (i == j) ? 0.0f : sii[q][v];
+          WS[j * P + i] = make_float2(sir[q][v], im);
+          WS[i * P + j] = make_float2(sir[q][v], -im);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// One detection on workgroup g of the G workgroups the instance owns.
 template <int LPMAX, int THREADS>
 __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int kWaves = THREADS / 64;
@@ -423,7 +646,6 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int P = Lp + 1;                                             // pitch of the L x L LDS matrix
   constexpr bool kShLds = LPMAX <= 64;                                  // SigmaHat resident in LDS
   constexpr int kRowBlocksPerWave = (Lb + kWaves - 1) / kWaves;
-  constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
   extern __shared__ float4 smem_raw[];
   __shared__ int s_ok, s_pd[LPMAX / 16];
   const int NT = A.NT, PT = A.NT + 1;
@@ -442,7 +664,6 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int n0 = g * NT;
-  constexpr int E = NB * 256;
   unsigned gen = 0;
   const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
 
@@ -480,218 +701,21 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     for (int c = tid; c < NT; c += THREADS)   // weights w_c
       red_q[c] = known ? gs[c] * xs[c] : xs[c];
     __syncthreads();
-    {
-      const float *wv = red_q;
-      float2 *dst = A.partials + (size_t)g * A.pstride;
-#pragma unroll
-      for (int q = 0; q < kBlocksPerWave; ++q) {
-        const int b = wave + kWaves * q;
-        if (b < NB) {
-          int I, J;
-          blk_coords(b, I, J);
-          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-          for (int cb = 0; cb < A.ncb; ++cb) {
-            float2 av4[4], bv4[4];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-              const int c = 16 * cb + 4 * ks + lq;
-              const float2 s = St[(16 * J + l16) * PT + c];
-              const float w = wv[c];
-              av4[ks] = St[(16 * I + l16) * PT + c];
-              bv4[ks] = make_float2(w * s.x, -w * s.y);
-            }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) cmfma(av4[ks], bv4[ks], cr, ci);
-          }
-          float4 *o = (float4 *)(dst + b * 256 + l16 * 16 + 4 * lq);
-          o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
-          o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
-        }
-      }
-    }
+    tile_gram<Lp, THREADS>(St, PT, A.ncb, red_q, A.partials + (size_t)g * A.pstride);
     PSCA_MARK(it, 1);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ===== B. reduce a slice of the partials into Sigma ===================
     PSCA_MARK(it, 2);
-    {
-      const int per = (E + A.G - 1) / A.G;
-      const int start = g * per, end = min(E, start + per);
-      const int cnt = max(0, end - start);
-      if (cnt > 0 && cnt <= THREADS) {
-        const int Pp = THREADS / cnt;   // threads per element
-        if (tid < cnt * Pp) {
-          const int e = start + tid % cnt, part = tid / cnt;
-          float2 acc = make_float2(0.f, 0.f);
-          for (int h = part; h < A.G; h += Pp) {
-            const float2 v = A.partials[(size_t)h * A.pstride + e];
-            acc.x += v.x;
-            acc.y += v.y;
-          }
-          scr[tid] = acc;
-        }
-        __syncthreads();
-        if (tid < cnt) {
-          float2 sm = make_float2(0.f, 0.f);
-          for (int part = 0; part < Pp; ++part) {
-            const float2 v = scr[part * cnt + tid];
-            sm.x += v.x;
-            sm.y += v.y;
-          }
-          const int e = start + tid;
-          const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
-          int I, J;
-          blk_coords(b, I, J);
-          if (I == J && ii == jj) {
-            const int i = 16 * I + ii;
-            sm.x += (i < A.L) ? A.sigma2 : 1.0f;   // padded rows: isolated unit pivots
-            sm.y = 0.0f;
-          }
-          A.sigma[e] = sm;
-        }
-      } else {
-        for (int e = start + tid; e < end; e += THREADS) {
-          float2 sm = make_float2(0.f, 0.f);
-          for (int h = 0; h < A.G; ++h) {
-            const float2 v = A.partials[(size_t)h * A.pstride + e];
-            sm.x += v.x;
-            sm.y += v.y;
-          }
-          const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
-          int I, J;
-          blk_coords(b, I, J);
-          if (I == J && ii == jj) {
-            const int i = 16 * I + ii;
-            sm.x += (i < A.L) ? A.sigma2 : 1.0f;
-            sm.y = 0.0f;
-          }
-          A.sigma[e] = sm;
-        }
-      }
-    }
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, A.sigma, scr, true, A.L, A.sigma2);
     PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
-    // ===== C1. Blocked Cholesky Sigma = L L^H, diagonal blocks of W = L^-1 ==
-    // Every workgroup factors the same Sigma (no further grid barrier).  Block
-    // step J: wavefront 0 has factored diagonal block J in registers and left
-    // W_JJ in its place; the panel L_IJ = A_IJ W_JJ^H follows on MFMA, then
-    // the trailing updates A_IK -= L_IJ L_KJ^H, during which wavefront 0
-    // updates block J+1 first and factors it.
+    // ===== C1-C3. Sigma^-1 (blocked Cholesky, W = L^-1, W^H W) ===========
     PSCA_MARK(it, 4);
-    for (int e = tid; e < E; e += THREADS) {
-      const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
-      int I, J;
-      blk_coords(b, I, J);
-      WS[(16 * J + jj) * P + 16 * I + ii] = A.sigma[e];
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const bool ok = leaf_chol(WS, P, lane);
-      if (lane == 0) s_pd[0] = ok ? 1 : 0;
-    }
-    __syncthreads();
-    for (int J = 0; J < Lb; ++J) {
-      PSCA_SUB_MARK(it, J, 0);
-      if (!s_pd[J]) {   // uniform: every workgroup factors the same Sigma
-        failed = true;
-        break;
-      }
-      if (J + 1 == Lb) break;
-      for (int I = J + 1 + wave; I < Lb; I += kWaves) chol_panel(WS, P, J, I, l16, lq);
-      __syncthreads();
-      PSCA_SUB_MARK(it, J, 1);
-      if (wave == 0) {
-        chol_trail(WS, P, J, J + 1, J + 1, l16, lq);
-        wave_lds_sync();
-        const bool ok = leaf_chol(WS + 16 * (J + 1) * P + 16 * (J + 1), P, lane);
-        if (lane == 0) s_pd[J + 1] = ok ? 1 : 0;
-      } else {
-        int q = 0;
-        for (int I = J + 2; I < Lb; ++I)
-          for (int K = J + 1; K <= I; ++K)
-            if (q++ % (kWaves - 1) == wave - 1) chol_trail(WS, P, J, I, K, l16, lq);
-      }
-      __syncthreads();
-    }
-    PSCA_MARK(it, 5);
-    if (failed) break;
-
-    // ===== C2. Off-diagonal blocks of W, right to left ======================
-    // W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ, written over L_IJ.
-    for (int J = Lb - 2; J >= 0; --J) {
-      f4 rr = {0.f, 0.f, 0.f, 0.f}, ri = {0.f, 0.f, 0.f, 0.f};
-      const int I = J + 1 + wave;
-      if (I < Lb) {
-        f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
-        for (int K = J + 1; K <= I; ++K)
-          cblock_mma(WS + (16 * K) * P + 16 * I, WS + (16 * J) * P + 16 * K, P, l16, lq, tr, ti);
-        float2 *T = scr + wave * 256;          // column-major, pitch 16
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
-        wave_lds_sync();
-        float2 ta[4], wb[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          ta[ks] = T[(4 * ks + lq) * 16 + l16];
-          wb[ks] = WS[(16 * J + l16) * P + 16 * J + 4 * ks + lq];
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(ta[ks], wb[ks], rr, ri);
-      }
-      __syncthreads();
-      if (I < Lb) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) WS[(16 * J + l16) * P + 16 * I + 4 * lq + v] = make_float2(-rr[v], -ri[v]);
-      }
-      __syncthreads();
-    }
-
-    // ===== C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS ======
-    PSCA_MARK(it, 6);
-    {
-      f4 sir[kBlocksPerWave], sii[kBlocksPerWave];
-#pragma unroll
-      for (int q = 0; q < kBlocksPerWave; ++q) {
-        sir[q] = (f4){0.f, 0.f, 0.f, 0.f};
-        sii[q] = (f4){0.f, 0.f, 0.f, 0.f};
-        const int b = wave + kWaves * q;
-        if (b < NB) {
-          int I, J;
-          blk_coords(b, I, J);
-          for (int K = I; K < Lb; ++K) {       // A[i][k] = conj(W[k][i]), B[k][j] = W[k][j]
-            float2 a4[4], b4[4];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-              const int k = 16 * K + 4 * ks + lq;
-              const float2 wi = WS[(16 * I + l16) * P + k];
-              a4[ks] = make_float2(wi.x, -wi.y);
-              b4[ks] = WS[(16 * J + l16) * P + k];
-            }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], sir[q], sii[q]);
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < kBlocksPerWave; ++q) {
-        const int b = wave + kWaves * q;
-        if (b < NB) {
-          int I, J;
-          blk_coords(b, I, J);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * lq + v, j = 16 * J + l16;
-            if (i >= j) {
-              const float im = (i == j) ? 0.0f : sii[q][v];
-              WS[j * P + i] = make_float2(sir[q][v], im);
-              WS[i * P + j] = make_float2(sir[q][v], -im);
-            }
-          }
-        }
-      }
-      __syncthreads();
+    if (!invert_hpd<Lp, THREADS>(A.sigma, WS, scr, s_pd, it)) {
+      failed = true;
+      break;
     }
 
     // ===== C4. B = Sigma^-1 S_g and q;  D = SigmaHat B and r =================
