@@ -140,6 +140,25 @@ int psca_iterate(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, in
                  const psca_params *prm, float rho, const float *x_in, float *x_out,
                  float *q_out, float *r_out, float *xt_out, int32_t *status, void *stream);
 
+/* The unrolled network's forward pass (PSCA-Net, the "-Net" subsections of
+ * Sec. III and IV): Algorithm 1 from x = 0 for prm->iters layers, layer k
+ * using step size prm->rho[k] (or the schedule when prm->rho is NULL), with
+ * every iterate recorded.  x_hist: DEVICE [(prm->iters + 1) x N], row k =
+ * x^(k) (row 0 = 0; the last row is the output). */
+int psca_net_forward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                     const psca_params *prm, float *x_hist, int32_t *status, void *stream);
+
+/* Backward of one layer x' = (1 - rho) x + rho x~(x) (one iteration of
+ * Algorithm 1 with step size rho in [0, 1], eqs. Update_*): given
+ * v = dL/dx', writes grad_x = dL/dx (DEVICE [N]) and grad_rho = dL/drho
+ * (DEVICE, one float).  Sigma^-1 is recomputed from x_in (the layer's input
+ * iterate), not stored.  The clip of Lemmas 1-4 passes gradient where its
+ * argument lies inside the bounds (bounds included).  prm->iters and
+ * prm->rho are ignored.  Needs L <= 64 (PSCA_ENOTSUP otherwise). */
+int psca_layer_backward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                        const psca_params *prm, float rho, const float *x_in, const float *v, float *grad_x,
+                        float *grad_rho, int32_t *status, void *stream);
+
 /* One instance of a batch: the arguments of psca_detect.  All pointers are
  * DEVICE pointers on the context's GPU; status is optional (NULL). */
 typedef struct {

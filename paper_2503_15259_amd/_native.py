@@ -25,6 +25,7 @@ EXPORTED = (
     "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
     "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold", "psca_detect_batch",
     "psca_autotune_batch", "psca_plan_create", "psca_plan_launch", "psca_plan_team_size", "psca_plan_destroy",
+    "psca_net_forward", "psca_layer_backward",
 )
 
 
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "psca_plan_launch": ([vp, vp], i32),
         "psca_plan_team_size": ([vp], i32),
         "psca_plan_destroy": ([vp], i32),
+        "psca_net_forward": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
+        "psca_layer_backward": ([vp, vp, vp, i32, i32, P, f32, vp, vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

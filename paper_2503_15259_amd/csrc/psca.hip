@@ -143,37 +143,95 @@ __device__ __forceinline__ float prior_log_ratio(float x, const StepArgs &a) {
   return -a.dens_c / x;                                             // -(2/beta + 1)/x
 }
 
-// g: known pathloss of the device (K variants); logit = log(p / (1 - p)) (MAP-K).
-__device__ __forceinline__ float coordinate_step(float x, float q, float r, float g, float logit,
+// g: known pathloss of the device (K variants); logit = log(p / (1 - p)) (MAP-K);
+// qmr = q - r, computed directly (see the phase that forms it).
+__device__ __forceinline__ float coordinate_step(float x, float q, float qmr, float g, float logit,
                                                  const StepArgs &a) {
   float grad, curv, hi;
   switch (a.variant) {
     case PSCA_ML_K: {
-      grad = g * (q - r);
+      grad = g * qmr;
       const float gq = g * q;
       curv = gq * gq;
       hi = 1.0f;
       break;
     }
     case PSCA_MAP_K: {
-      grad = g * (q - r) - logit * a.inv_M;
+      grad = g * qmr - logit * a.inv_M;
       const float gq = g * q;
       curv = gq * gq;
       hi = 1.0f;
       break;
     }
     case PSCA_ML_UD:
-      grad = q - r;
+      grad = qmr;
       curv = q * q;
       hi = INFINITY;
       break;
     default:  // PSCA_MAP_UR
-      grad = q - r - prior_log_ratio(x, a) * a.inv_M;
+      grad = qmr - prior_log_ratio(x, a) * a.inv_M;
       curv = q * q;
       hi = a.g_u;
       break;
   }
   return fminf(fmaxf(x - grad / curv, 0.0f), hi);
+}
+
+// Derivative of prior_log_ratio (the MAP-UR prior term of the gradient) in
+// the same per-piece forms; 0 in the gap.
+__device__ __forceinline__ float prior_log_ratio_deriv(float x, const StepArgs &a) {
+  const float e = a.eps;
+  if (x < e) {                                                      // (H1'/H1)'
+    const float t = (e + 2.0f * x) * (x - e);
+    return -6.0f * (2.0f * x * x + e * e) / (t * t);
+  }
+  if (x < a.g_l - e) return 0.0f;
+  if (x < a.g_l) {                                                  // (H2'/H2)'
+    const float u = x - a.g_l;
+    const float num = -6.0f * u / e + a.h2_b * (3.0f * u + e);
+    const float f = (1.0f - 2.0f * u / e) + a.h2_b * u;
+    const float den = (u + e) * f;
+    if (den == 0.0f) return 0.0f;
+    const float dnum = -6.0f / e + 3.0f * a.h2_b;
+    const float dden = f + (u + e) * (-2.0f / e + a.h2_b);
+    return (dnum * den - num * dden) / (den * den);
+  }
+  return a.dens_c / (x * x);                                        // (2/beta + 1)/x^2
+}
+
+// Partial derivatives of one layer's coordinate step for the backward pass:
+// with kappa = g (known pathloss) or 1, grad = kappa (q - r) - c(x),
+// curv = (kappa q)^2 and pre = x - grad / curv: x~ = clip(pre, lo, hi),
+// mask = [lo <= pre <= hi], dq = d pre/dq, dr = d pre/dr and own = d pre/dx
+// at fixed q, r.
+struct StepDerivs {
+  float xt, mask, dq, dr, own, kappa;
+};
+__device__ __forceinline__ StepDerivs step_derivs(float x, float q, float r, float g, float logit,
+                                                  const StepArgs &a) {
+  float kappa = 1.0f, c = 0.0f, cp = 0.0f, hi;
+  switch (a.variant) {
+    case PSCA_ML_K: kappa = g; hi = 1.0f; break;
+    case PSCA_MAP_K: kappa = g; c = logit * a.inv_M; hi = 1.0f; break;
+    case PSCA_ML_UD: hi = INFINITY; break;
+    default:   // PSCA_MAP_UR
+      c = prior_log_ratio(x, a) * a.inv_M;
+      cp = prior_log_ratio_deriv(x, a) * a.inv_M;
+      hi = a.g_u;
+      break;
+  }
+  const float grad = kappa * (q - r) - c;
+  const float kq = kappa * q;
+  const float curv = kq * kq;
+  const float pre = x - grad / curv;
+  StepDerivs d;
+  d.xt = fminf(fmaxf(pre, 0.0f), hi);
+  d.mask = (pre >= 0.0f && pre <= hi) ? 1.0f : 0.0f;
+  d.dq = (2.0f * grad - kq) / (kappa * kq * q * q);
+  d.dr = 1.0f / (kappa * q * q);
+  d.own = 1.0f + cp / curv;
+  d.kappa = kappa;
+  return d;
 }
 
 // ---------------------------------------------------------------------------
@@ -239,6 +297,7 @@ struct CoopArgs {
   StepArgs a;
   const float *x_in;    // [N] initial iterate or null (zeros)
   float *x_out, *q_out, *r_out, *xt_out;
+  float *x_hist;        // [iters + 1][N] every iterate, or null
   int32_t *status;
   float2 *partials;     // [G][pstride], workgroup g's packed partial of Sigma at g * pstride
   size_t pstride;       // >= NB * 256
@@ -514,12 +573,19 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
   }
 }
 
-// Sigma^-1 of the packed HPD matrix `sigma`, full and exactly Hermitian,
-// column-major with pitch Lp + 1 in WS.  Returns false (uniformly across
-// the workgroups of an instance) if a pivot is not positive and finite.
-// scr: per-wavefront 16x16 staging; s_pd: Lp / 16 ints of LDS.
-template <int LP, int THREADS>
-__device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, float2 *scr, int *s_pd, int it) {
+// Cholesky factor inverse W = L^-1 (kFull false: lower blocks of WS, zeros
+// above the diagonal inside the diagonal blocks, upper blocks untouched) or
+// Sigma^-1 = W^H W (kFull true: full and exactly Hermitian) of the packed
+// HPD matrix `sigma`, column-major with pitch Lp + 1 in WS.  Returns false
+// (uniformly across the workgroups of an instance) if a pivot is not
+// positive and finite.  scr: per-wavefront 16x16 staging; s_pd: Lp / 16
+// ints of LDS.
+// With delta != null, the wavefronts that wait for the first diagonal block
+// also write Sigma - SigmaHat (SigmaHat: L x L column-major in HBM, zero
+// beyond L) into delta, full, column-major with pitch Lp + 1.
+template <int LP, int THREADS, bool kFull>
+__device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, float2 *scr, int *s_pd, int it,
+                                           float2 *delta = nullptr, const float2 *shat = nullptr, int L = 0) {
   constexpr int kWaves = THREADS / 64, Lb = LP / 16, NB = Lb * (Lb + 1) / 2, P = LP + 1, E = NB * 256;
   constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lq = lane >> 4;
@@ -539,6 +605,20 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
   if (wave == 0) {
     const bool ok = leaf_chol(WS, P, lane);
     if (lane == 0) s_pd[0] = ok ? 1 : 0;
+  } else if (delta) {
+    for (int e = tid - 64; e < LP * LP; e += THREADS - 64) {
+      const int k = e / LP, i = e - k * LP;   // column k, row i
+      const int I = i >> 4, K = k >> 4;
+      float2 sg;   // from the packed copy: wavefront 0 overwrites block (0, 0) of WS
+      if (I >= K) {
+        sg = sigma[blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
+      } else {
+        const float2 t = sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
+        sg = make_float2(t.x, -t.y);
+      }
+      const float2 sh = (i < L && k < L) ? shat[(size_t)k * L + i] : make_float2(0.f, 0.f);
+      delta[k * P + i] = make_float2(sg.x - sh.x, sg.y - sh.y);
+    }
   }
   __syncthreads();
   for (int J = 0; J < Lb; ++J) {
@@ -593,6 +673,7 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
   }
   // C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS.
   PSCA_MARK(it, 6);
+  if constexpr (!kFull) return true;
   f4 sir[kBlocksPerWave], sii[kBlocksPerWave];
 #pragma unroll
   for (int q = 0; q < kBlocksPerWave; ++q) {
@@ -653,7 +734,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int kPB = 17;                   // pitch of the B tile
   float2 *Bt = St + Lp * PT;                // [Lp][kPB] B tile of one 16-column block
   float2 *WS = Bt + Lp * kPB;               // [Lp][P]   column-major: Cholesky factor, W, Sigma^-1
-  float2 *ShL = WS + Lp * P;                // [Lp][P]   SigmaHat, column-major (kShLds)
+  float2 *ShL = WS + Lp * P;                // [Lp][P]   Sigma - SigmaHat of the iteration (kShLds)
   float2 *scr = ShL + (kShLds ? Lp * P : 0);// [kWaves][256] per-wave 16x16 scratch
   float *xs = (float *)(scr + kWaves * 256);   // [NT] iterate of the tile
   float *gs = xs + NT;                      // [NT] pathloss
@@ -677,6 +758,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     const int n = n0 + c;
     const bool in = n < A.N;
     xs[c] = (in && A.x_in) ? A.x_in[n] : 0.0f;
+    if (in && A.x_hist) A.x_hist[n] = xs[c];
     gs[c] = (in && A.a.g) ? A.a.g[n] : 0.0f;
     float lg = 0.0f;
     if (in && A.a.p) {
@@ -684,12 +766,6 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
       lg = logf(pn / (1.0f - pn));
     }
     ls[c] = lg;
-  }
-  if constexpr (kShLds) {
-    for (int e = tid; e < Lp * Lp; e += THREADS) {
-      const int k = e / Lp, i = e - k * Lp;
-      ShL[k * P + i] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
-    }
   }
 
   double rho_d = A.rho0;
@@ -711,15 +787,19 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
-    // ===== C1-C3. Sigma^-1 (blocked Cholesky, W = L^-1, W^H W) ===========
+    // ===== C1-C2. W = L^-1 of the blocked Cholesky factor Sigma = L L^H ======
     PSCA_MARK(it, 4);
-    if (!invert_hpd<Lp, THREADS>(A.sigma, WS, scr, s_pd, it)) {
+    if (!invert_hpd<Lp, THREADS, false>(A.sigma, WS, scr, s_pd, it, kShLds ? ShL : nullptr, A.Sh, A.L)) {
       failed = true;
       break;
     }
 
-    // ===== C4. B = Sigma^-1 S_g and q;  D = SigmaHat B and r =================
-    // One 16-column block of the tile at a time, so the B tile is Lp x 16.
+    // ===== C4. Y = W S_t (q = |y|^2), B = W^H Y = Sigma^-1 S_t,
+    // q - r = b^H (Sigma - SigmaHat) b ========================================
+    // One 16-column block of the tile at a time (the B tile is Lp x 16).  q
+    // as a sum of squares and q - r in the difference form keep their
+    // relative accuracy for weak devices, whose q is small next to
+    // ||Sigma^-1||.
     PSCA_MARK(it, 7);
     for (int cb = 0; cb < A.ncb; ++cb) {
 #pragma unroll
@@ -727,16 +807,13 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
         const int I = wave + kWaves * rb;
         if (I < Lb) {
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int K = 0; K < Lb; ++K)
+          for (int K = 0; K <= I; ++K)   // W is lower triangular
             cblock_mma_rm(WS + 16 * I, P, St + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
           float qp = 0.0f;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int i = 16 * I + 4 * lq + v;
-            const float2 sv = St[i * PT + 16 * cb + l16];
-            qp += sv.x * cr[v] + sv.y * ci[v];
-            Bt[i * kPB + l16] = make_float2(cr[v], ci[v]);
+            qp += cr[v] * cr[v] + ci[v] * ci[v];
+            Bt[(16 * I + 4 * lq + v) * kPB + l16] = make_float2(cr[v], ci[v]);
           }
           qp += __shfl_xor(qp, 16);
           qp += __shfl_xor(qp, 32);
@@ -744,12 +821,50 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
         }
       }
       __syncthreads();
+      {   // B = W^H Y, in registers until every wavefront has read Y
+        f4 br[kRowBlocksPerWave], bi[kRowBlocksPerWave];
+#pragma unroll
+        for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+          br[rb] = (f4){0.f, 0.f, 0.f, 0.f};
+          bi[rb] = (f4){0.f, 0.f, 0.f, 0.f};
+          const int I = wave + kWaves * rb;
+          if (I < Lb) {
+            for (int K = I; K < Lb; ++K) {   // A[i][k] = conj(W[k][i])
+              float2 a4[4], b4[4];
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) {
+                const int k = 16 * K + 4 * ks + lq;
+                const float2 wv = WS[(16 * I + l16) * P + k];
+                a4[ks] = make_float2(wv.x, -wv.y);
+                b4[ks] = Bt[k * kPB + l16];
+              }
+#pragma unroll
+              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], br[rb], bi[rb]);
+            }
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+          const int I = wave + kWaves * rb;
+          if (I < Lb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              Bt[(16 * I + 4 * lq + v) * kPB + l16] = make_float2(br[rb][v], bi[rb][v]);
+          }
+        }
+        __syncthreads();
+      }
 #pragma unroll
       for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
         const int I = wave + kWaves * rb;
         if (I < Lb) {
+          // D' = (Sigma - SigmaHat) B: then b^H D' = q - r with an error that
+          // scales with Sigma - SigmaHat (small near a stationary point)
+          // rather than with q and r themselves.  Sigma from its packed
+          // lower blocks (diagonal blocks are stored whole).
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-          if constexpr (kShLds) {
+          if constexpr (kShLds) {   // ShL holds Sigma - SigmaHat for this iteration
 #pragma unroll
             for (int K = 0; K < Lb; ++K) cblock_mma_rm(ShL + 16 * I, P, Bt, kPB, 16 * K, l16, lq, cr, ci);
           } else {
@@ -759,7 +874,15 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) {
                 const int i = 16 * I + l16, k = 16 * K + 4 * ks + lq;
-                a4[ks] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+                float2 sg;
+                if (I >= K) {
+                  sg = A.sigma[blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
+                } else {
+                  const float2 t = A.sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
+                  sg = make_float2(t.x, -t.y);
+                }
+                const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+                a4[ks] = make_float2(sg.x - sh.x, sg.y - sh.y);
                 b4[ks] = Bt[k * kPB + l16];
               }
 #pragma unroll
@@ -791,17 +914,18 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     for (int c = tid; c < NT; c += THREADS) {
       const int n = n0 + c;
       if (n < A.N) {
-        float q = 0.0f, r = 0.0f;
+        float q = 0.0f, qmr = 0.0f;
         for (int I = 0; I < Lb; ++I) {
           q += red_q[I * NT + c];
-          r += red_r[I * NT + c];
+          qmr += red_r[I * NT + c];
         }
         const float x = xs[c];
-        const float xt = coordinate_step(x, q, r, gs[c], ls[c], A.a);
+        const float xt = coordinate_step(x, q, qmr, gs[c], ls[c], A.a);
         xs[c] = (1.0f - rho) * x + rho * xt;
+        if (A.x_hist) A.x_hist[(size_t)(it + 1) * A.N + n] = xs[c];
         if (last) {
           if (A.q_out) A.q_out[n] = q;
-          if (A.r_out) A.r_out[n] = r;
+          if (A.r_out) A.r_out[n] = q - qmr;
           if (A.xt_out) A.xt_out[n] = xt;
         }
       }
@@ -819,6 +943,279 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
 }
 
+// ---------------------------------------------------------------------------
+// Backward of one unrolled layer x' = (1 - rho) x + rho x~(x)
+// ---------------------------------------------------------------------------
+// Given v = dL/dx', with a_n = rho v_n mask_n d pre_n/dq_n and
+// b_n = rho v_n mask_n d pre_n/dr_n, G_a = S diag(a) S^H, G_b = S diag(b) S^H,
+// b_m = Sigma^-1 s_m and c_m = Sigma^-1 SigmaHat Sigma^-1 s_m:
+//   dL/dx_m = v_m (1 - rho) + rho v_m mask_m own_m
+//             - kappa_m (b_m^H G_a b_m + 2 Re c_m^H G_b b_m),
+//   dL/drho = sum_n v_n (x~_n - x_n),
+// from dSigma^-1 = -Sigma^-1 s_m s_m^H Sigma^-1 dw_m (w = kappa x).
+// Sigma^-1 is recomputed from x, not stored by the forward pass.
+struct BackArgs {
+  CoopArgs c;           // instance, tile plan, x_in = the layer's input, work buffers, barrier
+  float rho;
+  const float *v;       // [N] dL/dx'
+  float *grad_x;        // [N] dL/dx
+  float *rho_part;      // [G] per-workgroup parts of dL/drho
+  float2 *partials_b;   // [G][pstride] partials of G_b (those of G_a use c.partials)
+  float2 *gram_a, *gram_b;   // packed G_a, G_b
+};
+
+// LDS footprint of the backward body (Lp <= 64, SigmaHat resident)
+__host__ __device__ inline size_t lds_back_bytes(int Lp, int NT, int waves) {
+  const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
+  const size_t f2 = 3 * (size_t)Lp * pt + (size_t)Lp * 17 + 2 * (size_t)Lp * P + (size_t)waves * 256;
+  const size_t fl = 7 * (size_t)NT + 2 * Lb * NT + (size_t)waves;
+  return f2 * sizeof(float2) + fl * 4;
+}
+
+// Packed Hermitian -> full column-major (pitch P) in LDS.
+template <int LP, int THREADS>
+__device__ __forceinline__ void unpack_hermitian(const float2 *packed, float2 *M) {
+  constexpr int Lb = LP / 16, E = Lb * (Lb + 1) / 2 * 256, P = LP + 1;
+  for (int e = threadIdx.x; e < E; e += THREADS) {
+    const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+    int I, J;
+    blk_coords(b, I, J);
+    const float2 v = packed[e];
+    M[(16 * J + jj) * P + 16 * I + ii] = v;
+    if (I != J) M[(16 * I + ii) * P + 16 * J + jj] = make_float2(v.x, -v.y);
+  }
+}
+
+template <int LP, int THREADS>
+__device__ __forceinline__ void psca_back_body(const BackArgs &Bk, const int g) {
+  const CoopArgs &A = Bk.c;
+  constexpr int kWaves = THREADS / 64;
+  constexpr int Lp = LP, Lb = LP / 16, P = Lp + 1, kPB = 17;
+  constexpr int kRowBlocksPerWave = (Lb + kWaves - 1) / kWaves;
+  static_assert(LP <= 64, "the backward body keeps SigmaHat and two Gram matrices in LDS");
+  extern __shared__ float4 smem_raw[];
+  __shared__ int s_ok, s_pd[LP / 16];
+  const int NT = A.NT, PT = A.NT + 1;
+  float2 *St = (float2 *)smem_raw;     // [Lp][PT] S tile
+  float2 *Bf = St + Lp * PT;           // [Lp][PT] Sigma^-1 S tile
+  float2 *Cf = Bf + Lp * PT;           // [Lp][PT] Sigma^-1 SigmaHat Sigma^-1 S tile
+  float2 *Dt = Cf + Lp * PT;           // [Lp][kPB] SigmaHat B of one 16-column block
+  float2 *WS = Dt + Lp * kPB;          // [Lp][P] Sigma^-1, then G_a
+  float2 *ShL = WS + Lp * P;           // [Lp][P] SigmaHat, then G_b
+  float2 *scr = ShL + Lp * P;          // [kWaves][256]
+  float *xs = (float *)(scr + kWaves * 256);
+  float *gs = xs + NT, *ls = gs + NT, *vs = ls + NT, *aw = vs + NT, *bw = aw + NT, *dxo = bw + NT;
+  float *red_q = dxo + NT;             // [Lb][NT]
+  float *red_r = red_q + Lb * NT;      // [Lb][NT]
+  float *s_red = red_r + Lb * NT;      // [kWaves]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lq = lane >> 4;
+  const int n0 = g * NT;
+  unsigned gen = 0;
+  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
+
+  for (int e = tid; e < Lp * NT; e += THREADS) {
+    const int c = e / Lp, i = e - c * Lp;
+    const int n = n0 + c;
+    St[i * PT + c] = (i < A.L && n < A.N) ? A.S[(size_t)n * A.L + i] : make_float2(0.f, 0.f);
+  }
+  for (int c = tid; c < NT; c += THREADS) {
+    const int n = n0 + c;
+    const bool in = n < A.N;
+    xs[c] = in ? A.x_in[n] : 0.0f;
+    gs[c] = (in && A.a.g) ? A.a.g[n] : 0.0f;
+    float lg = 0.0f;
+    if (in && A.a.p) {
+      const float pn = A.a.p[n];
+      lg = logf(pn / (1.0f - pn));
+    }
+    ls[c] = lg;
+    vs[c] = in ? Bk.v[n] : 0.0f;
+  }
+  for (int e = tid; e < Lp * Lp; e += THREADS) {
+    const int k = e / Lp, i = e - k * Lp;
+    ShL[k * P + i] = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+  }
+  bool failed = false, aborted = false;
+  do {
+    // Sigma(x) and its inverse, as in the forward pass
+    for (int c = tid; c < NT; c += THREADS) red_q[c] = known ? gs[c] * xs[c] : xs[c];
+    __syncthreads();
+    tile_gram<Lp, THREADS>(St, PT, A.ncb, red_q, A.partials + (size_t)g * A.pstride);
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, A.sigma, scr, true, A.L, A.sigma2);
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+    if (!invert_hpd<Lp, THREADS, true>(A.sigma, WS, scr, s_pd, 0)) { failed = true; break; }
+
+    // B = Sigma^-1 S_t (q), D = SigmaHat B (r), C = Sigma^-1 D, per 16-column block
+    for (int cb = 0; cb < A.ncb; ++cb) {
+#pragma unroll
+      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+        const int I = wave + kWaves * rb;
+        if (I < Lb) {
+          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int K = 0; K < Lb; ++K) cblock_mma_rm(WS + 16 * I, P, St + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
+          float qp = 0.0f;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * lq + v, j = 16 * cb + l16;
+            const float2 sv = St[i * PT + j];
+            qp += sv.x * cr[v] + sv.y * ci[v];
+            Bf[i * PT + j] = make_float2(cr[v], ci[v]);
+          }
+          qp += __shfl_xor(qp, 16);
+          qp += __shfl_xor(qp, 32);
+          if (lq == 0) red_q[I * NT + 16 * cb + l16] = qp;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+        const int I = wave + kWaves * rb;
+        if (I < Lb) {
+          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int K = 0; K < Lb; ++K) cblock_mma_rm(ShL + 16 * I, P, Bf + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
+          float rp = 0.0f;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * lq + v;
+            const float2 bv = Bf[i * PT + 16 * cb + l16];
+            rp += bv.x * cr[v] + bv.y * ci[v];
+            Dt[i * kPB + l16] = make_float2(cr[v], ci[v]);
+          }
+          rp += __shfl_xor(rp, 16);
+          rp += __shfl_xor(rp, 32);
+          if (lq == 0) red_r[I * NT + 16 * cb + l16] = rp;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+        const int I = wave + kWaves * rb;
+        if (I < Lb) {
+          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int K = 0; K < Lb; ++K) cblock_mma_rm(WS + 16 * I, P, Dt, kPB, 16 * K, l16, lq, cr, ci);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Cf[(16 * I + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(cr[v], ci[v]);
+        }
+      }
+      __syncthreads();
+    }
+
+    // per device: step derivatives, the weights a, b and the direct term
+    float rho_term = 0.0f;
+    for (int c = tid; c < NT; c += THREADS) {
+      float a_c = 0.0f, b_c = 0.0f, d_c = 0.0f;
+      if (n0 + c < A.N) {
+        float q = 0.0f, r = 0.0f;
+        for (int I = 0; I < Lb; ++I) {
+          q += red_q[I * NT + c];
+          r += red_r[I * NT + c];
+        }
+        const StepDerivs d = step_derivs(xs[c], q, r, gs[c], ls[c], A.a);
+        const float rv = Bk.rho * vs[c] * d.mask;
+        a_c = rv * d.dq;
+        b_c = rv * d.dr;
+        d_c = vs[c] * (1.0f - Bk.rho) + rv * d.own;
+        rho_term += vs[c] * (d.xt - xs[c]);
+        gs[c] = d.kappa;   // kappa replaces g from here on
+      }
+      aw[c] = a_c;
+      bw[c] = b_c;
+      dxo[c] = d_c;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) rho_term += __shfl_xor(rho_term, o);
+    if (lane == 0) s_red[wave] = rho_term;
+    __syncthreads();
+    if (tid == 0) {
+      float t = 0.0f;
+      for (int w = 0; w < kWaves; ++w) t += s_red[w];
+      Bk.rho_part[g] = t;
+    }
+
+    // G_a and G_b
+    tile_gram<Lp, THREADS>(St, PT, A.ncb, aw, A.partials + (size_t)g * A.pstride);
+    tile_gram<Lp, THREADS>(St, PT, A.ncb, bw, Bk.partials_b + (size_t)g * A.pstride);
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, Bk.gram_a, scr, false, A.L, 0.0f);
+    __syncthreads();
+    reduce_slice<Lp, THREADS>(Bk.partials_b, A.pstride, A.G, g, Bk.gram_b, scr, false, A.L, 0.0f);
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+    unpack_hermitian<Lp, THREADS>(Bk.gram_a, WS);
+    unpack_hermitian<Lp, THREADS>(Bk.gram_b, ShL);
+    __syncthreads();
+
+    // t1 = Re b^H G_a b, t2 = Re c^H G_b b, per device
+    for (int cb = 0; cb < A.ncb; ++cb) {
+#pragma unroll
+      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
+        const int I = wave + kWaves * rb;
+        if (I < Lb) {
+          f4 ar = {0.f, 0.f, 0.f, 0.f}, ai = {0.f, 0.f, 0.f, 0.f};
+          f4 br = {0.f, 0.f, 0.f, 0.f}, bi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int K = 0; K < Lb; ++K) {
+            cblock_mma_rm(WS + 16 * I, P, Bf + 16 * cb, PT, 16 * K, l16, lq, ar, ai);
+            cblock_mma_rm(ShL + 16 * I, P, Bf + 16 * cb, PT, 16 * K, l16, lq, br, bi);
+          }
+          float t1 = 0.0f, t2 = 0.0f;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + 4 * lq + v, j = 16 * cb + l16;
+            const float2 bv = Bf[i * PT + j], cv = Cf[i * PT + j];
+            t1 += bv.x * ar[v] + bv.y * ai[v];
+            t2 += cv.x * br[v] + cv.y * bi[v];
+          }
+          t1 += __shfl_xor(t1, 16);
+          t1 += __shfl_xor(t1, 32);
+          t2 += __shfl_xor(t2, 16);
+          t2 += __shfl_xor(t2, 32);
+          if (lq == 0) {
+            red_q[I * NT + 16 * cb + l16] = t1;
+            red_r[I * NT + 16 * cb + l16] = t2;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < NT; c += THREADS) {
+      const int n = n0 + c;
+      if (n < A.N) {
+        float t1 = 0.0f, t2 = 0.0f;
+        for (int I = 0; I < Lb; ++I) {
+          t1 += red_q[I * NT + c];
+          t2 += red_r[I * NT + c];
+        }
+        Bk.grad_x[n] = dxo[c] - gs[c] * (t1 + 2.0f * t2);
+      }
+    }
+  } while (false);
+  if (g == 0 && tid == 0 && A.status) *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
+}
+
+template <int LP>
+__global__ void __launch_bounds__(512) k_psca_back(BackArgs Bk) {
+  psca_back_body<LP, 512>(Bk, blockIdx.x);
+}
+
+// dL/drho = the sum of the per-workgroup parts (one workgroup)
+__global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__restrict__ out) {
+  __shared__ float sh[256];
+  float t = 0.0f;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) t += parts[i];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
 template <int LPMAX, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
   psca_body<LPMAX, THREADS>(A, blockIdx.x);
@@ -830,21 +1227,30 @@ __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
 // the team takes part in instance b iff g < descs[b].G (the planner sets
 // G = T).  Every instance synchronises on its own barrier words.
 constexpr int kBatchThreads = 512;
+
+// One instance inside the batch kernel; kept out of line so that each pilot
+// length gets its own register allocation.
+template <int LP>
+__device__ __noinline__ void team_member(const CoopArgs *__restrict__ desc, int g) {
+  const CoopArgs A = *desc;
+  psca_body<LP, kBatchThreads>(A, g);
+}
+
 __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__restrict__ descs,
                                                               const int *__restrict__ lists,
                                                               const int *__restrict__ offsets, int T) {
   const int t = blockIdx.x / T, g = blockIdx.x - t * T;
   const int i1 = offsets[t + 1];
   for (int idx = offsets[t]; idx < i1; ++idx) {
-    const CoopArgs A = descs[lists[idx]];
-    if (g < A.G) {
-      switch ((A.L + 15) & ~15) {
-        case 16: psca_body<16, kBatchThreads>(A, g); break;
-        case 32: psca_body<32, kBatchThreads>(A, g); break;
-        case 48: psca_body<48, kBatchThreads>(A, g); break;
-        case 64: psca_body<64, kBatchThreads>(A, g); break;
-        case 80: psca_body<80, kBatchThreads>(A, g); break;
-        default: psca_body<96, kBatchThreads>(A, g); break;
+    const CoopArgs *desc = descs + lists[idx];
+    if (g < desc->G) {
+      switch ((desc->L + 15) & ~15) {
+        case 16: team_member<16>(desc, g); break;
+        case 32: team_member<32>(desc, g); break;
+        case 48: team_member<48>(desc, g); break;
+        case 64: team_member<64>(desc, g); break;
+        case 80: team_member<80>(desc, g); break;
+        default: team_member<96>(desc, g); break;
       }
     }
     __syncthreads();   // the next instance reuses the LDS
@@ -1096,13 +1502,14 @@ void fill_args(CoopArgs &a, const float2 *Sh, const float2 *S, int L, int N, con
   a.q_out = q_out;
   a.r_out = r_out;
   a.xt_out = xt_out;
+  a.x_hist = nullptr;
   a.status = status;
 }
 
 // Runs k_psca for `iters` iterations from x_in (null: zeros).
 int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
                int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
-               float *xt_out, int32_t *status, hipStream_t st) {
+               float *xt_out, int32_t *status, hipStream_t st, float *x_hist = nullptr) {
   const int Lp = (L + 15) & ~15;
   const KernelChoice kc = pick_kernel(Lp);
   InstPlan p{};
@@ -1121,6 +1528,7 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
   if ((rc = ensure_ws(ctx, p.ws)) != PSCA_OK) return rc;
   CoopArgs a;
   fill_args(a, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
+  a.x_hist = x_hist;
   bind_ws(a, (char *)ctx->ws, p);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.bar.arrive, p.G, a.bar.release, a.bar.abort_flag,
                      a.status);
@@ -1165,6 +1573,77 @@ int stage_desc(psca_ctx *ctx, size_t bytes, char **host) {
   }
   *host = (char *)ctx->hdesc;
   return PSCA_OK;
+}
+
+// ---- backward of one unrolled layer ------------------------------------------
+const void *pick_back(int Lp) {
+  switch (Lp) {
+    case 16: return (const void *)k_psca_back<16>;
+    case 32: return (const void *)k_psca_back<32>;
+    case 48: return (const void *)k_psca_back<48>;
+    default: return (const void *)k_psca_back<64>;
+  }
+}
+
+int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
+                       float rho, const float *x_in, const float *v, float *grad_x, float *grad_rho,
+                       int32_t *status, hipStream_t st) {
+  const int Lp = (L + 15) & ~15;
+  const KernelChoice kc{pick_back(Lp), 512, Lp};
+  InstPlan p{};
+  for (int ncb = 1;; ++ncb) {
+    if (ncb > kMaxNcb) return PSCA_ENOTSUP;
+    const int NT = 16 * ncb, G = (N + NT - 1) / NT;
+    const size_t lds = lds_back_bytes(Lp, NT, 8);
+    if (lds > 159 * 1024) return PSCA_ENOTSUP;
+    const int cap = max_coresident(ctx, kc, lds);
+    if (cap <= 0) return PSCA_ENOTSUP;
+    if (G <= cap) {
+      p = InstPlan{Lp, ncb, NT, G, lds, 0};
+      break;
+    }
+  }
+  const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
+  const size_t o_pa = 0;
+  const size_t o_pb = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
+  const size_t o_sig = align_up(o_pb + (size_t)p.G * E * sizeof(float2));
+  const size_t o_ga = align_up(o_sig + E * sizeof(float2));
+  const size_t o_gb = align_up(o_ga + E * sizeof(float2));
+  const size_t o_arr = align_up(o_gb + E * sizeof(float2));
+  const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
+  const size_t o_abt = align_up(o_rel + sizeof(unsigned));
+  const size_t o_st = align_up(o_abt + sizeof(unsigned));
+  const size_t o_rp = align_up(o_st + sizeof(unsigned));
+  const size_t total = align_up(o_rp + (size_t)p.G * sizeof(float));
+  int rc = ensure_ws(ctx, total);
+  if (rc != PSCA_OK) return rc;
+  char *base = (char *)ctx->ws;
+  BackArgs b;
+  fill_args(b.c, Sh, S, L, N, prm, 1, rho, x_in, nullptr, nullptr, nullptr, nullptr, status, p);
+  b.c.partials = (float2 *)(base + o_pa);
+  b.c.pstride = E;
+  b.c.sigma = (float2 *)(base + o_sig);
+  b.c.bar.arrive = (unsigned *)(base + o_arr);
+  b.c.bar.release = (unsigned *)(base + o_rel);
+  b.c.bar.abort_flag = (int32_t *)(base + o_abt);
+  if (!b.c.status) b.c.status = (int32_t *)(base + o_st);
+  b.rho = rho;
+  b.v = v;
+  b.grad_x = grad_x;
+  b.rho_part = (float *)(base + o_rp);
+  b.partials_b = (float2 *)(base + o_pb);
+  b.gram_a = (float2 *)(base + o_ga);
+  b.gram_b = (float2 *)(base + o_gb);
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, b.c.bar.arrive, p.G, b.c.bar.release,
+                     b.c.bar.abort_flag, b.c.status);
+  if ((rc = launch_ok()) != PSCA_OK) return rc;
+  void *args[] = {&b};
+  if (hipLaunchCooperativeKernel(kc.fn, dim3(p.G), dim3(512), args, (unsigned)p.lds, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, (const float *)b.rho_part, p.G, grad_rho);
+  return launch_ok();
 }
 
 // ---- batches: persistent teams ---------------------------------------------
@@ -1659,6 +2138,31 @@ int psca_plan_destroy(psca_plan *plan) {
   (void)hipFree(plan->dimg);
   delete plan;
   return rc;
+}
+
+int psca_net_forward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                     const psca_params *prm, float *x_hist, int32_t *status, void *stream) {
+  if (!ctx || !Sigma_hat || !S || !x_hist) return PSCA_EINVAL;
+  int rc = validate_params(prm, L, N, true);
+  if (rc != PSCA_OK) return rc;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PSCA_EHIP;
+  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr,
+                    x_hist + (size_t)prm->iters * N, nullptr, nullptr, nullptr, status, as_stream(stream), x_hist);
+}
+
+int psca_layer_backward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                        const psca_params *prm, float rho, const float *x_in, const float *v, float *grad_x,
+                        float *grad_rho, int32_t *status, void *stream) {
+  if (!ctx || !Sigma_hat || !S || !x_in || !v || !grad_x || !grad_rho) return PSCA_EINVAL;
+  if (!(rho >= 0.0f) || rho > 1.0f) return PSCA_EINVAL;
+  int rc = validate_params(prm, L, N, false);
+  if (rc != PSCA_OK) return rc;
+  if (L > 64) return PSCA_ENOTSUP;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PSCA_EHIP;
+  return run_layer_backward(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, rho, x_in, v, grad_x,
+                            grad_rho, status, as_stream(stream));
 }
 
 #ifdef PSCA_PHASE_TRACE

@@ -1,0 +1,124 @@
+"""The unrolled PSCA network (PSCA-Net): K layers, layer k one iteration of
+Algorithm 1 with its own learned step size rho_k in [0, 1]; trained end to
+end on the binary cross-entropy of the last iterate against the true
+activity (eq. Loss_alpha on alpha~ for known pathloss, eq. Loss_gamma on
+gamma~ / g for unknown pathloss), with Adam; the detection threshold is
+chosen afterwards on validation data.
+
+Forward and backward run in the HIP kernels: psca_net_forward records every
+iterate; the backward pass calls psca_layer_backward from the last layer to
+the first, recomputing Sigma^-1 from each layer's input instead of storing
+it.  torch only carries the step-size parameters, the optimiser and the
+scalar loss.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import replace
+from typing import Optional
+
+import torch
+
+from . import psca as P
+
+
+def schedule(K: int, rho0: float = 0.5, decay: float = 0.5) -> list:
+    """rho_0 = rho0, rho_{k+1} = rho_k (1 - decay rho_k): the initial step sizes."""
+    out, rho = [], rho0
+    for _ in range(K):
+        out.append(rho)
+        rho = rho * (1.0 - decay * rho)
+    return out
+
+
+class _Unrolled(torch.autograd.Function):
+    """x^(K) of the unrolled network as a function of the step sizes."""
+
+    @staticmethod
+    def forward(fctx, rhos, Sigma_hat, S, params, pctx):
+        rho_dev = rhos.detach().to(S.device, torch.float32).contiguous()
+        prm = replace(params, iters=rhos.numel(), rho=rho_dev)
+        hist = P.net_forward(Sigma_hat, S, prm, ctx=pctx)
+        fctx.save_for_backward(rho_dev.clone(), hist)
+        fctx.rho_device = rhos.device
+        fctx.inputs = (Sigma_hat, S, params, pctx)
+        return hist[-1].clone()
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        rhos, hist = fctx.saved_tensors
+        Sigma_hat, S, params, pctx = fctx.inputs
+        host_rhos = rhos.cpu().tolist()
+        v = grad_out.contiguous().float()
+        grads = []
+        for k in range(len(host_rhos) - 1, -1, -1):
+            v, g = P.layer_backward(Sigma_hat, S, params, float(host_rhos[k]), hist[k].contiguous(), v, ctx=pctx)
+            grads.append(g)
+        d_rho = torch.cat(grads[::-1]).to(fctx.rho_device)
+        return d_rho, None, None, None, None
+
+
+def bce(x: torch.Tensor, alpha: torch.Tensor, g: Optional[torch.Tensor], known: bool, clamp: float = 1e-7):
+    """Eq. Loss_alpha (known pathloss: z = alpha~) or eq. Loss_gamma
+    (z = gamma~ / g), mean over devices; z clamped to [clamp, 1 - clamp].
+    Evaluated in float64: in float32, 1 - 1e-7 rounds to 1 - 1.19e-7."""
+    x = x.double()
+    z = x if known else x / g.double()
+    z = z.clamp(clamp, 1.0 - clamp)
+    a = alpha.double()
+    return -(a * torch.log(z) + (1.0 - a) * torch.log(1.0 - z)).mean()
+
+
+class PscaNet(torch.nn.Module):
+    """K-layer unrolled PSCA for one estimator (params.variant)."""
+
+    def __init__(self, K: int, params: P.Params, ctx: Optional[P.Context] = None):
+        super().__init__()
+        self.params = params
+        self.ctx = ctx
+        self.rho = torch.nn.Parameter(torch.tensor(schedule(K), dtype=torch.float32))
+        self.theta = 0.5
+
+    @property
+    def known(self) -> bool:
+        return self.params.variant in (P.ML_K, P.MAP_K)
+
+    def forward(self, Sigma_hat: torch.Tensor, S: torch.Tensor, params: Optional[P.Params] = None):
+        prm = params or self.params
+        return _Unrolled.apply(self.rho, Sigma_hat, S, prm, self.ctx or P.default_context(S.device))
+
+    def project(self):
+        """Keep every step size in [0, 1] after an optimiser step."""
+        with torch.no_grad():
+            self.rho.clamp_(0.0, 1.0)
+
+
+def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch) -> float:
+    """One Adam step on a minibatch of (Sigma_hat, S, params, alpha, g)."""
+    opt.zero_grad()
+    total = 0.0
+    for Sh, S, prm, alpha, g in batch:
+        x = net(Sh, S, prm)
+        loss = bce(x, alpha, g, net.known) / len(batch)
+        loss.backward()
+        total += float(loss.detach())
+    opt.step()
+    net.project()
+    return total
+
+
+def choose_threshold(scores, truths) -> float:
+    """Threshold minimising the average error rate ||alpha^ - alpha||_1 / n
+    over validation data (detection is score >= threshold)."""
+    import numpy as np
+    s = np.concatenate([np.asarray(t.detach().cpu(), dtype=np.float64).ravel() for t in scores])
+    a = np.concatenate([np.asarray(t.detach().cpu(), dtype=np.float64).ravel() for t in truths]) > 0.5
+    order = np.argsort(s, kind="stable")
+    s, a = s[order], a[order]
+    n = s.size
+    miss_before = np.concatenate([[0], np.cumsum(a)])            # actives below index i
+    inactive_from = (~a)[::-1].cumsum()[::-1]                    # inactives at index >= i
+    first = np.concatenate([[True], s[1:] != s[:-1]])            # first index of each distinct score
+    idx = np.nonzero(first)[0]
+    err = (miss_before[idx] + inactive_from[idx]) / n
+    return float(s[idx[int(np.argmin(err))]])

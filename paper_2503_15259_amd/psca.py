@@ -301,6 +301,49 @@ def iterate(Sigma_hat: torch.Tensor, S: torch.Tensor, x: torch.Tensor, rho: floa
     return x_next, q, r, xt
 
 
+def net_forward(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Context] = None,
+                stream=None, status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """psca_net_forward: params.iters layers (step sizes params.rho, or the
+    schedule), every iterate recorded.  Returns x_hist [(iters + 1), N]."""
+    ctx = ctx or default_context(S.device)
+    _need(S, torch.complex64, ctx.device, "S")
+    _need(Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
+    S = colmajor(S)
+    Sigma_hat = colmajor(Sigma_hat)
+    L, n = S.shape
+    params.check_tensors(ctx.device, n)
+    hist = torch.empty((params.iters + 1, n), dtype=torch.float32, device=ctx.device)
+    c = params.to_c()
+    N.check(ctx._lib.psca_net_forward(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c), _ptr(hist),
+                                      _ptr(status), _stream(ctx.device, stream)), "psca_net_forward")
+    return hist
+
+
+def layer_backward(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, rho: float, x_in: torch.Tensor,
+                   v: torch.Tensor, ctx: Optional[Context] = None, stream=None,
+                   status: Optional[torch.Tensor] = None):
+    """psca_layer_backward: (dL/dx, dL/drho) of one layer from v = dL/dx'.
+    dL/drho is returned as a one-element device tensor."""
+    ctx = ctx or default_context(S.device)
+    _need(S, torch.complex64, ctx.device, "S")
+    _need(Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
+    _need(x_in, torch.float32, ctx.device, "x_in")
+    _need(v, torch.float32, ctx.device, "v")
+    S = colmajor(S)
+    Sigma_hat = colmajor(Sigma_hat)
+    L, n = S.shape
+    if x_in.numel() != n or v.numel() != n or not x_in.is_contiguous() or not v.is_contiguous():
+        raise ValueError("x_in and v must be contiguous float32 vectors of length N")
+    params.check_tensors(ctx.device, n)
+    gx = torch.empty(n, dtype=torch.float32, device=ctx.device)
+    gr = torch.empty(1, dtype=torch.float32, device=ctx.device)
+    c = params.to_c()
+    N.check(ctx._lib.psca_layer_backward(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c),
+                                         ctypes.c_float(rho), _ptr(x_in), _ptr(v), _ptr(gx), _ptr(gr),
+                                         _ptr(status), _stream(ctx.device, stream)), "psca_layer_backward")
+    return gx, gr
+
+
 def threshold(x: torch.Tensor, theta: float, stream=None) -> torch.Tensor:
     """support = 1[x >= theta] (psca_threshold)."""
     lib = N.load()

@@ -1,0 +1,131 @@
+"""Unrolled network (PSCA-Net) on the GPU against the FP64 oracle: the
+per-layer backward kernel, the recorded forward pass, the step-size gradient
+and a short training run (needs an MI355X)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2503_15259_amd import instances as I
+from parity import assert_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [O.ML_K, O.MAP_K, O.ML_UD, O.MAP_UR]
+EPS = float(np.float32(0.01))
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_15259_amd import psca
+    return psca
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def c64(a):
+    return torch.from_numpy(np.ascontiguousarray(a).astype(np.complex64)).to(dev())
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).astype(np.float32)).to(dev())
+
+
+def params_for(P, inst, variant, iters=1):
+    kw = dict(variant=variant, iters=iters, sigma2=inst.sigma2, M=inst.M, d_lo=inst.d_lo, d_hi=inst.d_hi,
+              pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS)
+    if variant in O.KNOWN_PATHLOSS:
+        kw["g"] = f32(inst.g)
+    if variant == O.MAP_K:
+        kw["p"] = f32(np.full(inst.N, inst.p))
+    return P.Params(**kw)
+
+
+CASES = [(20, 8, 64), (100, 20, 32), (300, 64, 128)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("N,L,M", CASES)
+def test_layer_backward_matches_oracle_vjp(P, variant, N, L, M):
+    inst = I.make_instance(3, 500 + N + L, N, L, M, 0.2).fp32_inputs()
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    _, hist = O.psca(prob, 6, record=True)
+    x = np.asarray(hist[5].x, np.float32).astype(np.float64)   # the input the kernel sees
+    rho = 0.3
+    v = np.random.default_rng(N + L + variant).standard_normal(N)
+    v = v.astype(np.float32).astype(np.float64)
+    dx_ref, drho_ref = O.layer_vjp(prob, x, rho, v)
+    Sh = P.sample_cov(c64(inst.Y))
+    status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+    print(f"[layer backward {O.VARIANT_NAMES[variant]} N={N} L={L} M={M}]", flush=True)
+    gx, gr = P.layer_backward(Sh, c64(inst.S), params_for(P, inst, variant), rho, f32(x), f32(v), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    gx = gx.cpu().numpy().astype(np.float64)
+    scale = np.max(np.abs(dx_ref))
+    err = np.max(np.abs(gx - dx_ref)) / scale
+    assert err < 2e-3, (O.VARIANT_NAMES[variant], N, L, err)
+    assert float(gr.item()) == pytest.approx(drho_ref, rel=2e-3, abs=1e-6 * np.sum(np.abs(v)) * np.max(np.abs(x)))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_net_forward_records_the_oracle_trajectory(P, variant):
+    inst = I.workload_instance("small", 3).fp32_inputs()
+    rhos = np.random.default_rng(variant).uniform(0.2, 0.8, 8).astype(np.float32)
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    ref = O.net_forward(prob, rhos.astype(np.float64))
+    prm = params_for(P, inst, variant, iters=8)
+    prm.rho = torch.from_numpy(rhos).to(dev())
+    hist = P.net_forward(P.sample_cov(c64(inst.Y)), c64(inst.S), prm)
+    torch.cuda.synchronize()
+    assert hist.shape == (9, inst.N)
+    assert torch.count_nonzero(hist[0]) == 0
+    for k in range(1, 9):
+        assert_parity(hist[k].cpu().numpy().astype(np.float64), ref[k], variant, f"layer {k}")
+
+
+@pytest.mark.parametrize("variant", [O.ML_K, O.MAP_K, O.ML_UD])
+def test_network_step_size_gradient_matches_oracle(P, variant):
+    """Whole-network gradient against the oracle's reverse accumulation.  MAP-UR
+    is covered layer by layer above: after a few layers many gamma~/g sit at
+    the BCE clamp and near the prior's branch points, where the FP32 and FP64
+    trajectories need not take the same branch."""
+    from paper_2503_15259_amd import net as NET
+    inst = I.make_instance(3, 900 + variant, 60, 16, 64, 0.2).fp32_inputs()
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    K = 5
+    rhos = np.asarray(NET.schedule(K), np.float32).astype(np.float64)
+    loss_ref, g_ref = O.net_loss_and_grad(prob, rhos, inst.alpha, inst.g)
+    model = NET.PscaNet(K, params_for(P, inst, variant))
+    Sh = P.sample_cov(c64(inst.Y))
+    x = model(Sh, c64(inst.S))
+    loss = NET.bce(x, f32(inst.alpha), f32(inst.g), model.known)
+    loss.backward()
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(loss_ref, rel=1e-3)
+    got = model.rho.grad.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, g_ref, rtol=5e-3, atol=5e-3 * np.max(np.abs(g_ref)))
+
+
+def test_training_lowers_the_loss(P):
+    """A few Adam steps of an ML-UD network on generated instances lower the
+    training loss and keep every step size in [0, 1]."""
+    from paper_2503_15259_amd import net as NET
+    insts = [I.make_instance(I.WORKLOAD_IDS["net"], 10 + k, 100, 20, 32, 0.1).fp32_inputs() for k in range(4)]
+    model = NET.PscaNet(6, params_for(P, insts[0], O.ML_UD))
+    batch = []
+    for inst in insts:
+        prm = params_for(P, inst, O.ML_UD)
+        batch.append((P.sample_cov(c64(inst.Y)), c64(inst.S), prm, f32(inst.alpha), f32(inst.g)))
+    opt = torch.optim.Adam(model.parameters(), lr=2e-2)
+    losses = [NET.train_step(model, opt, batch) for _ in range(12)]
+    torch.cuda.synchronize()
+    assert losses[-1] < losses[0], losses
+    r = model.rho.detach().cpu().numpy()
+    assert np.all(r >= 0.0) and np.all(r <= 1.0)
