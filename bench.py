@@ -249,6 +249,116 @@ def run_uneven(args):
 
 
 # ---------------------------------------------------------------------------
+# Unrolled network vs plain PSCA at the same equal-error rate
+# ---------------------------------------------------------------------------
+NET_EVAL = 32          # evaluation instances (seeds disjoint from training and validation)
+NET_BATCH = 8          # detections per timed launch
+PSCA_MAX_ITERS = 200
+
+
+def run_net(args):
+    import numpy as np
+    import torch
+    from paper_2503_15259_amd import instances as I
+    from paper_2503_15259_amd import metrics
+    from paper_2503_15259_amd import psca as P
+
+    path = os.path.join(ROOT, "paper_2503_15259_amd", "data", f"net_{args.net_variant}_K20.json")
+    with open(path) as f:
+        trained = json.load(f)
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    variant = P.VARIANTS[trained["variant"]]
+    tr = trained["train"]
+    K = trained["K"]
+    rho = torch.tensor(trained["rho"], dtype=torch.float32, device=dev)
+    ctx = P.Context(0)
+    wid = I.WORKLOAD_IDS["net"]
+    insts = [I.make_instance(wid, 2 * 10 ** 6 + i, tr["N"], tr["L"], tr["M"], tr["p"]) for i in range(NET_EVAL)]
+    data = []
+    for inst in insts:
+        S = P.colmajor(torch.from_numpy(inst.S.astype(np.complex64)).to(dev))
+        Y = P.colmajor(torch.from_numpy(inst.Y.astype(np.complex64)).to(dev))
+        g = torch.from_numpy(inst.g.astype(np.float32)).to(dev)
+        kw = dict(variant=variant, sigma2=inst.sigma2, M=inst.M, d_lo=inst.d_lo, d_hi=inst.d_hi,
+                  pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=tr["eps"])
+        if variant in (P.ML_K, P.MAP_K):
+            kw["g"] = g
+        if variant == P.MAP_K:
+            kw["p"] = torch.full((inst.N,), inst.p, dtype=torch.float32, device=dev)
+        data.append((P.sample_cov(Y, ctx=ctx), S, kw))
+    truth = np.concatenate([x.alpha for x in insts])
+
+    # equal-error rates: the network, and plain PSCA after every k <= 200
+    net_scores, hists = [], []
+    for Sh, S, kw in data:
+        net_scores.append(P.net_forward(Sh, S, P.Params(iters=K, rho=rho, **kw), ctx=ctx)[-1].cpu().numpy())
+        hists.append(P.net_forward(Sh, S, P.Params(iters=PSCA_MAX_ITERS, **kw), ctx=ctx).cpu().numpy())
+    eer_net = metrics.equal_error_point(np.concatenate(net_scores), truth)[0]
+    eer_psca = [metrics.equal_error_point(np.concatenate([h[k] for h in hists]), truth)[0]
+                for k in range(1, PSCA_MAX_ITERS + 1)]
+    matched = [k for k in range(1, PSCA_MAX_ITERS + 1) if eer_psca[k - 1] <= eer_net]
+    k_star = matched[0] if matched else PSCA_MAX_ITERS
+
+    def throughput(iters, rho_t):
+        probs = [P.Problem(Sigma_hat=data[b][0], S=data[b][1],
+                           params=P.Params(iters=iters, rho=rho_t, **data[b][2])) for b in range(NET_BATCH)]
+        plan = P.Plan(probs, ctx=ctx)
+        stream = torch.cuda.current_stream(dev)
+        for _ in range(args.warmup):
+            plan.launch()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(stream)
+            plan.launch()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        team = plan.team_size
+        plan.close()
+        return NET_BATCH / (ms / 1e3), ms, team
+
+    net_ips, net_ms, team = throughput(K, rho)
+    psca_ips, psca_ms, _ = throughput(k_star, None)
+    psca100_ips, _, _ = throughput(100, None)
+    N, L = tr["N"], tr["L"]
+    flops = NET_BATCH * K * iteration_flops(N, L)
+    achieved = flops / (net_ms / 1e3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": round(net_ips, 3),
+        "unit": "instances/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(net_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"unrolled {trained['variant']} network, K={K} trained layers, against plain "
+                               f"PSCA at the same equal-error rate; N={N}, L={L}, M={tr['M']}, p={tr['p']}; "
+                               f"{NET_BATCH} detections per launch",
+                   "K": K, "team_size": team, "eval_instances": NET_EVAL},
+        "equal_error": {"net": round(eer_net, 5), "psca_at_k_star": round(eer_psca[k_star - 1], 5),
+                        "psca_100": round(eer_psca[99], 5), "k_star": k_star, "matched": bool(matched)},
+        "psca_at_k_star_instances_per_s": round(psca_ips, 3),
+        "psca_100_instances_per_s": round(psca100_ips, 3),
+        "net_speedup_vs_psca_at_k_star": round(net_ips / psca_ips, 3),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
+                     "kernel": "k_psca_teams (network, %d layers)" % K, "flops_per_launch": flops,
+                     "avg_launch_ms": round(net_ms, 4)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
 # GPU leg
 # ---------------------------------------------------------------------------
 
@@ -260,10 +370,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain copy kernel of this many MiB (profiler calibration)")
-    ap.add_argument("--workload", choices=["single", "uneven"], default="single",
+    ap.add_argument("--workload", choices=["single", "uneven", "net"], default="single",
                     help="single: the four estimators on N=1000, L=64 (default); uneven: a batch of "
                          "independent ML-UD instances of mixed sizes in one persistent launch")
     ap.add_argument("--instances", type=int, default=4096, help="uneven workload: instances per batch")
+    ap.add_argument("--net-variant", default="MAP-UR", help="net workload: estimator of the trained network")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the team-size autotuner that runs before timing")
     ap.add_argument("--team-size", type=int, default=0,
@@ -280,6 +391,9 @@ def main():
 
     if args.workload == "uneven":
         run_uneven(args)
+        return
+    if args.workload == "net":
+        run_net(args)
         return
 
     cpu_info, cpu_x, cpu_x64 = (None, {}, {})
