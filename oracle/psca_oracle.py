@@ -57,7 +57,9 @@ def sample_covariance(Y: np.ndarray) -> np.ndarray:
 def model_covariance(S: np.ndarray, w: np.ndarray, sigma2: float) -> np.ndarray:
     """Sigma = S Diag(w) S^H + sigma^2 I  (w = g*alpha or gamma)."""
     L = S.shape[0]
-    return S @ np.diag(np.asarray(w, dtype=np.float64)) @ S.conj().T + sigma2 * np.eye(L)
+    # S Diag(w): column n of S scaled by w_n (the same products as the dense
+    # diagonal matrix, without forming an N x N array)
+    return (S * np.asarray(w, dtype=np.float64)[None, :]) @ S.conj().T + sigma2 * np.eye(L)
 
 
 def frobenius_inverse(Sigma: np.ndarray) -> np.ndarray:
