@@ -60,8 +60,12 @@ typedef enum {
   PSCA_ESYNC = -6     /* a device-wide barrier timed out (device status word only) */
 } psca_status;
 
-/* Largest pilot length L handled on chip (the L x L factor lives in LDS). */
-#define PSCA_MAX_L 96
+/* Largest pilot length L.  Up to 96 the L x L work matrix lives in each
+ * workgroup's LDS; from 97 to 256 a single detection factors Sigma in device
+ * memory cooperatively across its workgroups (psca_detect, psca_detect_y,
+ * psca_iterate, psca_net_forward).  psca_detect_batch and its plans take
+ * L <= 96, psca_layer_backward L <= 64 (PSCA_ENOTSUP beyond). */
+#define PSCA_MAX_L 256
 
 /*
  * Parameters of one detection (Algorithm 1 inputs besides SigmaHat and S).
@@ -180,7 +184,7 @@ typedef struct {
  * for a batch of the same (L, N) list, else a default (one team per instance
  * when the batch fits the GPU at once, else the smallest teams).  Every
  * instance is validated as in psca_detect before anything is launched
- * (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one). */
+ * (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one; L <= 96). */
 int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream);
 
 /* Autotuner for psca_detect_batch: times the batch with every candidate team

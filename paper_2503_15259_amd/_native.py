@@ -18,7 +18,7 @@ PSCA_ENOTSUP = -5
 PSCA_ESYNC = -6
 
 ML_K, MAP_K, ML_UD, MAP_UR = 0, 1, 2, 3
-MAX_L = 96
+MAX_L = 256
 
 # every symbol include/psca.h declares
 EXPORTED = (

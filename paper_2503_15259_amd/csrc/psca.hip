@@ -48,7 +48,8 @@ namespace {
 
 constexpr int kThreads = 256;                              // helper kernels
 constexpr int kBlk = 16;
-constexpr int kMaxL = PSCA_MAX_L;                          // 96
+constexpr int kMaxL = PSCA_MAX_L;                          // 256 (above 96: the cooperative large-L kernel)
+constexpr int kMaxLdsL = 96;                               // largest L whose L x L matrix lives in LDS
 constexpr int kMaxNcb = 4;                                 // column blocks per workgroup
 constexpr unsigned kSpinLimit = 1u << 20;                  // grid-barrier wait bound
 
@@ -1216,6 +1217,367 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
   if (threadIdx.x == 0) *out = sh[0];
 }
 
+// ---------------------------------------------------------------------------
+// Pilot lengths above 96: the L x L matrix no longer fits a workgroup's LDS
+// ---------------------------------------------------------------------------
+// Sigma stays packed in memory (lower 16x16 blocks, column-major inside) and
+// the instance's workgroups factor it together: every workgroup factors the
+// diagonal block J redundantly in registers and keeps W_JJ = L_JJ^-1 in LDS;
+// the panel blocks L_IJ = A_IJ W_JJ^H and then the trailing updates
+// A_IK -= L_IJ L_KJ^H are spread over all wavefronts of the instance, with a
+// device-wide barrier after each.  Each workgroup then solves its own tile
+// locally: Y = L^-1 S_t (q = |y|^2), B = L^-H Y, and
+// q - r = b^H (Sigma - SigmaHat) b with Sigma from a copy kept before the
+// factorisation.
+constexpr int kLargeMaxLp = 256;
+
+struct LargeArgs {
+  CoopArgs c;             // sigma: packed Sigma, factored in place into L
+  float2 *sigma_copy;     // packed Sigma of the iteration
+};
+
+__host__ __device__ inline size_t lds_large_bytes(int Lp, int NT, int waves) {
+  const size_t f2 = (size_t)Lp * (NT + 1) + (size_t)(Lp / 16) * 256 + (size_t)waves * 256;
+  const size_t fl = 3 * (size_t)NT + 2 * (size_t)(Lp / 16) * NT;
+  return f2 * sizeof(float2) + fl * 4;
+}
+
+__device__ __forceinline__ const float2 *pblk(const float2 *packed, int I, int J) {
+  return packed + (size_t)blk_index(I, J) * 256;
+}
+
+template <int THREADS>
+__device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
+  const CoopArgs &A = Lg.c;
+  constexpr int kWaves = THREADS / 64;
+  extern __shared__ float4 smem_raw[];
+  __shared__ int s_ok, s_pd;
+  const int Lp = (A.L + 15) & ~15, Lb = Lp / 16, NB = Lb * (Lb + 1) / 2, E = NB * 256;
+  const int NT = A.NT, PT = A.NT + 1, ncb = A.ncb;
+  float2 *Yt = (float2 *)smem_raw;     // [Lp][PT] tile: S, then Y = L^-1 S, then B = L^-H Y
+  float2 *Wd = Yt + Lp * PT;           // [Lb][256] W_JJ, column-major blocks
+  float2 *scr = Wd + Lb * 256;         // [kWaves][256]
+  float *xs = (float *)(scr + kWaves * 256);
+  float *gs = xs + NT, *ls = gs + NT;
+  float *red_q = ls + NT;              // [Lb][NT]
+  float *red_r = red_q + Lb * NT;      // [Lb][NT]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lq = lane >> 4;
+  const int n0 = g * NT;
+  const int gwave = g * kWaves + wave, nwaves = A.G * kWaves;
+  unsigned gen = 0;
+  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
+  float2 *sig = A.sigma;
+
+  for (int c = tid; c < NT; c += THREADS) {
+    const int n = n0 + c;
+    const bool in = n < A.N;
+    xs[c] = (in && A.x_in) ? A.x_in[n] : 0.0f;
+    if (in && A.x_hist) A.x_hist[n] = xs[c];
+    gs[c] = (in && A.a.g) ? A.a.g[n] : 0.0f;
+    float lg = 0.0f;
+    if (in && A.a.p) {
+      const float pn = A.a.p[n];
+      lg = logf(pn / (1.0f - pn));
+    }
+    ls[c] = lg;
+  }
+  auto s_at = [&](int i, int c) -> float2 {   // S element (row i, tile column c), zero outside
+    const int n = n0 + c;
+    return (i < A.L && n < A.N) ? A.S[(size_t)n * A.L + i] : make_float2(0.f, 0.f);
+  };
+
+  double rho_d = A.rho0;
+  bool failed = false, aborted = false;
+  for (int it = 0; it < A.iters; ++it) {
+    // ---- A. packed Gram partial of the tile, S read from memory
+    for (int c = tid; c < NT; c += THREADS) red_q[c] = known ? gs[c] * xs[c] : xs[c];
+    __syncthreads();
+    for (int b = wave; b < NB; b += kWaves) {
+      int I, J;
+      blk_coords(b, I, J);
+      f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+      for (int cb = 0; cb < ncb; ++cb) {
+        float2 av4[4], bv4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int c = 16 * cb + 4 * ks + lq;
+          const float2 sv = s_at(16 * J + l16, c);
+          const float w = red_q[c];
+          av4[ks] = s_at(16 * I + l16, c);
+          bv4[ks] = make_float2(w * sv.x, -w * sv.y);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(av4[ks], bv4[ks], cr, ci);
+      }
+      float4 *o = (float4 *)(A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + 4 * lq);
+      o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
+      o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
+    }
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+
+    // ---- B. reduce a slice into Sigma and its copy
+    {
+      const int per = (E + A.G - 1) / A.G;
+      const int start = g * per, end = min(E, start + per);
+      for (int e = start + tid; e < end; e += THREADS) {
+        float2 sm = make_float2(0.f, 0.f);
+        for (int h = 0; h < A.G; ++h) {
+          const float2 v = A.partials[(size_t)h * A.pstride + e];
+          sm.x += v.x;
+          sm.y += v.y;
+        }
+        const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+        int I, J;
+        blk_coords(b, I, J);
+        if (I == J && ii == jj) {
+          sm.x += (16 * I + ii < A.L) ? A.sigma2 : 1.0f;
+          sm.y = 0.0f;
+        }
+        sig[e] = sm;
+        Lg.sigma_copy[e] = sm;
+      }
+    }
+    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+
+    // ---- C1. cooperative blocked Cholesky in memory
+    for (int J = 0; J < Lb; ++J) {
+      float2 *Wj = Wd + J * 256;
+      for (int e = tid; e < 256; e += THREADS) Wj[e] = pblk(sig, J, J)[e];
+      __syncthreads();
+      if (wave == 0) {
+        const bool ok = leaf_chol(Wj, 16, lane);
+        if (lane == 0) s_pd = ok ? 1 : 0;
+      }
+      __syncthreads();
+      if (!s_pd) {   // uniform: every workgroup factors the same block
+        failed = true;
+        break;
+      }
+      if (J + 1 == Lb) break;
+      for (int I = J + 1 + gwave; I < Lb; I += nwaves) {   // panel L_IJ = A_IJ W_JJ^H
+        float2 *blk = sig + (size_t)blk_index(I, J) * 256;
+        f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = 4 * ks + lq;
+          a4[ks] = blk[k * 16 + l16];
+          const float2 w = Wj[k * 16 + l16];
+          b4[ks] = make_float2(w.x, -w.y);
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) blk[l16 * 16 + 4 * lq + v] = make_float2(cr[v], ci[v]);
+      }
+      if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+      {   // trailing A_IK -= L_IJ L_KJ^H, J < K <= I
+        const int m = Lb - 1 - J;
+        for (int t = gwave; t < m * (m + 1) / 2; t += nwaves) {
+          int ii = 0;
+          while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+          const int I = J + 1 + ii, K = J + 1 + (t - ii * (ii + 1) / 2);
+          float2 *dst = sig + (size_t)blk_index(I, K) * 256;
+          const float2 *lij = pblk(sig, I, J), *lkj = pblk(sig, K, J);
+          f4 cr, ci;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float2 c = dst[l16 * 16 + 4 * lq + v];
+            cr[v] = c.x;
+            ci[v] = c.y;
+          }
+          float2 a4[4], b4[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lq;
+            const float2 l = lij[k * 16 + l16];
+            a4[ks] = make_float2(-l.x, -l.y);
+            const float2 r = lkj[k * 16 + l16];
+            b4[ks] = make_float2(r.x, -r.y);
+          }
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) dst[l16 * 16 + 4 * lq + v] = make_float2(cr[v], ci[v]);
+        }
+      }
+      if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+    }
+    if (failed || aborted) break;
+
+    // ---- C4. local solves: Y = L^-1 S_t, q = |y|^2, B = L^-H Y
+    for (int e = tid; e < Lp * NT; e += THREADS) {
+      const int c = e / Lp, i = e - c * Lp;
+      Yt[i * PT + c] = s_at(i, c);
+    }
+    __syncthreads();
+    for (int I = 0; I < Lb; ++I) {   // forward: Y_I = W_II (S_I - sum_{K<I} L_IK Y_K)
+      for (int cb = wave; cb < ncb; cb += kWaves) {
+        f4 tr, ti;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float2 y = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
+          tr[v] = y.x;
+          ti[v] = y.y;
+        }
+        for (int K = 0; K < I; ++K) {
+          const float2 *lik = pblk(sig, I, K);
+          float2 a4[4], b4[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lq;
+            const float2 l = lik[k * 16 + l16];
+            a4[ks] = make_float2(-l.x, -l.y);
+            b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
+          }
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], tr, ti);
+        }
+        float2 *T = scr + wave * 256;   // row-major staging of the right-hand side
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = make_float2(tr[v], ti[v]);
+        wave_lds_sync();
+        f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = 4 * ks + lq;
+          a4[ks] = Wd[I * 256 + k * 16 + l16];   // W_II[l16][k]
+          b4[ks] = T[k * 16 + l16];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(yr[v], yi[v]);
+        wave_lds_sync();
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < Lb * NT; e += THREADS) {   // q per row block and column
+      const int I = e / NT, c = e - I * NT;
+      float acc = 0.0f;
+      for (int i = 16 * I; i < 16 * I + 16; ++i) {
+        const float2 y = Yt[i * PT + c];
+        acc += y.x * y.x + y.y * y.y;
+      }
+      red_q[I * NT + c] = acc;
+    }
+    __syncthreads();
+    for (int I = Lb - 1; I >= 0; --I) {   // backward: B_I = W_II^H (Y_I - sum_{K>I} L_KI^H B_K)
+      for (int cb = wave; cb < ncb; cb += kWaves) {
+        f4 tr, ti;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float2 y = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
+          tr[v] = y.x;
+          ti[v] = y.y;
+        }
+        for (int K = I + 1; K < Lb; ++K) {
+          const float2 *lki = pblk(sig, K, I);
+          float2 a4[4], b4[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lq;
+            const float2 l = lki[l16 * 16 + k];   // L_KI[k][l16]; A = -conj of it
+            a4[ks] = make_float2(-l.x, l.y);
+            b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
+          }
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], tr, ti);
+        }
+        float2 *T = scr + wave * 256;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = make_float2(tr[v], ti[v]);
+        wave_lds_sync();
+        f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = 4 * ks + lq;
+          const float2 w = Wd[I * 256 + l16 * 16 + k];   // W_II[k][l16]; A = conj of it
+          a4[ks] = make_float2(w.x, -w.y);
+          b4[ks] = T[k * 16 + l16];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(yr[v], yi[v]);
+        wave_lds_sync();
+      }
+      __syncthreads();
+    }
+    // q - r = b^H (Sigma - SigmaHat) b
+    for (int t = wave; t < Lb * ncb; t += kWaves) {
+      const int I = t / ncb, cb = t - I * ncb;
+      f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+      for (int K = 0; K < Lb; ++K) {
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int i = 16 * I + l16, k = 16 * K + 4 * ks + lq;
+          float2 sg;
+          if (I >= K) {
+            sg = Lg.sigma_copy[(size_t)blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
+          } else {
+            const float2 tt = Lg.sigma_copy[(size_t)blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
+            sg = make_float2(tt.x, -tt.y);
+          }
+          const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+          a4[ks] = make_float2(sg.x - sh.x, sg.y - sh.y);
+          b4[ks] = Yt[k * PT + 16 * cb + l16];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+      }
+      float rp = 0.0f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float2 bv = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
+        rp += bv.x * cr[v] + bv.y * ci[v];
+      }
+      rp += __shfl_xor(rp, 16);
+      rp += __shfl_xor(rp, 32);
+      if (lq == 0) red_r[I * NT + 16 * cb + l16] = rp;
+    }
+    __syncthreads();
+
+    // ---- C5. coordinate step and update
+    float rho;
+    if (A.rho_fixed >= 0.0f) rho = A.rho_fixed;
+    else if (A.rho_dev) rho = A.rho_dev[it];
+    else rho = (float)rho_d;
+    rho_d = rho_d * (1.0 - A.rho_decay * rho_d);
+    const bool last = (it == A.iters - 1);
+    for (int c = tid; c < NT; c += THREADS) {
+      const int n = n0 + c;
+      if (n < A.N) {
+        float q = 0.0f, qmr = 0.0f;
+        for (int I = 0; I < Lb; ++I) {
+          q += red_q[I * NT + c];
+          qmr += red_r[I * NT + c];
+        }
+        const float x = xs[c];
+        const float xt = coordinate_step(x, q, qmr, gs[c], ls[c], A.a);
+        xs[c] = (1.0f - rho) * x + rho * xt;
+        if (A.x_hist) A.x_hist[(size_t)(it + 1) * A.N + n] = xs[c];
+        if (last) {
+          if (A.q_out) A.q_out[n] = q;
+          if (A.r_out) A.r_out[n] = q - qmr;
+          if (A.xt_out) A.xt_out[n] = xt;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < NT; c += THREADS) {
+    const int n = n0 + c;
+    if (n < A.N) A.x_out[n] = xs[c];
+  }
+  if (g == 0 && tid == 0 && A.status) *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
+}
+
+__global__ void __launch_bounds__(512) k_psca_large(LargeArgs Lg) { large_body<512>(Lg, blockIdx.x); }
+
 template <int LPMAX, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
   psca_body<LPMAX, THREADS>(A, blockIdx.x);
@@ -1506,11 +1868,66 @@ void fill_args(CoopArgs &a, const float2 *Sh, const float2 *S, int L, int N, con
   a.status = status;
 }
 
+// Pilot lengths above 96: k_psca_large (cooperative factorisation in memory).
+int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm, int iters,
+              float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out, float *xt_out,
+              int32_t *status, hipStream_t st, float *x_hist) {
+  const int Lp = (L + 15) & ~15;
+  const KernelChoice kc{(const void *)k_psca_large, 512, Lp};
+  InstPlan p{};
+  for (int ncb = 1;; ++ncb) {
+    if (ncb > kMaxNcb) return PSCA_ENOTSUP;
+    const int NT = 16 * ncb, G = (N + NT - 1) / NT;
+    const size_t lds = lds_large_bytes(Lp, NT, 8);
+    if (lds > 159 * 1024) return PSCA_ENOTSUP;
+    const int cap = max_coresident(ctx, kc, lds);
+    if (cap <= 0) return PSCA_ENOTSUP;
+    if (G <= cap) {
+      p = InstPlan{Lp, ncb, NT, G, lds, 0};
+      break;
+    }
+  }
+  const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
+  const size_t o_pa = 0;
+  const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
+  const size_t o_cp = align_up(o_sig + E * sizeof(float2));
+  const size_t o_arr = align_up(o_cp + E * sizeof(float2));
+  const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
+  const size_t o_abt = align_up(o_rel + sizeof(unsigned));
+  const size_t o_st = align_up(o_abt + sizeof(unsigned));
+  const size_t total = align_up(o_st + sizeof(unsigned));
+  int rc = ensure_ws(ctx, total);
+  if (rc != PSCA_OK) return rc;
+  char *base = (char *)ctx->ws;
+  LargeArgs a;
+  fill_args(a.c, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
+  a.c.x_hist = x_hist;
+  a.c.partials = (float2 *)(base + o_pa);
+  a.c.pstride = E;
+  a.c.sigma = (float2 *)(base + o_sig);
+  a.c.bar.arrive = (unsigned *)(base + o_arr);
+  a.c.bar.release = (unsigned *)(base + o_rel);
+  a.c.bar.abort_flag = (int32_t *)(base + o_abt);
+  if (!a.c.status) a.c.status = (int32_t *)(base + o_st);
+  a.sigma_copy = (float2 *)(base + o_cp);
+  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.c.bar.arrive, p.G, a.c.bar.release,
+                     a.c.bar.abort_flag, a.c.status);
+  if ((rc = launch_ok()) != PSCA_OK) return rc;
+  void *args[] = {&a};
+  if (hipLaunchCooperativeKernel(kc.fn, dim3(p.G), dim3(512), args, (unsigned)p.lds, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  return PSCA_OK;
+}
+
 // Runs k_psca for `iters` iterations from x_in (null: zeros).
 int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
                int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
                float *xt_out, int32_t *status, hipStream_t st, float *x_hist = nullptr) {
   const int Lp = (L + 15) & ~15;
+  if (Lp > kMaxLdsL)
+    return run_large(ctx, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, st, x_hist);
   const KernelChoice kc = pick_kernel(Lp);
   InstPlan p{};
   for (int ncb = 1;; ++ncb) {   // occupancy depends on the tile's LDS
@@ -1853,6 +2270,7 @@ int validate_batch(int B, const psca_problem *pr) {
     if (!q.Sigma_hat || !q.S || !q.x_out) return PSCA_EINVAL;
     const int rc = validate_params(&q.prm, q.L, q.N, true);
     if (rc != PSCA_OK) return rc;
+    if (q.L > kMaxLdsL) return PSCA_ENOTSUP;   // batches keep the L x L matrix in LDS
   }
   return PSCA_OK;
 }

@@ -192,9 +192,14 @@ def test_host_validation_errors(P):
         P.detect_y(Y, S, P.Params(variant=O.ML_UD, iters=5, M=16, rho0=1.5))
     with pytest.raises(P.PscaError):
         P.detect_y(Y, S, P.Params(variant=O.MAP_UR, iters=5, M=16, eps=100.0))   # 2 eps >= g_l
-    big = I.make_instance(5, 4, 20, 97, 8, 0.2).fp32_inputs()
+    big = I.make_instance(5, 4, 20, 257, 8, 0.2).fp32_inputs()
     with pytest.raises(P.PscaError) as e:
         P.detect_y(c64(big.Y), c64(big.S), P.Params(variant=O.ML_UD, iters=5, M=8))
+    assert e.value.code == -5
+    mid = I.make_instance(5, 5, 20, 97, 8, 0.2).fp32_inputs()   # batches keep L x L in LDS
+    with pytest.raises(P.PscaError) as e:
+        P.detect_batch([P.Problem(Sigma_hat=P.sample_cov(c64(mid.Y)), S=c64(mid.S),
+                                  params=P.Params(variant=O.ML_UD, iters=5, M=8))])
     assert e.value.code == -5
 
 
@@ -358,3 +363,27 @@ def test_long_team_lists_finish_without_barrier_timeouts(P):
     for inst, x, ref in zip(insts, outs, refs):
         assert_parity(x.cpu().numpy().astype(np.float64), ref, O.ML_UD, "team lists " + label(inst, O.ML_UD, 10))
     plan.close()
+
+
+@pytest.mark.parametrize("N,L,M", [(50, 97, 32), (300, 130, 64), (200, 200, 256), (129, 256, 40)])
+def test_large_pilot_lengths_match_oracle(P, N, L, M):
+    """L above 96 (the cooperative factorisation in device memory)."""
+    inst = I.make_instance(5, 7000 + N + L, N, L, M, 0.2).fp32_inputs()
+    for variant in (O.ML_K, O.ML_UD, O.MAP_UR):
+        iters = 15
+        ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
+        print(label(inst, variant, iters), flush=True)
+        got = run_gpu(P, inst, variant, iters)
+        assert_parity(got, ref, variant, label(inst, variant, iters))
+
+
+def test_large_scale_workload_size(P):
+    """The large-scale size, N = 10^4 devices, L = 200, M = 256 (p = 0.05):
+    ten iterations of ML-K and MAP-UR, every device against the oracle."""
+    inst = I.workload_instance("large", 0).fp32_inputs()
+    for variant in (O.ML_K, O.MAP_UR):
+        iters = 10
+        ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
+        print(label(inst, variant, iters), flush=True)
+        got = run_gpu(P, inst, variant, iters)
+        assert_parity(got, ref, variant, label(inst, variant, iters))
