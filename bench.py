@@ -249,6 +249,70 @@ def run_uneven(args):
 
 
 # ---------------------------------------------------------------------------
+# Large scale: N = 10^4 devices, L = 200, M = 256, one detection per launch
+# ---------------------------------------------------------------------------
+LARGE_POOL = 4
+
+
+def run_large(args):
+    import numpy as np
+    import torch
+    from paper_2503_15259_amd import instances as I
+    from paper_2503_15259_amd import psca as P
+
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = I.WORKLOADS["large"]
+    N, L, M, iters = w["N"], w["L"], w["M"], w["iters"]
+    insts = [I.workload_instance("large", i) for i in range(LARGE_POOL)]
+    ctx = P.Context(0)
+    data = []
+    for inst in insts:
+        S = P.colmajor(torch.from_numpy(inst.S.astype(np.complex64)).to(dev))
+        Y = P.colmajor(torch.from_numpy(inst.Y.astype(np.complex64)).to(dev))
+        g = torch.from_numpy(inst.g.astype(np.float32)).to(dev)
+        data.append((Y, S, g, inst))
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for name, variant in (("ML-K", P.ML_K), ("MAP-UR", P.MAP_UR)):
+        def one(i):
+            Y, S, g, inst = data[i % LARGE_POOL]
+            prm = P.Params(variant=variant, iters=iters, sigma2=inst.sigma2, M=M, d_lo=inst.d_lo,
+                           d_hi=inst.d_hi, pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS,
+                           g=g if variant == P.ML_K else None)
+            return P.detect_y(Y, S, prm, ctx=ctx)
+        for i in range(args.warmup):
+            one(i)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for i, (a, b) in enumerate(ev):
+            a.record(stream)
+            one(i)
+            b.record(stream)
+        torch.cuda.synchronize()
+        res[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms = float(np.mean(list(res.values())))
+    flops = iters * iteration_flops(N, L)
+    achieved = flops / (ms / 1e3) / 1e12
+    line = {
+        "metric": METRIC, "value": round(1e3 / ms, 4), "unit": "instances/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"large-scale PSCA, one detection per launch: N={N}, L={L}, M={M}, "
+                               f"p={w['p']}, {iters} iterations, ML-K and MAP-UR",
+                   "N": N, "L": L, "M": M, "iters": iters},
+        "per_estimator_ms": {k: round(v, 3) for k, v in res.items()},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
+                     "kernel": "k_psca_large", "flops_per_launch": flops, "avg_launch_ms": round(ms, 3)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
 # Unrolled network vs plain PSCA at the same equal-error rate
 # ---------------------------------------------------------------------------
 NET_EVAL = 32          # evaluation instances (seeds disjoint from training and validation)
@@ -370,7 +434,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain copy kernel of this many MiB (profiler calibration)")
-    ap.add_argument("--workload", choices=["single", "uneven", "net"], default="single",
+    ap.add_argument("--workload", choices=["single", "uneven", "net", "large"], default="single",
                     help="single: the four estimators on N=1000, L=64 (default); uneven: a batch of "
                          "independent ML-UD instances of mixed sizes in one persistent launch")
     ap.add_argument("--instances", type=int, default=4096, help="uneven workload: instances per batch")
@@ -394,6 +458,9 @@ def main():
         return
     if args.workload == "net":
         run_net(args)
+        return
+    if args.workload == "large":
+        run_large(args)
         return
 
     cpu_info, cpu_x, cpu_x64 = (None, {}, {})
