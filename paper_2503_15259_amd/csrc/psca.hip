@@ -93,6 +93,20 @@ __device__ __forceinline__ void cmfma(float2 a, float2 b, f4 &cr, f4 &ci) {
   ci = mfma4(a.y, b.x, ci);
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4 mfma4d(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Complex 16x16x4 block product accumulated in FP64 (real 4-product split).
+// Operand layout as the FP32 form (A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k); the result differs: C[i][j] sits in lane j + 16 (i % 4), element i / 4.
+__device__ __forceinline__ void cmfma_d(double2 a, double2 b, d4 &cr, d4 &ci) {
+  cr = mfma4d(a.x, b.x, cr);
+  cr = mfma4d(-a.y, b.y, cr);
+  ci = mfma4d(a.x, b.y, ci);
+  ci = mfma4d(a.y, b.x, ci);
+}
+
 // Keeps the enclosing block a real (scalar) branch: the compiler may not
 // speculate it into unconditional code plus selects.
 #define PSCA_KEEP_BRANCH() asm volatile("" ::: "memory")
@@ -300,7 +314,7 @@ struct CoopArgs {
   float *x_out, *q_out, *r_out, *xt_out;
   float *x_hist;        // [iters + 1][N] every iterate, or null
   int32_t *status;
-  float2 *partials;     // [G][pstride], workgroup g's packed partial of Sigma at g * pstride
+  double2 *partials;    // [G][pstride], workgroup g's packed FP64 partial of Sigma at g * pstride
   size_t pstride;       // >= NB * 256
   float2 *sigma;        // [NB * 256]
   GridBar bar;
@@ -363,55 +377,63 @@ __device__ __forceinline__ float row_bcast(float v) {   // lane K of each 16-lan
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + K, 0xf, 0xf, true));
 }
 
+// Value held by lane (j, G) for every lane (j, r), j = lane % 16, r = lane / 16:
+// the upper or lower half of the wavefront is copied to both halves by a
+// 32-lane swap, then row G & 1 of each pair of 16-lane rows by a 16-lane swap.
+template <int G>
+__device__ __forceinline__ float group_bcast(float v) {
+  const unsigned u = __float_as_uint(v);
+  const auto h = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  const unsigned hv = (G >> 1) ? h[1] : h[0];
+  const auto q = __builtin_amdgcn_permlane16_swap(hv, hv, false, false);
+  return __uint_as_float((G & 1) ? q[1] : q[0]);
+}
+
 // leaf_chol: one wavefront factors a 16x16 HPD block A = L L^H held in
-// registers and builds W = L^-1 alongside.  Lane l holds column j = l % 16
-// of rows r, r+4, r+8, r+12 (r = l / 16) of A (both triangles) and of the
-// running X (starting from I).  Step k: the pivot comes by readlane, column
-// k on the lane's rows by a DPP row broadcast (lane k of its 16-lane row),
-// row k on the lane's column (A[k][j] = conj(A[j][k]) and X[k][j]) by a lane
-// permute; row k of W is X[k][.] / L[k][k], then rows i > k take
-// X[i][.] -= L[i][k] W[k][.] and the trailing A[i][j] -= A[i][k] A[k][j] / A[k][k].
-// No LDS and no barrier.  ok turns false if a pivot is not positive and finite.
+// registers and turns it into W = L^-1 in place.  Lane l holds column
+// j = l % 16 of rows r, r+4, r+8, r+12 (r = l / 16) of the working matrix Z,
+// which starts as A (both triangles).  Columns j < K of Z hold the rows of
+// the running inverse X (X[i][j], unscaled below row K), columns j >= K the
+// trailing part of A.  Step K, with p = Z[K][K] and c = column K of Z:
+//   Z[i][j] -= c_i Z[K][j] / p     rows i > K, columns j != K
+//                                  (j > K: Schur update; j < K: X[i][j] -= L[i][K] W[K][j])
+//   Z[i][K]  = -c_i / p            rows i > K (X[i][K] = -L[i][K] W[K][K])
+//   Z[K][j] *= 1 / sqrt(p), Z[K][K] = 1 / sqrt(p)   (row K of W is final)
+// The pivot comes by readlane, column K on the lane's rows by a DPP row
+// broadcast, row K on the lane's column by two lane swaps.  No LDS and no
+// barrier.  ok turns false if a pivot is not positive and finite.
 template <int K>
-__device__ __forceinline__ void chol_step(float2 (&a)[4], float2 (&x)[4], int j, int r, bool &ok) {
-  const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[K >> 2].x), K + 16 * (K & 3)));
+__device__ __forceinline__ void chol_step(float2 (&z)[4], int j, int r, bool &ok) {
+  constexpr int mk = K >> 2, gk = K & 3;
+  const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z[mk].x), K + 16 * gk));
   ok = ok && (p > 0.0f) && (p < INFINITY);
+  const bool colk = (j == K);
+  const float2 zk = make_float2(group_bcast<gk>(z[mk].x), group_bcast<gk>(z[mk].y));   // Z[K][j]
+  const float2 zs = colk ? make_float2(1.0f, 0.0f) : zk;
+  // 1/p carries the update to the next pivot; 1/sqrt(p) only scales row K.
+  float invd = __builtin_amdgcn_rcpf(p);
+  invd = __builtin_fmaf(invd, __builtin_fmaf(-p, invd, 1.0f), invd);   // one Newton step
   float rs = __builtin_amdgcn_rsqf(p);
-  rs = rs * (1.5f - 0.5f * p * rs * rs);   // one Newton step
-  const float invd = rs * rs;
-  float2 ck[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) ck[m] = make_float2(row_bcast<K>(a[m].x), row_bcast<K>(a[m].y));
-  const int src = j + 16 * (K & 3);
-  const float2 rk = make_float2(__shfl(a[K >> 2].x, src), __shfl(a[K >> 2].y, src));   // A[K][j]
-  float2 wk = make_float2(__shfl(x[K >> 2].x, src), __shfl(x[K >> 2].y, src));         // X[K][j]
-  wk.x *= rs;
-  wk.y *= rs;   // W[K][j]
-  if (r == (K & 3)) {   // row K of W is final
-    x[K >> 2].x *= rs;
-    x[K >> 2].y *= rs;
-  }
+  rs = rs * (1.5f - 0.5f * p * rs * rs);                                // one Newton step
+  const float2 rk = make_float2(zs.x * invd, zs.y * invd);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    if (r + 4 * m > K) {
-      const float2 lik = make_float2(ck[m].x * rs, ck[m].y * rs);   // L[i][K]
-      const float2 t = cmul(lik, wk);
-      x[m].x -= t.x;
-      x[m].y -= t.y;
-      if (j > K) {
-        const float2 u = cmul(ck[m], rk);
-        a[m].x -= u.x * invd;
-        a[m].y -= u.y * invd;
+    if (4 * m + 3 > K) {                   // some row r + 4m lies below K
+      const float2 ck = make_float2(row_bcast<K>(z[m].x), row_bcast<K>(z[m].y));   // Z[r+4m][K]
+      if (r + 4 * m > K) {
+        const float2 base = colk ? make_float2(0.0f, 0.0f) : z[m];
+        z[m].x = base.x - ck.x * rk.x + ck.y * rk.y;
+        z[m].y = base.y - ck.x * rk.y - ck.y * rk.x;
       }
     }
   }
+  if (r == gk) z[mk] = colk ? make_float2(rs, 0.0f) : make_float2(z[mk].x * rs, z[mk].y * rs);
 }
 
 template <int... Ks>
-__device__ __forceinline__ bool chol_steps(float2 (&a)[4], float2 (&x)[4], int j, int r,
-                                           std::integer_sequence<int, Ks...>) {
+__device__ __forceinline__ bool chol_steps(float2 (&z)[4], int j, int r, std::integer_sequence<int, Ks...>) {
   bool ok = true;
-  (chol_step<Ks>(a, x, j, r, ok), ...);
+  (chol_step<Ks>(z, j, r, ok), ...);
   return ok;
 }
 
@@ -419,15 +441,12 @@ __device__ __forceinline__ bool chol_steps(float2 (&a)[4], float2 (&x)[4], int j
 // overwrites it with W = L^-1 (zeros above the diagonal).
 __device__ __forceinline__ bool leaf_chol(float2 *D, int ld, int lane) {
   const int j = lane & 15, r = lane >> 4;
-  float2 a[4], x[4];
+  float2 z[4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    a[m] = D[j * ld + r + 4 * m];
-    x[m] = make_float2(r + 4 * m == j ? 1.0f : 0.0f, 0.0f);
-  }
-  const bool ok = chol_steps(a, x, j, r, std::make_integer_sequence<int, 16>{});
+  for (int m = 0; m < 4; ++m) z[m] = D[j * ld + r + 4 * m];
+  const bool ok = chol_steps(z, j, r, std::make_integer_sequence<int, 16>{});
 #pragma unroll
-  for (int m = 0; m < 4; ++m) D[j * ld + r + 4 * m] = x[m];
+  for (int m = 0; m < 4; ++m) D[j * ld + r + 4 * m] = (r + 4 * m < j) ? make_float2(0.0f, 0.0f) : z[m];
   return ok;
 }
 
@@ -479,10 +498,14 @@ __device__ __forceinline__ void chol_trail(float2 *WS, int P, int J, int I, int 
 // ---------------------------------------------------------------------------
 // Phases shared by the forward and the backward bodies
 // ---------------------------------------------------------------------------
-// Packed lower blocks of the tile's Gram matrix S_t diag(wv) S_t^H (MFMA,
-// complex product on the real 4-product split) into dst.  St: [Lp][PT] S tile.
+// Packed lower blocks of the tile's Gram matrix S_t diag(wv) S_t^H into dst
+// (MFMA, complex product on the real 4-product split).  The products of the
+// FP32 operands are exact in FP64 and the sums are FP64: the entries of Sigma
+// then carry a single rounding (when it is stored), which matters because q
+// and q - r move with kappa(Sigma) times the entry errors of Sigma.
+// St: [Lp][PT] S tile.
 template <int LP, int THREADS>
-__device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, const float *wv, float2 *dst) {
+__device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, const float *wv, double2 *dst) {
   constexpr int kWaves = THREADS / 64, Lb = LP / 16, NB = Lb * (Lb + 1) / 2;
   constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
@@ -492,49 +515,52 @@ __device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, con
     if (b < NB) {
       int I, J;
       blk_coords(b, I, J);
-      f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+      d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
       for (int cb = 0; cb < ncb; ++cb) {
-        float2 av4[4], bv4[4];
+        double2 av4[4], bv4[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int c = 16 * cb + 4 * ks + lq;
           const float2 s = St[(16 * J + l16) * PT + c];
-          const float w = wv[c];
-          av4[ks] = St[(16 * I + l16) * PT + c];
-          bv4[ks] = make_float2(w * s.x, -w * s.y);
+          const float2 a = St[(16 * I + l16) * PT + c];
+          const double w = wv[c];
+          av4[ks] = make_double2(a.x, a.y);
+          bv4[ks] = make_double2(w * s.x, -w * s.y);
         }
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(av4[ks], bv4[ks], cr, ci);
+        for (int ks = 0; ks < 4; ++ks) cmfma_d(av4[ks], bv4[ks], cr, ci);
       }
-      float4 *o = (float4 *)(dst + b * 256 + l16 * 16 + 4 * lq);
-      o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
-      o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
+      double2 *o = dst + b * 256 + l16 * 16 + lq;   // rows lq + 4v of column l16
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[4 * v] = make_double2(cr[v], ci[v]);
     }
   }
 }
 
-__device__ __forceinline__ void store_reduced(float2 *out, int e, float2 sm, bool add_diag, int L, float sigma2) {
+__device__ __forceinline__ void store_reduced(float2 *out, int e, double2 sm, bool add_diag, int L, float sigma2) {
   if (add_diag) {
     const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
     int I, J;
     blk_coords(b, I, J);
     if (I == J && ii == jj) {
       const int i = 16 * I + ii;
-      sm.x += (i < L) ? sigma2 : 1.0f;
-      sm.y = 0.0f;
+      sm.x += (i < L) ? (double)sigma2 : 1.0;
+      sm.y = 0.0;
     }
   }
-  out[e] = sm;
+  out[e] = make_float2((float)sm.x, (float)sm.y);
 }
 
 // Workgroup g's 1/G slice of the sum over the G packed partials (rank h at
 // partials + h * pstride) into out; with add_diag, sigma2 is added to the
 // diagonal of rows < L and 1 to padded rows (isolated unit pivots), and the
-// diagonal is made real.  scr: THREADS float2 of LDS.
+// imaginary part of the diagonal is zeroed.  The FP64 partials are summed
+// in FP64 and the result rounded once.  scr: THREADS double2 of LDS.
 template <int LP, int THREADS>
-__device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstride, int G, int g, float2 *out,
-                                             float2 *scr, bool add_diag, int L, float sigma2) {
+__device__ __forceinline__ void reduce_slice(const double2 *partials, size_t pstride, int G, int g, float2 *out,
+                                             double2 *scr, bool add_diag, int L, float sigma2) {
   constexpr int Lb = LP / 16, E = Lb * (Lb + 1) / 2 * 256;
+  static_assert(THREADS * sizeof(double2) <= (THREADS / 64) * 256 * sizeof(float2), "scr holds THREADS double2");
   const int tid = threadIdx.x;
   const int per = (E + G - 1) / G;
   const int start = g * per, end = min(E, start + per);
@@ -543,9 +569,9 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
     const int Pp = THREADS / cnt;   // threads per element
     if (tid < cnt * Pp) {
       const int e = start + tid % cnt, part = tid / cnt;
-      float2 acc = make_float2(0.f, 0.f);
+      double2 acc = make_double2(0.0, 0.0);
       for (int h = part; h < G; h += Pp) {
-        const float2 v = partials[(size_t)h * pstride + e];
+        const double2 v = partials[(size_t)h * pstride + e];
         acc.x += v.x;
         acc.y += v.y;
       }
@@ -553,9 +579,9 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
     }
     __syncthreads();
     if (tid < cnt) {
-      float2 sm = make_float2(0.f, 0.f);
+      double2 sm = make_double2(0.0, 0.0);
       for (int part = 0; part < Pp; ++part) {
-        const float2 v = scr[part * cnt + tid];
+        const double2 v = scr[part * cnt + tid];
         sm.x += v.x;
         sm.y += v.y;
       }
@@ -563,9 +589,9 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
     }
   } else {
     for (int e = start + tid; e < end; e += THREADS) {
-      float2 sm = make_float2(0.f, 0.f);
+      double2 sm = make_double2(0.0, 0.0);
       for (int h = 0; h < G; ++h) {
-        const float2 v = partials[(size_t)h * pstride + e];
+        const double2 v = partials[(size_t)h * pstride + e];
         sm.x += v.x;
         sm.y += v.y;
       }
@@ -632,8 +658,10 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
     if (wave == 0) {
       chol_trail(WS, P, J, J + 1, J + 1, l16, lq);
       wave_lds_sync();
+      PSCA_SUB_MARK(it, J, 2);
       const bool ok = leaf_chol(WS + 16 * (J + 1) * P + 16 * (J + 1), P, lane);
       if (lane == 0) s_pd[J + 1] = ok ? 1 : 0;
+      PSCA_SUB_MARK(it, J, 3);
     } else {
       int q = 0;
       for (int I = J + 2; I < Lb; ++I)
@@ -784,7 +812,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
 
     // ===== B. reduce a slice of the partials into Sigma ===================
     PSCA_MARK(it, 2);
-    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, A.sigma, scr, true, A.L, A.sigma2);
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, A.sigma, (double2 *)scr, true, A.L, A.sigma2);
     PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
@@ -961,7 +989,7 @@ struct BackArgs {
   const float *v;       // [N] dL/dx'
   float *grad_x;        // [N] dL/dx
   float *rho_part;      // [G] per-workgroup parts of dL/drho
-  float2 *partials_b;   // [G][pstride] partials of G_b (those of G_a use c.partials)
+  double2 *partials_b;  // [G][pstride] partials of G_b (those of G_a use c.partials)
   float2 *gram_a, *gram_b;   // packed G_a, G_b
 };
 
@@ -1044,7 +1072,7 @@ __device__ __forceinline__ void psca_back_body(const BackArgs &Bk, const int g) 
     __syncthreads();
     tile_gram<Lp, THREADS>(St, PT, A.ncb, red_q, A.partials + (size_t)g * A.pstride);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
-    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, A.sigma, scr, true, A.L, A.sigma2);
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, A.sigma, (double2 *)scr, true, A.L, A.sigma2);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
     if (!invert_hpd<Lp, THREADS, true>(A.sigma, WS, scr, s_pd, 0)) { failed = true; break; }
 
@@ -1142,9 +1170,9 @@ __device__ __forceinline__ void psca_back_body(const BackArgs &Bk, const int g) 
     tile_gram<Lp, THREADS>(St, PT, A.ncb, aw, A.partials + (size_t)g * A.pstride);
     tile_gram<Lp, THREADS>(St, PT, A.ncb, bw, Bk.partials_b + (size_t)g * A.pstride);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
-    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, Bk.gram_a, scr, false, A.L, 0.0f);
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, Bk.gram_a, (double2 *)scr, false, A.L, 0.0f);
     __syncthreads();
-    reduce_slice<Lp, THREADS>(Bk.partials_b, A.pstride, A.G, g, Bk.gram_b, scr, false, A.L, 0.0f);
+    reduce_slice<Lp, THREADS>(Bk.partials_b, A.pstride, A.G, g, Bk.gram_b, (double2 *)scr, false, A.L, 0.0f);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
     unpack_hermitian<Lp, THREADS>(Bk.gram_a, WS);
     unpack_hermitian<Lp, THREADS>(Bk.gram_b, ShL);
@@ -1295,23 +1323,24 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     for (int b = wave; b < NB; b += kWaves) {
       int I, J;
       blk_coords(b, I, J);
-      f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+      d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};   // FP64, as tile_gram
       for (int cb = 0; cb < ncb; ++cb) {
-        float2 av4[4], bv4[4];
+        double2 av4[4], bv4[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int c = 16 * cb + 4 * ks + lq;
           const float2 sv = s_at(16 * J + l16, c);
-          const float w = red_q[c];
-          av4[ks] = s_at(16 * I + l16, c);
-          bv4[ks] = make_float2(w * sv.x, -w * sv.y);
+          const float2 av = s_at(16 * I + l16, c);
+          const double w = red_q[c];
+          av4[ks] = make_double2(av.x, av.y);
+          bv4[ks] = make_double2(w * sv.x, -w * sv.y);
         }
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(av4[ks], bv4[ks], cr, ci);
+        for (int ks = 0; ks < 4; ++ks) cmfma_d(av4[ks], bv4[ks], cr, ci);
       }
-      float4 *o = (float4 *)(A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + 4 * lq);
-      o[0] = make_float4(cr[0], ci[0], cr[1], ci[1]);
-      o[1] = make_float4(cr[2], ci[2], cr[3], ci[3]);
+      double2 *o = A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + lq;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[4 * v] = make_double2(cr[v], ci[v]);
     }
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
@@ -1320,9 +1349,9 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       const int per = (E + A.G - 1) / A.G;
       const int start = g * per, end = min(E, start + per);
       for (int e = start + tid; e < end; e += THREADS) {
-        float2 sm = make_float2(0.f, 0.f);
+        double2 sm = make_double2(0.0, 0.0);   // summed in double, rounded once
         for (int h = 0; h < A.G; ++h) {
-          const float2 v = A.partials[(size_t)h * A.pstride + e];
+          const double2 v = A.partials[(size_t)h * A.pstride + e];
           sm.x += v.x;
           sm.y += v.y;
         }
@@ -1330,11 +1359,12 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
         int I, J;
         blk_coords(b, I, J);
         if (I == J && ii == jj) {
-          sm.x += (16 * I + ii < A.L) ? A.sigma2 : 1.0f;
-          sm.y = 0.0f;
+          sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
+          sm.y = 0.0;
         }
-        sig[e] = sm;
-        Lg.sigma_copy[e] = sm;
+        const float2 sf = make_float2((float)sm.x, (float)sm.y);
+        sig[e] = sf;
+        Lg.sigma_copy[e] = sf;
       }
     }
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
@@ -1629,15 +1659,16 @@ __global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restric
   while (i * (i + 1) / 2 > e) --i;
   while ((i + 1) * (i + 2) / 2 <= e) ++i;
   const int j = e - i * (i + 1) / 2;
-  float2 acc = make_float2(0.f, 0.f);
+  // Accumulated in double and rounded once: Sigma - SigmaHat is formed from
+  // this matrix every iteration, so its FP32 entries should carry no more
+  // than their own rounding.
+  double ax = 0.0, ay = 0.0;
   for (int m = 0; m < M; ++m) {
-    const float2 t = cmul_conj(Y[i + (size_t)m * L], Y[j + (size_t)m * L]);
-    acc.x += t.x;
-    acc.y += t.y;
+    const float2 a = Y[i + (size_t)m * L], b = Y[j + (size_t)m * L];
+    ax += (double)a.x * b.x + (double)a.y * b.y;
+    ay += (double)a.y * b.x - (double)a.x * b.y;
   }
-  const float s = 1.0f / (float)M;
-  acc.x *= s;
-  acc.y *= s;
+  float2 acc = make_float2((float)(ax / M), (float)(ay / M));
   if (i == j) acc.y = 0.0f;
   Sh[i + (size_t)j * L] = acc;
   Sh[j + (size_t)i * L] = make_float2(acc.x, -acc.y);
@@ -1825,7 +1856,7 @@ struct InstPlan {
 
 size_t ws_bytes_of(int Lp, int G) {
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
-  return align_up((size_t)G * E * sizeof(float2)) + align_up(E * sizeof(float2)) +
+  return align_up((size_t)G * E * sizeof(double2)) + align_up(E * sizeof(float2)) +
          align_up((size_t)G * 16 * sizeof(unsigned)) + 3 * align_up(sizeof(unsigned));
 }
 
@@ -1834,7 +1865,7 @@ void bind_ws(CoopArgs &a, char *base, const InstPlan &p) {
   const size_t E = (size_t)(p.Lp / 16) * (p.Lp / 16 + 1) / 2 * 256;
   size_t off = 0;
   a.pstride = E;
-  a.partials = (float2 *)(base + off); off += align_up((size_t)p.G * E * sizeof(float2));
+  a.partials = (double2 *)(base + off); off += align_up((size_t)p.G * E * sizeof(double2));
   a.sigma = (float2 *)(base + off);    off += align_up(E * sizeof(float2));
   a.bar.arrive = (unsigned *)(base + off); off += align_up((size_t)p.G * 16 * sizeof(unsigned));
   a.bar.release = (unsigned *)(base + off); off += align_up(sizeof(unsigned));
@@ -1889,7 +1920,7 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   }
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
   const size_t o_pa = 0;
-  const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
+  const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(double2));
   const size_t o_cp = align_up(o_sig + E * sizeof(float2));
   const size_t o_arr = align_up(o_cp + E * sizeof(float2));
   const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
@@ -1902,7 +1933,7 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   LargeArgs a;
   fill_args(a.c, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
   a.c.x_hist = x_hist;
-  a.c.partials = (float2 *)(base + o_pa);
+  a.c.partials = (double2 *)(base + o_pa);
   a.c.pstride = E;
   a.c.sigma = (float2 *)(base + o_sig);
   a.c.bar.arrive = (unsigned *)(base + o_arr);
@@ -2022,8 +2053,8 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   }
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
   const size_t o_pa = 0;
-  const size_t o_pb = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
-  const size_t o_sig = align_up(o_pb + (size_t)p.G * E * sizeof(float2));
+  const size_t o_pb = align_up(o_pa + (size_t)p.G * E * sizeof(double2));
+  const size_t o_sig = align_up(o_pb + (size_t)p.G * E * sizeof(double2));
   const size_t o_ga = align_up(o_sig + E * sizeof(float2));
   const size_t o_gb = align_up(o_ga + E * sizeof(float2));
   const size_t o_arr = align_up(o_gb + E * sizeof(float2));
@@ -2037,7 +2068,7 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   char *base = (char *)ctx->ws;
   BackArgs b;
   fill_args(b.c, Sh, S, L, N, prm, 1, rho, x_in, nullptr, nullptr, nullptr, nullptr, status, p);
-  b.c.partials = (float2 *)(base + o_pa);
+  b.c.partials = (double2 *)(base + o_pa);
   b.c.pstride = E;
   b.c.sigma = (float2 *)(base + o_sig);
   b.c.bar.arrive = (unsigned *)(base + o_arr);
@@ -2048,7 +2079,7 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   b.v = v;
   b.grad_x = grad_x;
   b.rho_part = (float *)(base + o_rp);
-  b.partials_b = (float2 *)(base + o_pb);
+  b.partials_b = (double2 *)(base + o_pb);
   b.gram_a = (float2 *)(base + o_ga);
   b.gram_b = (float2 *)(base + o_gb);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, b.c.bar.arrive, p.G, b.c.bar.release,
@@ -2177,7 +2208,7 @@ int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
   }
   plan.part_off = off;
   plan.E_max = E_max;
-  plan.part_stride = align_up((size_t)T * E_max * sizeof(float2));
+  plan.part_stride = align_up((size_t)T * E_max * sizeof(double2));
   plan.ws_bytes = off + plan.part_stride * plan.n_teams;
   return PSCA_OK;
 }
@@ -2198,7 +2229,7 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
     if (!a.status) a.status = (int32_t *)w;
     // every rank of a team owns the same slot for all of the team's instances:
     // a rank that sits out an instance may start the next one early
-    a.partials = (float2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
+    a.partials = (double2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
     a.pstride = plan.E_max;
     out[b] = a;
   }
@@ -2592,6 +2623,11 @@ int psca_sub_trace(unsigned long long *host) {
 int psca_step_trace(unsigned long long *host) {
   return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_step_trace), sizeof(unsigned long long) * 128) == hipSuccess
              ? PSCA_OK : PSCA_EHIP;
+}
+// Profiling builds only: copy bytes of the context's workspace at offset to host.
+int psca_debug_ws(psca_ctx *ctx, size_t offset, size_t bytes, void *host) {
+  if (!ctx || !host || offset + bytes > ctx->ws_bytes) return PSCA_EINVAL;
+  return hipMemcpy(host, (char *)ctx->ws + offset, bytes, hipMemcpyDeviceToHost) == hipSuccess ? PSCA_OK : PSCA_EHIP;
 }
 int psca_phase_trace(unsigned long long *host, int count) {
   if (!host || count < kTraceIters * kTraceMarks) return PSCA_EINVAL;
