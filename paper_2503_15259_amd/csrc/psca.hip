@@ -392,29 +392,29 @@ __device__ __forceinline__ float group_bcast(float v) {
 // leaf_chol: one wavefront factors a 16x16 HPD block A = L L^H held in
 // registers and turns it into W = L^-1 in place.  Lane l holds column
 // j = l % 16 of rows r, r+4, r+8, r+12 (r = l / 16) of the working matrix Z,
-// which starts as A (both triangles).  Columns j < K of Z hold the rows of
-// the running inverse X (X[i][j], unscaled below row K), columns j >= K the
-// trailing part of A.  Step K, with p = Z[K][K] and c = column K of Z:
+// which starts as A (both triangles).  Below the diagonal, columns j < K of
+// Z hold the running inverse X (unit diagonal, rows not yet scaled), columns
+// j >= K the trailing part of A.  Step K, with p = Z[K][K] and c = column K:
 //   Z[i][j] -= c_i Z[K][j] / p     rows i > K, columns j != K
-//                                  (j > K: Schur update; j < K: X[i][j] -= L[i][K] W[K][j])
-//   Z[i][K]  = -c_i / p            rows i > K (X[i][K] = -L[i][K] W[K][K])
-//   Z[K][j] *= 1 / sqrt(p), Z[K][K] = 1 / sqrt(p)   (row K of W is final)
-// The pivot comes by readlane, column K on the lane's rows by a DPP row
-// broadcast, row K on the lane's column by two lane swaps.  No LDS and no
-// barrier.  ok turns false if a pivot is not positive and finite.
+//                                  (j > K: Schur update; j < K: X[i][j] -= L[i][K] W[K][j] sqrt(p))
+//   Z[i][K]  = -c_i / p            rows i > K (X[i][K] = -L[i][K] / sqrt(p))
+// Row K of X is final after step K; W = diag(p)^-1/2 X is applied at the end
+// together with the unit diagonal and the zero upper triangle, so 1/p is the
+// only quantity on the chain from one pivot to the next.  The pivot comes
+// by readlane, column K on the lane's rows by a DPP row broadcast, row K on
+// the lane's column by two lane swaps.  No LDS and no barrier.  ok turns
+// false if a pivot is not positive and finite.
 template <int K>
-__device__ __forceinline__ void chol_step(float2 (&z)[4], int j, int r, bool &ok) {
+__device__ __forceinline__ void chol_step(float2 (&z)[4], int j, int r, float (&piv)[16], bool &ok) {
   constexpr int mk = K >> 2, gk = K & 3;
   const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(z[mk].x), K + 16 * gk));
-  ok = ok && (p > 0.0f) && (p < INFINITY);
+  piv[K] = p;
+  ok = ok && __builtin_amdgcn_classf(p, 0x180);   // positive, finite, not zero
   const bool colk = (j == K);
   const float2 zk = make_float2(group_bcast<gk>(z[mk].x), group_bcast<gk>(z[mk].y));   // Z[K][j]
   const float2 zs = colk ? make_float2(1.0f, 0.0f) : zk;
-  // 1/p carries the update to the next pivot; 1/sqrt(p) only scales row K.
   float invd = __builtin_amdgcn_rcpf(p);
   invd = __builtin_fmaf(invd, __builtin_fmaf(-p, invd, 1.0f), invd);   // one Newton step
-  float rs = __builtin_amdgcn_rsqf(p);
-  rs = rs * (1.5f - 0.5f * p * rs * rs);                                // one Newton step
   const float2 rk = make_float2(zs.x * invd, zs.y * invd);
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
@@ -427,13 +427,13 @@ __device__ __forceinline__ void chol_step(float2 (&z)[4], int j, int r, bool &ok
       }
     }
   }
-  if (r == gk) z[mk] = colk ? make_float2(rs, 0.0f) : make_float2(z[mk].x * rs, z[mk].y * rs);
 }
 
 template <int... Ks>
-__device__ __forceinline__ bool chol_steps(float2 (&z)[4], int j, int r, std::integer_sequence<int, Ks...>) {
+__device__ __forceinline__ bool chol_steps(float2 (&z)[4], int j, int r, float (&piv)[16],
+                                           std::integer_sequence<int, Ks...>) {
   bool ok = true;
-  (chol_step<Ks>(z, j, r, ok), ...);
+  (chol_step<Ks>(z, j, r, piv, ok), ...);
   return ok;
 }
 
@@ -442,11 +442,21 @@ __device__ __forceinline__ bool chol_steps(float2 (&z)[4], int j, int r, std::in
 __device__ __forceinline__ bool leaf_chol(float2 *D, int ld, int lane) {
   const int j = lane & 15, r = lane >> 4;
   float2 z[4];
+  float piv[16];
 #pragma unroll
   for (int m = 0; m < 4; ++m) z[m] = D[j * ld + r + 4 * m];
-  const bool ok = chol_steps(z, j, r, std::make_integer_sequence<int, 16>{});
+  const bool ok = chol_steps(z, j, r, piv, std::make_integer_sequence<int, 16>{});
 #pragma unroll
-  for (int m = 0; m < 4; ++m) D[j * ld + r + 4 * m] = (r + 4 * m < j) ? make_float2(0.0f, 0.0f) : z[m];
+  for (int m = 0; m < 4; ++m) {
+    const int i = r + 4 * m;
+    const float p = r == 0 ? piv[4 * m] : (r == 1 ? piv[4 * m + 1] : (r == 2 ? piv[4 * m + 2] : piv[4 * m + 3]));
+    float rs = __builtin_amdgcn_rsqf(p);
+    rs = rs * (1.5f - 0.5f * p * rs * rs);   // one Newton step
+    float2 w = make_float2(z[m].x * rs, z[m].y * rs);
+    if (i == j) w = make_float2(rs, 0.0f);
+    if (i < j) w = make_float2(0.0f, 0.0f);
+    D[j * ld + i] = w;
+  }
   return ok;
 }
 
