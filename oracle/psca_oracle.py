@@ -30,6 +30,12 @@ Readings where the paper is silent, ambiguous or garbled:
       at iteration k uses rho_k.  Fixed iteration count (no stopping rule).
   R6  Clip bounds are inclusive; K variants [0, 1], ML-UD [0, inf),
       MAP-UR [0, g_u].
+  R8  MAP-K2 is PSCA-MAP-K under the second-order approximation of the
+      general activity model (eq. second): f_t of eq. ft with t = G keeps
+      the coefficients c_{n} and c_{n,n'} only, so its gradient (eq.
+      ft_gradient, case G) is -(1/M)(c_n + sum_{n'} c_{n,n'} alpha_n').
+      The pairwise coefficients form a symmetric matrix C with zero
+      diagonal, and f_t = -(1/M)(c^T alpha + alpha^T C alpha / 2).
 """
 from __future__ import annotations
 
@@ -38,9 +44,9 @@ import math
 
 import numpy as np
 
-ML_K, MAP_K, ML_UD, MAP_UR = 0, 1, 2, 3
-VARIANT_NAMES = {ML_K: "ML-K", MAP_K: "MAP-K", ML_UD: "ML-UD", MAP_UR: "MAP-UR"}
-KNOWN_PATHLOSS = (ML_K, MAP_K)
+ML_K, MAP_K, ML_UD, MAP_UR, MAP_K2 = 0, 1, 2, 3, 4
+VARIANT_NAMES = {ML_K: "ML-K", MAP_K: "MAP-K", ML_UD: "ML-UD", MAP_UR: "MAP-UR", MAP_K2: "MAP-K2"}
+KNOWN_PATHLOSS = (ML_K, MAP_K, MAP_K2)
 
 
 # ---------------------------------------------------------------------------
@@ -269,6 +275,8 @@ class Problem:
     g: np.ndarray | None = None        # known pathloss (ML-K, MAP-K)
     p: np.ndarray | None = None        # activity probabilities (MAP-K)
     prior: PowerLawPrior | None = None  # MAP-UR prior (common to all devices)
+    c1: np.ndarray | None = None       # MAP-K2: first-order coefficients c_{n}
+    C2: object | None = None           # MAP-K2: pairwise c_{n,n'} (scipy CSR, symmetric, zero diagonal)
 
     @property
     def N(self):
@@ -301,6 +309,8 @@ def objective(prob: Problem, x: np.ndarray) -> float:
     f = ml_objective(Sigma, prob.Sigma_hat)
     if prob.variant == MAP_K:
         f += -np.sum(np.log(prob.p / (1.0 - prob.p)) * x) / prob.M
+    elif prob.variant == MAP_K2:   # reading R8
+        f += -(np.dot(prob.c1, x) + 0.5 * np.dot(x, prob.C2 @ x)) / prob.M
     elif prob.variant == MAP_UR:
         for xn in x:
             pe = prob.prior.p_eps(float(xn))
@@ -324,6 +334,9 @@ def gradient_and_curvature(prob: Problem, x: np.ndarray, q: np.ndarray, r: np.nd
         curv = (prob.g * q) ** 2
     elif v == MAP_K:
         grad = prob.g * (q - r) - np.log(prob.p / (1.0 - prob.p)) / prob.M   # reading R1
+        curv = (prob.g * q) ** 2
+    elif v == MAP_K2:
+        grad = prob.g * (q - r) - (prob.c1 + prob.C2 @ x) / prob.M   # eq. ft_gradient, case G; R8
         curv = (prob.g * q) ** 2
     elif v == ML_UD:
         grad = q - r
@@ -405,7 +418,17 @@ def problem_from_instance(inst, variant: int, eps: float = 0.01) -> Problem:
         kw["p"] = np.full(N, float(inst.p))
     if variant == MAP_UR:
         kw["prior"] = make_prior(inst.p, inst.d_lo, inst.d_hi, inst.pl_c0, inst.pl_beta, eps)
+    if variant == MAP_K2:
+        kw["c1"], kw["C2"] = pairwise_prior(N, inst.c_single, *inst.pair_csr())
     return Problem(**kw)
+
+
+def pairwise_prior(N: int, c_single: float, ptr, col, val):
+    """First-order coefficients c_{n} = c_single and the pairwise matrix C of
+    eq. second from its CSR arrays (rows n, entries c_{n,n'})."""
+    from scipy.sparse import csr_matrix
+    C = csr_matrix((np.asarray(val, np.float64), np.asarray(col), np.asarray(ptr)), shape=(N, N))
+    return np.full(N, float(c_single)), C
 
 
 # ---------------------------------------------------------------------------
@@ -529,6 +552,8 @@ def layer_vjp(prob: Problem, x: np.ndarray, rho: float, v: np.ndarray):
     dq = -(np.abs(P) ** 2) * kappa[None, :]           # dq_n/dx_m
     dr = -2.0 * np.real(P * R.conj()) * kappa[None, :]  # dr_n/dx_m
     dx = v * (1.0 - rho) + rho * v * mask * own + a @ dq + b @ dr
+    if prob.variant == MAP_K2:   # d pre_n / d x_m = c_{n,m} / (M curv_n): the pairwise prior couples devices
+        dx = dx + rho * (prob.C2.T @ (v * mask / curv)) / prob.M
     return dx, d_rho
 
 

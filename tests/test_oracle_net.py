@@ -12,11 +12,14 @@ import pytest
 import oracle as O
 from paper_2503_15259_amd import instances as I
 
-VARIANTS = [O.ML_K, O.MAP_K, O.ML_UD, O.MAP_UR]
+VARIANTS = [O.ML_K, O.MAP_K, O.ML_UD, O.MAP_UR, O.MAP_K2]
 
 
 def tiny(variant, seed=0):
-    inst = I.make_instance(3, 100 + seed, 20, 8, 64, 0.3)
+    if variant == O.MAP_K2:
+        inst = I.make_group_instance(3, 100 + seed, 20, 8, 64, 0.3, 4, 1.5)
+    else:
+        inst = I.make_instance(3, 100 + seed, 20, 8, 64, 0.3)
     return inst, O.problem_from_instance(inst, variant, eps=0.01)
 
 
