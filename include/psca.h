@@ -9,6 +9,9 @@
  *   PSCA_MAP_K  MAPE of alpha with the independent Bernoulli prior (Sec. III-B)
  *   PSCA_ML_UD  MLE of the effective pathloss gamma >= 0, unknown g (Sec. IV-A)
  *   PSCA_MAP_UR MAPE of gamma with the Hermite-smoothed prior p^eps (Sec. IV-B)
+ *   PSCA_MAP_K2 MAPE of alpha, known pathloss, under the second-order activity
+ *               model (eq. second; Sec. III-B with t = G restricted to sets of
+ *               one or two devices)
  *
  * Conventions shared by every entry point:
  *   - Complex numbers are interleaved single precision (psca_c32, the layout
@@ -47,7 +50,8 @@ typedef enum {
   PSCA_ML_K = 0,
   PSCA_MAP_K = 1,
   PSCA_ML_UD = 2,
-  PSCA_MAP_UR = 3
+  PSCA_MAP_UR = 3,
+  PSCA_MAP_K2 = 4
 } psca_variant;
 
 typedef enum {
@@ -87,6 +91,15 @@ typedef enum {
  *              d^-pl_beta (pl_c0 > 0, pl_beta > 0), Hermite width eps with
  *              0 < eps and 2 eps < g_l = phi(d_hi).  The gradient's prior term
  *              p^eps'/p^eps does not depend on the activity probability.
+ *   c1, c2_ptr, c2_col, c2_val, c2_nnz   MAP-K2 prior (eq. second): DEVICE
+ *              [N] first-order coefficients c_n, and the symmetric pairwise
+ *              coefficients c_{n,n'} (zero diagonal) as CSR: row pointers
+ *              [N+1], columns and values [c2_nnz], each pair stored in both
+ *              rows.  The gradient's prior term is -(1/M)(c_n + sum_n'
+ *              c_{n,n'} alpha_n') (eq. ft_gradient, case G).  Row entries
+ *              outside [0, c2_nnz) and columns outside [0, N) are skipped on
+ *              the device.  Required by MAP-K2 (with g); ignored otherwise, but
+ *              must then be zero-initialised by callers that build the struct.
  */
 typedef struct {
   int32_t variant;
@@ -99,6 +112,11 @@ typedef struct {
   const float *g;
   const float *p;
   float d_lo, d_hi, pl_c0, pl_beta, eps;
+  const float *c1;
+  const int32_t *c2_ptr;
+  const int32_t *c2_col;
+  const float *c2_val;
+  int32_t c2_nnz;
 } psca_params;
 
 typedef struct psca_ctx psca_ctx;

@@ -17,7 +17,7 @@ PSCA_ENOMEM = -4
 PSCA_ENOTSUP = -5
 PSCA_ESYNC = -6
 
-ML_K, MAP_K, ML_UD, MAP_UR = 0, 1, 2, 3
+ML_K, MAP_K, ML_UD, MAP_UR, MAP_K2 = 0, 1, 2, 3, 4
 MAX_L = 256
 
 # every symbol include/psca.h declares
@@ -45,6 +45,11 @@ class PscaParams(ctypes.Structure):
         ("pl_c0", ctypes.c_float),
         ("pl_beta", ctypes.c_float),
         ("eps", ctypes.c_float),
+        ("c1", ctypes.c_void_p),
+        ("c2_ptr", ctypes.c_void_p),
+        ("c2_col", ctypes.c_void_p),
+        ("c2_val", ctypes.c_void_p),
+        ("c2_nnz", ctypes.c_int32),
     ]
 
 

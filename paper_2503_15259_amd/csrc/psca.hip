@@ -141,7 +141,27 @@ struct StepArgs {
   const float *g;   // [N] known pathloss (K variants)
   const float *p;   // [N] activity probability (MAP-K)
   float eps, g_l, g_u, h2_b, dens_c;   // MAP-UR prior constants
+  // MAP-K2 (second-order activity model): c_n, the CSR rows of c_{n,n'}, and
+  // the exchange buffer of the iterate [2][N] (x^(k) in half k % 2)
+  const float *c1;
+  const int32_t *c2_ptr, *c2_col;
+  const float *c2_val;
+  int32_t c2_nnz;
+  float *xg;
 };
+
+// sum_{n'} c_{n,n'} x_n' over row n of the pairwise coefficients, x the
+// exchanged iterate.  Entries outside [0, nnz) or with a column outside
+// [0, N) are skipped.
+__device__ __forceinline__ float pair_sum(const StepArgs &a, int n, int N, const float *x) {
+  const int k0 = max(0, a.c2_ptr[n]), k1 = min(a.c2_nnz, a.c2_ptr[n + 1]);
+  float acc = 0.0f;
+  for (int k = k0; k < k1; ++k) {
+    const int m = a.c2_col[k];
+    if ((unsigned)m < (unsigned)N) acc += a.c2_val[k] * x[m];
+  }
+  return acc;
+}
 
 // p^eps'(x) / p^eps(x) of the smoothed prior (eqs. peps, H2, pepsd) in the
 // simplified per-piece forms; 0 where p^eps = 0 (the gap between eps and g_l - eps).
@@ -171,7 +191,8 @@ __device__ __forceinline__ float coordinate_step(float x, float q, float qmr, fl
       hi = 1.0f;
       break;
     }
-    case PSCA_MAP_K: {
+    case PSCA_MAP_K:
+    case PSCA_MAP_K2: {   // logit: log(p/(1-p)), or c_n + sum_n' c_{n,n'} x_n'
       grad = g * qmr - logit * a.inv_M;
       const float gq = g * q;
       curv = gq * gq;
@@ -785,7 +806,8 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   const int l16 = lane & 15, lq = lane >> 4;
   const int n0 = g * NT;
   unsigned gen = 0;
-  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
+  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K || A.a.variant == PSCA_MAP_K2);
+  const bool pairs = (A.a.variant == PSCA_MAP_K2);
 
   // ---- resident tile data -------------------------------------------------
   for (int e = tid; e < Lp * NT; e += THREADS) {
@@ -803,6 +825,10 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     if (in && A.a.p) {
       const float pn = A.a.p[n];
       lg = logf(pn / (1.0f - pn));
+    }
+    if (in && pairs) {
+      lg = A.a.c1[n];
+      A.a.xg[n] = xs[c];   // x^(0), read after the first barrier
     }
     ls[c] = lg;
   }
@@ -959,8 +985,13 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           qmr += red_r[I * NT + c];
         }
         const float x = xs[c];
-        const float xt = coordinate_step(x, q, qmr, gs[c], ls[c], A.a);
+        // MAP-K2: x^(k) of every device is in half k % 2 of the exchange
+        // buffer (written before this iteration's barriers); x^(k+1) goes to
+        // the other half, which no workgroup reads before the next barriers.
+        const float prior = pairs ? ls[c] + pair_sum(A.a, n, A.N, A.a.xg + (size_t)(it & 1) * A.N) : ls[c];
+        const float xt = coordinate_step(x, q, qmr, gs[c], prior, A.a);
         xs[c] = (1.0f - rho) * x + rho * xt;
+        if (pairs) A.a.xg[(size_t)((it + 1) & 1) * A.N + n] = xs[c];
         if (A.x_hist) A.x_hist[(size_t)(it + 1) * A.N + n] = xs[c];
         if (last) {
           if (A.q_out) A.q_out[n] = q;
@@ -1303,7 +1334,8 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
   const int n0 = g * NT;
   const int gwave = g * kWaves + wave, nwaves = A.G * kWaves;
   unsigned gen = 0;
-  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
+  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K || A.a.variant == PSCA_MAP_K2);
+  const bool pairs = (A.a.variant == PSCA_MAP_K2);
   float2 *sig = A.sigma;
 
   for (int c = tid; c < NT; c += THREADS) {
@@ -1316,6 +1348,10 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     if (in && A.a.p) {
       const float pn = A.a.p[n];
       lg = logf(pn / (1.0f - pn));
+    }
+    if (in && pairs) {
+      lg = A.a.c1[n];
+      A.a.xg[n] = xs[c];   // x^(0), read after the first barrier
     }
     ls[c] = lg;
   }
@@ -1597,8 +1633,10 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
           qmr += red_r[I * NT + c];
         }
         const float x = xs[c];
-        const float xt = coordinate_step(x, q, qmr, gs[c], ls[c], A.a);
+        const float prior = pairs ? ls[c] + pair_sum(A.a, n, A.N, A.a.xg + (size_t)(it & 1) * A.N) : ls[c];
+        const float xt = coordinate_step(x, q, qmr, gs[c], prior, A.a);
         xs[c] = (1.0f - rho) * x + rho * xt;
+        if (pairs) A.a.xg[(size_t)((it + 1) & 1) * A.N + n] = xs[c];
         if (A.x_hist) A.x_hist[(size_t)(it + 1) * A.N + n] = xs[c];
         if (last) {
           if (A.q_out) A.q_out[n] = q;
@@ -1779,7 +1817,7 @@ int validate_params(const psca_params *prm, int L, int N, bool need_iters) {
   if (!prm) return PSCA_EINVAL;
   if (L < 1 || N < 1) return PSCA_EINVAL;
   if (L > kMaxL) return PSCA_ENOTSUP;
-  if (prm->variant < PSCA_ML_K || prm->variant > PSCA_MAP_UR) return PSCA_EINVAL;
+  if (prm->variant < PSCA_ML_K || prm->variant > PSCA_MAP_K2) return PSCA_EINVAL;
   if (!(prm->sigma2 > 0.0f) || !isfinite(prm->sigma2)) return PSCA_EINVAL;
   if (prm->M < 1) return PSCA_EINVAL;
   if (need_iters) {
@@ -1788,8 +1826,12 @@ int validate_params(const psca_params *prm, int L, int N, bool need_iters) {
                       prm->rho_decay > 2.0f))
       return PSCA_EINVAL;
   }
-  if ((prm->variant == PSCA_ML_K || prm->variant == PSCA_MAP_K) && !prm->g) return PSCA_EINVAL;
+  if ((prm->variant == PSCA_ML_K || prm->variant == PSCA_MAP_K || prm->variant == PSCA_MAP_K2) && !prm->g)
+    return PSCA_EINVAL;
   if (prm->variant == PSCA_MAP_K && !prm->p) return PSCA_EINVAL;
+  if (prm->variant == PSCA_MAP_K2 &&
+      (!prm->c1 || !prm->c2_ptr || prm->c2_nnz < 0 || (prm->c2_nnz > 0 && (!prm->c2_col || !prm->c2_val))))
+    return PSCA_EINVAL;
   if (prm->variant == PSCA_MAP_UR) {
     if (!(prm->d_lo > 0.0f) || !(prm->d_hi > prm->d_lo) || !(prm->pl_c0 > 0.0f) || !(prm->pl_beta > 0.0f) ||
         !(prm->eps > 0.0f) || !isfinite(prm->d_hi) || !isfinite(prm->pl_c0) || !isfinite(prm->pl_beta))
@@ -1804,8 +1846,15 @@ StepArgs make_step_args(const psca_params *prm) {
   StepArgs a;
   a.variant = prm->variant;
   a.inv_M = (float)(1.0 / (double)prm->M);
-  a.g = (prm->variant == PSCA_ML_K || prm->variant == PSCA_MAP_K) ? prm->g : nullptr;
+  const bool k2 = prm->variant == PSCA_MAP_K2;
+  a.g = (prm->variant == PSCA_ML_K || prm->variant == PSCA_MAP_K || k2) ? prm->g : nullptr;
   a.p = (prm->variant == PSCA_MAP_K) ? prm->p : nullptr;
+  a.c1 = k2 ? prm->c1 : nullptr;
+  a.c2_ptr = k2 ? prm->c2_ptr : nullptr;
+  a.c2_col = k2 ? prm->c2_col : nullptr;
+  a.c2_val = k2 ? prm->c2_val : nullptr;
+  a.c2_nnz = k2 ? prm->c2_nnz : 0;
+  a.xg = nullptr;   // bound with the workspace
   a.eps = a.g_l = a.g_u = a.h2_b = a.dens_c = 0.0f;
   if (prm->variant == PSCA_MAP_UR) {
     const double beta = prm->pl_beta;
@@ -1864,10 +1913,11 @@ struct InstPlan {
   size_t lds, ws;
 };
 
-size_t ws_bytes_of(int Lp, int G) {
+size_t ws_bytes_of(int Lp, int G, int N) {
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
   return align_up((size_t)G * E * sizeof(double2)) + align_up(E * sizeof(float2)) +
-         align_up((size_t)G * 16 * sizeof(unsigned)) + 3 * align_up(sizeof(unsigned));
+         align_up((size_t)G * 16 * sizeof(unsigned)) + 3 * align_up(sizeof(unsigned)) +
+         align_up(2 * (size_t)N * sizeof(float));
 }
 
 // Point the instance's work buffers into `base` (laid out as ws_bytes_of).
@@ -1881,6 +1931,8 @@ void bind_ws(CoopArgs &a, char *base, const InstPlan &p) {
   a.bar.release = (unsigned *)(base + off); off += align_up(sizeof(unsigned));
   a.bar.abort_flag = (int32_t *)(base + off); off += align_up(sizeof(unsigned));
   if (!a.status) a.status = (int32_t *)(base + off);
+  off += align_up(sizeof(unsigned));
+  a.a.xg = (float *)(base + off);   // [2][N] iterate exchange (MAP-K2)
 }
 
 void fill_args(CoopArgs &a, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm, int iters,
@@ -1936,7 +1988,8 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
   const size_t o_abt = align_up(o_rel + sizeof(unsigned));
   const size_t o_st = align_up(o_abt + sizeof(unsigned));
-  const size_t total = align_up(o_st + sizeof(unsigned));
+  const size_t o_xg = align_up(o_st + sizeof(unsigned));
+  const size_t total = align_up(o_xg + 2 * (size_t)N * sizeof(float));
   int rc = ensure_ws(ctx, total);
   if (rc != PSCA_OK) return rc;
   char *base = (char *)ctx->ws;
@@ -1951,6 +2004,7 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   a.c.bar.abort_flag = (int32_t *)(base + o_abt);
   if (!a.c.status) a.c.status = (int32_t *)(base + o_st);
   a.sigma_copy = (float2 *)(base + o_cp);
+  a.c.a.xg = (float *)(base + o_xg);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.c.bar.arrive, p.G, a.c.bar.release,
                      a.c.bar.abort_flag, a.c.status);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
@@ -1978,7 +2032,7 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
     const int cap = max_coresident(ctx, kc, lds);
     if (cap <= 0) return PSCA_ENOTSUP;
     if (G <= cap) {
-      p = InstPlan{Lp, ncb, NT, G, lds, ws_bytes_of(Lp, G)};
+      p = InstPlan{Lp, ncb, NT, G, lds, ws_bytes_of(Lp, G, N)};
       break;
     }
   }
@@ -2123,9 +2177,9 @@ struct BatchPlan {
 
 size_t packed_entries(int Lp) { return (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256; }
 
-size_t inst_ws_bytes(int Lp, int G) {
+size_t inst_ws_bytes(int Lp, int G, int N) {
   return align_up(packed_entries(Lp) * sizeof(float2)) + align_up((size_t)G * 16 * sizeof(unsigned)) +
-         3 * align_up(sizeof(unsigned));
+         3 * align_up(sizeof(unsigned)) + align_up(2 * (size_t)N * sizeof(float));
 }
 
 // Largest column tile (multiple of 16, at most 64) whose LDS fits a workgroup.
@@ -2186,7 +2240,7 @@ int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
     // instance for team mates still busy with earlier ones
     q.G = T;
     q.lds = lds_bytes(q.Lp, q.NT, kBatchThreads / 64);
-    q.ws = inst_ws_bytes(q.Lp, q.G);
+    q.ws = inst_ws_bytes(q.Lp, q.G, pr[b].N);
     plan.lds = std::max(plan.lds, q.lds);
     plan.iters[b] = iters_cap >= 0 ? std::min(pr[b].prm.iters, iters_cap) : pr[b].prm.iters;
     const double Lb = q.Lp / 16;
@@ -2237,6 +2291,8 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
     a.bar.release = (unsigned *)w;        w += align_up(sizeof(unsigned));
     a.bar.abort_flag = (int32_t *)w;      w += align_up(sizeof(unsigned));
     if (!a.status) a.status = (int32_t *)w;
+    w += align_up(sizeof(unsigned));
+    a.a.xg = (float *)w;                  // [2][N] iterate exchange (MAP-K2)
     // every rank of a team owns the same slot for all of the team's instances:
     // a rank that sits out an instance may start the next one early
     a.partials = (double2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
@@ -2617,7 +2673,7 @@ int psca_layer_backward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32
   if (!(rho >= 0.0f) || rho > 1.0f) return PSCA_EINVAL;
   int rc = validate_params(prm, L, N, false);
   if (rc != PSCA_OK) return rc;
-  if (L > 64) return PSCA_ENOTSUP;
+  if (L > 64 || prm->variant == PSCA_MAP_K2) return PSCA_ENOTSUP;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
   return run_layer_backward(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, rho, x_in, v, grad_x,

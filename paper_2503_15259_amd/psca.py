@@ -15,9 +15,9 @@ from typing import Optional
 import torch
 
 from . import _native as N
-from ._native import ML_K, MAP_K, ML_UD, MAP_UR, MAX_L, PscaError  # noqa: F401
+from ._native import ML_K, MAP_K, ML_UD, MAP_UR, MAP_K2, MAX_L, PscaError  # noqa: F401
 
-VARIANTS = {"ML-K": ML_K, "MAP-K": MAP_K, "ML-UD": ML_UD, "MAP-UR": MAP_UR}
+VARIANTS = {"ML-K": ML_K, "MAP-K": MAP_K, "ML-UD": ML_UD, "MAP-UR": MAP_UR, "MAP-K2": MAP_K2}
 
 
 def colmajor(t: torch.Tensor) -> torch.Tensor:
@@ -94,6 +94,12 @@ class Params:
     pl_c0: float = 10.0 ** 0.89
     pl_beta: float = 3.76
     eps: float = 0.01
+    # MAP-K2: first-order coefficients [N] and the pairwise coefficients as
+    # CSR (row pointers [N+1] int32, columns [nnz] int32, values [nnz] float32)
+    c1: Optional[torch.Tensor] = None
+    c2_ptr: Optional[torch.Tensor] = None
+    c2_col: Optional[torch.Tensor] = None
+    c2_val: Optional[torch.Tensor] = None
 
     def to_c(self) -> N.PscaParams:
         c = N.PscaParams()
@@ -108,6 +114,11 @@ class Params:
         c.p = None if self.p is None else self.p.data_ptr()
         c.d_lo, c.d_hi = float(self.d_lo), float(self.d_hi)
         c.pl_c0, c.pl_beta, c.eps = float(self.pl_c0), float(self.pl_beta), float(self.eps)
+        c.c1 = None if self.c1 is None else self.c1.data_ptr()
+        c.c2_ptr = None if self.c2_ptr is None else self.c2_ptr.data_ptr()
+        c.c2_col = None if self.c2_col is None else self.c2_col.data_ptr()
+        c.c2_val = None if self.c2_val is None else self.c2_val.data_ptr()
+        c.c2_nnz = 0 if self.c2_col is None else int(self.c2_col.numel())
         return c
 
     def check_tensors(self, device, n):
@@ -117,6 +128,23 @@ class Params:
                 _need(t, torch.float32, device, name)
                 if t.numel() != n or not t.is_contiguous():
                     raise ValueError(f"{name} must be a contiguous float32 vector of length N")
+        if self.c1 is not None:
+            _need(self.c1, torch.float32, device, "c1")
+            if self.c1.numel() != n or not self.c1.is_contiguous():
+                raise ValueError("c1 must be a contiguous float32 vector of length N")
+        if self.c2_ptr is not None:
+            _need(self.c2_ptr, torch.int32, device, "c2_ptr")
+            if self.c2_ptr.numel() != n + 1 or not self.c2_ptr.is_contiguous():
+                raise ValueError("c2_ptr must be a contiguous int32 vector of length N + 1")
+            for name, dt in (("c2_col", torch.int32), ("c2_val", torch.float32)):
+                t = getattr(self, name)
+                if t is None:
+                    raise ValueError(f"{name} is required with c2_ptr")
+                _need(t, dt, device, name)
+                if not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous")
+            if self.c2_col.numel() != self.c2_val.numel():
+                raise ValueError("c2_col and c2_val must have the same length")
         if self.rho is not None:
             _need(self.rho, torch.float32, device, "rho")
             if self.rho.numel() < self.iters or not self.rho.is_contiguous():

@@ -48,11 +48,31 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.psca_threshold(None, 4, ctypes.c_float(0.5), None, None) == N.PSCA_EINVAL
 
 
-def test_params_struct_layout_matches_header():
-    # int32 variant, int32 iters, float rho0, float rho_decay, ptr rho, float sigma2,
-    # int32 M, ptr g, ptr p, 5 floats -> 4+4+4+4+8+4+4+8+8+20 = 68, padded to 72
-    assert ctypes.sizeof(N.PscaParams) == 72
-    assert N.PscaParams.rho.offset == 16 and N.PscaParams.g.offset == 32
+def test_params_struct_layout_matches_header(tmp_path):
+    """Field offsets and sizes of the ctypes mirrors against the C compiler's
+    layout of include/psca.h."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in N.PscaParams._fields_]
+    pfields = [f for f, _ in N.PscaProblem._fields_]
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psca.h"', "int main(void) {",
+             'printf("%zu %zu\\n", sizeof(psca_params), sizeof(psca_problem));']
+    lines += [f'printf("%zu\\n", offsetof(psca_params, {f}));' for f in fields]
+    lines += [f'printf("%zu\\n", offsetof(psca_problem, {f}));' for f in pfields]
+    lines += ["return 0; }"]
+    src.write_text("\n".join(lines))
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    vals = [int(v) for v in out]
+    assert vals[0] == ctypes.sizeof(N.PscaParams)
+    assert vals[1] == ctypes.sizeof(N.PscaProblem)
+    assert vals[2:2 + len(fields)] == [getattr(N.PscaParams, f).offset for f in fields]
+    assert vals[2 + len(fields):] == [getattr(N.PscaProblem, f).offset for f in pfields]
 
 
 def test_missing_library_fails_loudly(tmp_path):
