@@ -250,15 +250,19 @@ def run_uneven(args):
 
 
 # ---------------------------------------------------------------------------
-# Large scale: N = 10^4 devices, L = 200, M = 256, one detection per launch
+# Large scale: N = 10^4 devices, L = 200, M = 256, one detection per launch;
+# plain PSCA (ML-K and MAP-UR, 200 iterations) and the unrolled ML-K network
+# against ML-K PSCA at the same equal-error rate
 # ---------------------------------------------------------------------------
-LARGE_POOL = 4
+LARGE_POOL = 4      # instances cycled by the timed PSCA-200 launches
+LARGE_EVAL = 16     # instances of the equal-error comparison (seeds disjoint from training)
 
 
 def run_large(args):
     import numpy as np
     import torch
     from paper_2503_15259_amd import instances as I
+    from paper_2503_15259_amd import metrics
     from paper_2503_15259_amd import psca as P
 
     if not torch.cuda.is_available():
@@ -267,47 +271,85 @@ def run_large(args):
     torch.cuda.set_device(dev)
     w = I.WORKLOADS["large"]
     N, L, M, iters = w["N"], w["L"], w["M"], w["iters"]
-    insts = [I.workload_instance("large", i) for i in range(LARGE_POOL)]
+    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20.json")) as f:
+        trained = json.load(f)
+    K = trained["K"]
+    rho_net = torch.tensor(trained["rho"], dtype=torch.float32, device=dev)
     ctx = P.Context(0)
-    data = []
-    for inst in insts:
+    stream = torch.cuda.current_stream(dev)
+
+    def upload(inst):
         S = P.colmajor(torch.from_numpy(inst.S.astype(np.complex64)).to(dev))
         Y = P.colmajor(torch.from_numpy(inst.Y.astype(np.complex64)).to(dev))
         g = torch.from_numpy(inst.g.astype(np.float32)).to(dev)
-        data.append((Y, S, g, inst))
-    stream = torch.cuda.current_stream(dev)
-    res = {}
-    for name, variant in (("ML-K", P.ML_K), ("MAP-UR", P.MAP_UR)):
-        def one(i):
-            Y, S, g, inst = data[i % LARGE_POOL]
-            prm = P.Params(variant=variant, iters=iters, sigma2=inst.sigma2, M=M, d_lo=inst.d_lo,
-                           d_hi=inst.d_hi, pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS,
-                           g=g if variant == P.ML_K else None)
-            return P.detect_y(Y, S, prm, ctx=ctx)
+        return P.sample_cov(Y, ctx=ctx), S, g, inst
+
+    def params(variant, inst, g, n_iter, rho=None):
+        return P.Params(variant=variant, iters=n_iter, sigma2=inst.sigma2, M=M, d_lo=inst.d_lo, d_hi=inst.d_hi,
+                        pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS,
+                        g=g if variant == P.ML_K else None, rho=rho)
+
+    def timed(fn, n):
         for i in range(args.warmup):
-            one(i)
+            fn(i)
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
         for i, (a, b) in enumerate(ev):
             a.record(stream)
-            one(i)
+            fn(i)
             b.record(stream)
         torch.cuda.synchronize()
-        res[name] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    # equal-error rates of the network and of ML-K PSCA after every k <= 200
+    evals = [upload(I.workload_instance("large", 1000 + i)) for i in range(LARGE_EVAL)]
+    truth = np.concatenate([e[3].alpha for e in evals])
+    net_scores, hists = [], []
+    for Sh, S, g, inst in evals:
+        net_scores.append(P.net_forward(Sh, S, params(P.ML_K, inst, g, K, rho_net), ctx=ctx)[-1].cpu().numpy())
+        hists.append(P.net_forward(Sh, S, params(P.ML_K, inst, g, iters), ctx=ctx).cpu().numpy())
+    eer_net = metrics.equal_error_point(np.concatenate(net_scores), truth)[0]
+    eer_psca = [metrics.equal_error_point(np.concatenate([h[k] for h in hists]), truth)[0]
+                for k in range(1, iters + 1)]
+    matched = [k for k in range(1, iters + 1) if eer_psca[k - 1] <= eer_net]
+    k_star = matched[0] if matched else iters
+
+    # timings: one detection per launch, inputs resident in HBM
+    pool = evals[:LARGE_POOL]
+    res = {}
+    for name, variant in (("ML-K", P.ML_K), ("MAP-UR", P.MAP_UR)):
+        res[name] = timed(lambda i, v=variant: P.detect(pool[i % LARGE_POOL][0], pool[i % LARGE_POOL][1],
+                                                        params(v, pool[i % LARGE_POOL][3], pool[i % LARGE_POOL][2],
+                                                               iters), ctx=ctx), args.steps)
+    ms_k_star = timed(lambda i: P.detect(pool[i % LARGE_POOL][0], pool[i % LARGE_POOL][1],
+                                         params(P.ML_K, pool[i % LARGE_POOL][3], pool[i % LARGE_POOL][2], k_star),
+                                         ctx=ctx), args.steps)
+    ms_net = timed(lambda i: P.net_forward(pool[i % LARGE_POOL][0], pool[i % LARGE_POOL][1],
+                                           params(P.ML_K, pool[i % LARGE_POOL][3], pool[i % LARGE_POOL][2], K, rho_net),
+                                           ctx=ctx), args.steps)
     ms = float(np.mean(list(res.values())))
     flops = iters * iteration_flops(N, L)
     achieved = flops / (ms / 1e3) / 1e12
+    tr = trained["train"]
     line = {
-        "metric": METRIC, "value": round(1e3 / ms, 4), "unit": "instances/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "metric": METRIC, "value": round(1e3 / ms_net, 4), "unit": "instances/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_net, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"large-scale PSCA, one detection per launch: N={N}, L={L}, M={M}, "
-                               f"p={w['p']}, {iters} iterations, ML-K and MAP-UR",
-                   "N": N, "L": L, "M": M, "iters": iters},
-        "per_estimator_ms": {k: round(v, 3) for k, v in res.items()},
+        "config": {"workload": f"large-scale detection, one instance per launch: N={N}, L={L}, M={M}, "
+                               f"p={w['p']}; unrolled ML-K network (K={K}, step sizes trained at "
+                               f"N={tr['N']}, L={tr['L']}, M={tr['M']}, p={tr['p']}) against ML-K PSCA at the "
+                               f"same equal-error rate; plain PSCA-{iters} for ML-K and MAP-UR",
+                   "N": N, "L": L, "M": M, "iters": iters, "K": K, "eval_instances": LARGE_EVAL},
+        "equal_error": {"net": round(eer_net, 5), "psca_at_k_star": round(eer_psca[k_star - 1], 5),
+                        f"psca_{iters}": round(eer_psca[iters - 1], 5), "k_star": k_star, "matched": bool(matched)},
+        "net_ms": round(ms_net, 3),
+        "psca_at_k_star_instances_per_s": round(1e3 / ms_k_star, 4),
+        f"psca_{iters}_instances_per_s": {k: round(1e3 / v, 4) for k, v in res.items()},
+        "net_speedup_vs_psca_at_k_star": round(ms_k_star / ms_net, 3),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
-                     "kernel": "k_psca_large", "flops_per_launch": flops, "avg_launch_ms": round(ms, 3)},
+                     "kernel": f"k_psca_large (PSCA-{iters}, ML-K and MAP-UR)", "flops_per_launch": flops,
+                     "avg_launch_ms": round(ms, 3)},
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
