@@ -335,7 +335,7 @@ struct CoopArgs {
   float *x_out, *q_out, *r_out, *xt_out;
   float *x_hist;        // [iters + 1][N] every iterate, or null
   int32_t *status;
-  double2 *partials;    // [G][pstride], workgroup g's packed FP64 partial of Sigma at g * pstride
+  float2 *partials;     // [G][pstride], workgroup g's packed partial of Sigma at g * pstride
   size_t pstride;       // >= NB * 256
   float2 *sigma;        // [NB * 256]
   GridBar bar;
@@ -531,12 +531,13 @@ __device__ __forceinline__ void chol_trail(float2 *WS, int P, int J, int I, int 
 // ---------------------------------------------------------------------------
 // Packed lower blocks of the tile's Gram matrix S_t diag(wv) S_t^H into dst
 // (MFMA, complex product on the real 4-product split).  The products of the
-// FP32 operands are exact in FP64 and the sums are FP64: the entries of Sigma
-// then carry a single rounding (when it is stored), which matters because q
-// and q - r move with kappa(Sigma) times the entry errors of Sigma.
-// St: [Lp][PT] S tile.
+// FP32 operands are exact in FP64 and the sums over the tile are FP64; each
+// entry is rounded once to FP32 when stored.  With the FP64 sum over the
+// partials in phase B, the entries of Sigma carry about one rounding, which
+// matters because q and q - r move with kappa(Sigma) times the entry errors
+// of Sigma.  St: [Lp][PT] S tile.
 template <int LP, int THREADS>
-__device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, const float *wv, double2 *dst) {
+__device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, const float *wv, float2 *dst) {
   constexpr int kWaves = THREADS / 64, Lb = LP / 16, NB = Lb * (Lb + 1) / 2;
   constexpr int kBlocksPerWave = (NB + kWaves - 1) / kWaves;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
@@ -561,9 +562,9 @@ __device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, con
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) cmfma_d(av4[ks], bv4[ks], cr, ci);
       }
-      double2 *o = dst + b * 256 + l16 * 16 + lq;   // rows lq + 4v of column l16
+      float2 *o = dst + b * 256 + l16 * 16 + lq;   // rows lq + 4v of column l16
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[4 * v] = make_double2(cr[v], ci[v]);
+      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)cr[v], (float)ci[v]);
     }
   }
 }
@@ -585,10 +586,10 @@ __device__ __forceinline__ void store_reduced(float2 *out, int e, double2 sm, bo
 // Workgroup g's 1/G slice of the sum over the G packed partials (rank h at
 // partials + h * pstride) into out; with add_diag, sigma2 is added to the
 // diagonal of rows < L and 1 to padded rows (isolated unit pivots), and the
-// imaginary part of the diagonal is zeroed.  The FP64 partials are summed
-// in FP64 and the result rounded once.  scr: THREADS double2 of LDS.
+// imaginary part of the diagonal is zeroed.  The partials are summed in FP64
+// and the result rounded once.  scr: THREADS double2 of LDS.
 template <int LP, int THREADS>
-__device__ __forceinline__ void reduce_slice(const double2 *partials, size_t pstride, int G, int g, float2 *out,
+__device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstride, int G, int g, float2 *out,
                                              double2 *scr, bool add_diag, int L, float sigma2) {
   constexpr int Lb = LP / 16, E = Lb * (Lb + 1) / 2 * 256;
   static_assert(THREADS * sizeof(double2) <= (THREADS / 64) * 256 * sizeof(float2), "scr holds THREADS double2");
@@ -602,7 +603,7 @@ __device__ __forceinline__ void reduce_slice(const double2 *partials, size_t pst
       const int e = start + tid % cnt, part = tid / cnt;
       double2 acc = make_double2(0.0, 0.0);
       for (int h = part; h < G; h += Pp) {
-        const double2 v = partials[(size_t)h * pstride + e];
+        const float2 v = partials[(size_t)h * pstride + e];
         acc.x += v.x;
         acc.y += v.y;
       }
@@ -622,7 +623,7 @@ __device__ __forceinline__ void reduce_slice(const double2 *partials, size_t pst
     for (int e = start + tid; e < end; e += THREADS) {
       double2 sm = make_double2(0.0, 0.0);
       for (int h = 0; h < G; ++h) {
-        const double2 v = partials[(size_t)h * pstride + e];
+        const float2 v = partials[(size_t)h * pstride + e];
         sm.x += v.x;
         sm.y += v.y;
       }
@@ -1030,7 +1031,7 @@ struct BackArgs {
   const float *v;       // [N] dL/dx'
   float *grad_x;        // [N] dL/dx
   float *rho_part;      // [G] per-workgroup parts of dL/drho
-  double2 *partials_b;  // [G][pstride] partials of G_b (those of G_a use c.partials)
+  float2 *partials_b;   // [G][pstride] partials of G_b (those of G_a use c.partials)
   float2 *gram_a, *gram_b;   // packed G_a, G_b
 };
 
@@ -1363,8 +1364,14 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
   double rho_d = A.rho0;
   bool failed = false, aborted = false;
   for (int it = 0; it < A.iters; ++it) {
-    // ---- A. packed Gram partial of the tile, S read from memory
+    // ---- A. packed Gram partial of the tile; the S tile is staged in Yt,
+    // where it stays until the solves of C4 overwrite it
+    PSCA_MARK(it, 0);
     for (int c = tid; c < NT; c += THREADS) red_q[c] = known ? gs[c] * xs[c] : xs[c];
+    for (int e = tid; e < Lp * NT; e += THREADS) {
+      const int c = e / Lp, i = e - c * Lp;   // down a column: coalesced
+      Yt[i * PT + c] = s_at(i, c);
+    }
     __syncthreads();
     for (int b = wave; b < NB; b += kWaves) {
       int I, J;
@@ -1375,8 +1382,8 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int c = 16 * cb + 4 * ks + lq;
-          const float2 sv = s_at(16 * J + l16, c);
-          const float2 av = s_at(16 * I + l16, c);
+          const float2 sv = Yt[(16 * J + l16) * PT + c];
+          const float2 av = Yt[(16 * I + l16) * PT + c];
           const double w = red_q[c];
           av4[ks] = make_double2(av.x, av.y);
           bv4[ks] = make_double2(w * sv.x, -w * sv.y);
@@ -1384,20 +1391,38 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) cmfma_d(av4[ks], bv4[ks], cr, ci);
       }
-      double2 *o = A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + lq;
+      float2 *o = A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + lq;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[4 * v] = make_double2(cr[v], ci[v]);
+      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)cr[v], (float)ci[v]);
     }
+    PSCA_MARK(it, 1);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ---- B. reduce a slice into Sigma and its copy
+    PSCA_MARK(it, 2);
     {
+      // Pp threads per element of the slice each sum every Pp-th partial
+      // (double), then one thread per element adds the Pp sums in LDS.
       const int per = (E + A.G - 1) / A.G;
-      const int start = g * per, end = min(E, start + per);
-      for (int e = start + tid; e < end; e += THREADS) {
+      const int start = g * per, end = min(E, start + per), cnt = max(0, end - start);
+      const int Pp = cnt > 0 ? max(1, THREADS / cnt) : 1;
+      double2 *dscr = (double2 *)scr;   // [THREADS]
+      for (int e0 = 0; e0 < cnt; e0 += THREADS / Pp) {
+        const int e_loc = e0 + tid % (THREADS / Pp), part = tid / (THREADS / Pp);
+        double2 acc = make_double2(0.0, 0.0);
+        if (part < Pp && e_loc < cnt)
+          for (int h = part; h < A.G; h += Pp) {
+            const float2 v = A.partials[(size_t)h * A.pstride + start + e_loc];
+            acc.x += v.x;
+            acc.y += v.y;
+          }
+        dscr[tid] = acc;
+        __syncthreads();
+        const int e = start + e0 + tid;
+        if (tid < THREADS / Pp && e0 + tid < cnt) {
         double2 sm = make_double2(0.0, 0.0);   // summed in double, rounded once
-        for (int h = 0; h < A.G; ++h) {
-          const double2 v = A.partials[(size_t)h * A.pstride + e];
+        for (int q = 0; q < Pp; ++q) {
+          const double2 v = dscr[q * (THREADS / Pp) + tid];
           sm.x += v.x;
           sm.y += v.y;
         }
@@ -1411,11 +1436,15 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
         const float2 sf = make_float2((float)sm.x, (float)sm.y);
         sig[e] = sf;
         Lg.sigma_copy[e] = sf;
+        }
+        __syncthreads();
       }
     }
+    PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ---- C1. cooperative blocked Cholesky in memory
+    PSCA_MARK(it, 4);
     for (int J = 0; J < Lb; ++J) {
       float2 *Wj = Wd + J * 256;
       for (int e = tid; e < 256; e += THREADS) Wj[e] = pblk(sig, J, J)[e];
@@ -1482,11 +1511,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     if (failed || aborted) break;
 
     // ---- C4. local solves: Y = L^-1 S_t, q = |y|^2, B = L^-H Y
-    for (int e = tid; e < Lp * NT; e += THREADS) {
-      const int c = e / Lp, i = e - c * Lp;
-      Yt[i * PT + c] = s_at(i, c);
-    }
-    __syncthreads();
+    PSCA_MARK(it, 5);   // Yt still holds the S tile of phase A
     for (int I = 0; I < Lb; ++I) {   // forward: Y_I = W_II (S_I - sum_{K<I} L_IK Y_K)
       for (int cb = wave; cb < ncb; cb += kWaves) {
         f4 tr, ti;
@@ -1539,6 +1564,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       red_q[I * NT + c] = acc;
     }
     __syncthreads();
+    PSCA_MARK(it, 6);
     for (int I = Lb - 1; I >= 0; --I) {   // backward: B_I = W_II^H (Y_I - sum_{K>I} L_KI^H B_K)
       for (int cb = wave; cb < ncb; cb += kWaves) {
         f4 tr, ti;
@@ -1583,6 +1609,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       __syncthreads();
     }
     // q - r = b^H (Sigma - SigmaHat) b
+    PSCA_MARK(it, 8);
     for (int t = wave; t < Lb * ncb; t += kWaves) {
       const int I = t / ncb, cb = t - I * ncb;
       f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
@@ -1618,6 +1645,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     __syncthreads();
 
     // ---- C5. coordinate step and update
+    PSCA_MARK(it, 9);
     float rho;
     if (A.rho_fixed >= 0.0f) rho = A.rho_fixed;
     else if (A.rho_dev) rho = A.rho_dev[it];
@@ -1646,6 +1674,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       }
     }
     __syncthreads();
+    PSCA_MARK(it, 10);
   }
   for (int c = tid; c < NT; c += THREADS) {
     const int n = n0 + c;
@@ -1915,7 +1944,7 @@ struct InstPlan {
 
 size_t ws_bytes_of(int Lp, int G, int N) {
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
-  return align_up((size_t)G * E * sizeof(double2)) + align_up(E * sizeof(float2)) +
+  return align_up((size_t)G * E * sizeof(float2)) + align_up(E * sizeof(float2)) +
          align_up((size_t)G * 16 * sizeof(unsigned)) + 3 * align_up(sizeof(unsigned)) +
          align_up(2 * (size_t)N * sizeof(float));
 }
@@ -1925,7 +1954,7 @@ void bind_ws(CoopArgs &a, char *base, const InstPlan &p) {
   const size_t E = (size_t)(p.Lp / 16) * (p.Lp / 16 + 1) / 2 * 256;
   size_t off = 0;
   a.pstride = E;
-  a.partials = (double2 *)(base + off); off += align_up((size_t)p.G * E * sizeof(double2));
+  a.partials = (float2 *)(base + off); off += align_up((size_t)p.G * E * sizeof(float2));
   a.sigma = (float2 *)(base + off);    off += align_up(E * sizeof(float2));
   a.bar.arrive = (unsigned *)(base + off); off += align_up((size_t)p.G * 16 * sizeof(unsigned));
   a.bar.release = (unsigned *)(base + off); off += align_up(sizeof(unsigned));
@@ -1982,7 +2011,7 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   }
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
   const size_t o_pa = 0;
-  const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(double2));
+  const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
   const size_t o_cp = align_up(o_sig + E * sizeof(float2));
   const size_t o_arr = align_up(o_cp + E * sizeof(float2));
   const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
@@ -1996,7 +2025,7 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   LargeArgs a;
   fill_args(a.c, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
   a.c.x_hist = x_hist;
-  a.c.partials = (double2 *)(base + o_pa);
+  a.c.partials = (float2 *)(base + o_pa);
   a.c.pstride = E;
   a.c.sigma = (float2 *)(base + o_sig);
   a.c.bar.arrive = (unsigned *)(base + o_arr);
@@ -2117,8 +2146,8 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   }
   const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
   const size_t o_pa = 0;
-  const size_t o_pb = align_up(o_pa + (size_t)p.G * E * sizeof(double2));
-  const size_t o_sig = align_up(o_pb + (size_t)p.G * E * sizeof(double2));
+  const size_t o_pb = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
+  const size_t o_sig = align_up(o_pb + (size_t)p.G * E * sizeof(float2));
   const size_t o_ga = align_up(o_sig + E * sizeof(float2));
   const size_t o_gb = align_up(o_ga + E * sizeof(float2));
   const size_t o_arr = align_up(o_gb + E * sizeof(float2));
@@ -2132,7 +2161,7 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   char *base = (char *)ctx->ws;
   BackArgs b;
   fill_args(b.c, Sh, S, L, N, prm, 1, rho, x_in, nullptr, nullptr, nullptr, nullptr, status, p);
-  b.c.partials = (double2 *)(base + o_pa);
+  b.c.partials = (float2 *)(base + o_pa);
   b.c.pstride = E;
   b.c.sigma = (float2 *)(base + o_sig);
   b.c.bar.arrive = (unsigned *)(base + o_arr);
@@ -2143,7 +2172,7 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   b.v = v;
   b.grad_x = grad_x;
   b.rho_part = (float *)(base + o_rp);
-  b.partials_b = (double2 *)(base + o_pb);
+  b.partials_b = (float2 *)(base + o_pb);
   b.gram_a = (float2 *)(base + o_ga);
   b.gram_b = (float2 *)(base + o_gb);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, b.c.bar.arrive, p.G, b.c.bar.release,
@@ -2272,7 +2301,7 @@ int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
   }
   plan.part_off = off;
   plan.E_max = E_max;
-  plan.part_stride = align_up((size_t)T * E_max * sizeof(double2));
+  plan.part_stride = align_up((size_t)T * E_max * sizeof(float2));
   plan.ws_bytes = off + plan.part_stride * plan.n_teams;
   return PSCA_OK;
 }
@@ -2295,7 +2324,7 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
     a.a.xg = (float *)w;                  // [2][N] iterate exchange (MAP-K2)
     // every rank of a team owns the same slot for all of the team's instances:
     // a rank that sits out an instance may start the next one early
-    a.partials = (double2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
+    a.partials = (float2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
     a.pstride = plan.E_max;
     out[b] = a;
   }
