@@ -1287,24 +1287,58 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-// ---------------------------------------------------------------------------
-// Pilot lengths above 96: the L x L matrix no longer fits a workgroup's LDS
-// ---------------------------------------------------------------------------
-// Sigma stays packed in memory (lower 16x16 blocks, column-major inside) and
-// the instance's workgroups factor it together: every workgroup factors the
+// Pilot lengths 97..256: the L x L matrices no longer fit a workgroup's LDS
+// beside an S tile, so Sigma, its factor L and Sigma - SigmaHat live in
+// device memory (packed lower 16x16 blocks) and the factorisation is spread
+// over the instance's workgroups.  Block step J: every workgroup factors the
 // diagonal block J redundantly in registers and keeps W_JJ = L_JJ^-1 in LDS;
 // the panel blocks L_IJ = A_IJ W_JJ^H and then the trailing updates
 // A_IK -= L_IJ L_KJ^H are spread over all wavefronts of the instance, with a
-// device-wide barrier after each.  Each workgroup then solves its own tile
-// locally: Y = L^-1 S_t (q = |y|^2), B = L^-H Y, and
-// q - r = b^H (Sigma - SigmaHat) b with Sigma from a copy kept before the
-// factorisation.
+// device-wide barrier after each.  Each workgroup then solves its own tile,
+// Y = L^-1 S_t (q = |y|^2) and B = L^-H Y, one block row per round with the
+// row's block products split over its wavefronts, and forms
+// q - r = b^H (Sigma - SigmaHat) b, the difference taken in phase B from the
+// FP64 sum.
 constexpr int kLargeMaxLp = 256;
 
 struct LargeArgs {
   CoopArgs c;             // sigma: packed Sigma, factored in place into L
-  float2 *sigma_copy;     // packed Sigma of the iteration
+  float2 *delta;          // packed Sigma - SigmaHat of the iteration
 };
+
+// Touches n float2 at p (16-byte loads spread over `nthreads` threads from
+// thread `t`) so that a later pass finds them in this XCD's L2; the loaded
+// bits are folded into a register that an empty asm statement consumes.
+__device__ __forceinline__ void warm_l2(const float2 *p, int n, int t, int nthreads) {
+  const float4 *q = (const float4 *)p;
+  unsigned x = 0;
+  for (int e = t; e < n / 2; e += nthreads) {
+    const float4 v = q[e];
+    x ^= __float_as_uint(v.x) ^ __float_as_uint(v.w);
+  }
+  asm volatile("" ::"v"(x));
+}
+
+// acc += A B over a run of 16x16 blocks, operands fetched four blocks at a
+// time so that their loads are in flight together.  get(q, a4, b4) fills
+// the operands of term q.
+template <typename Get>
+__device__ __forceinline__ void block_sum(int q0, int q1, int qs, f4 &cr, f4 &ci, Get get) {
+  for (int q = q0; q < q1; q += 4 * qs) {
+    float2 a4[4][4], b4[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (q + u * qs < q1) get(q + u * qs, a4[u], b4[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (q + u * qs < q1) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[u][ks], b4[u][ks], cr, ci);
+      }
+    }
+  }
+}
 
 __host__ __device__ inline size_t lds_large_bytes(int Lp, int NT, int waves) {
   const size_t f2 = (size_t)Lp * (NT + 1) + (size_t)(Lp / 16) * 256 + (size_t)waves * 256;
@@ -1433,9 +1467,10 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
           sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
           sm.y = 0.0;
         }
-        const float2 sf = make_float2((float)sm.x, (float)sm.y);
-        sig[e] = sf;
-        Lg.sigma_copy[e] = sf;
+        sig[e] = make_float2((float)sm.x, (float)sm.y);
+        const int i = 16 * I + ii, k = 16 * J + jj;   // Sigma - SigmaHat from the FP64 sum
+        const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+        Lg.delta[e] = make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y));
         }
         __syncthreads();
       }
@@ -1452,6 +1487,8 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       if (wave == 0) {
         const bool ok = leaf_chol(Wj, 16, lane);
         if (lane == 0) s_pd = ok ? 1 : 0;
+      } else if (J == 0) {   // while the first leaf runs: Sigma - SigmaHat into L2 for C4
+        warm_l2(Lg.delta, E, tid - 64, THREADS - 64);
       }
       __syncthreads();
       if (!s_pd) {   // uniform: every workgroup factors the same block
@@ -1459,7 +1496,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
         break;
       }
       if (J + 1 == Lb) break;
-      for (int I = J + 1 + gwave; I < Lb; I += nwaves) {   // panel L_IJ = A_IJ W_JJ^H
+      for (int I = J + 1 + gwave; I < Lb; I += nwaves) {   // panel L_IJ = A_IJ W_JJ^H, in place
         float2 *blk = sig + (size_t)blk_index(I, J) * 256;
         f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
         float2 a4[4], b4[4];
@@ -1510,128 +1547,118 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     }
     if (failed || aborted) break;
 
-    // ---- C4. local solves: Y = L^-1 S_t, q = |y|^2, B = L^-H Y
+    // ---- C4. local solves Y = L^-1 S_t (q = |y|^2), then B = L^-H Y, in place
+    // of the S tile, one block row per round.  In round R the block products
+    // of the row's sum are split over the wavefronts (ng per column block,
+    // each fetching four blocks at a time); one wavefront per column block adds
+    // the partial sums and applies the diagonal W_RR (or W_RR^H).
     PSCA_MARK(it, 5);   // Yt still holds the S tile of phase A
-    for (int I = 0; I < Lb; ++I) {   // forward: Y_I = W_II (S_I - sum_{K<I} L_IK Y_K)
-      for (int cb = wave; cb < ncb; cb += kWaves) {
-        f4 tr, ti;
+    warm_l2(sig, E, tid, THREADS);   // the factor L, read block by block below
+    {
+      const int ng = kWaves / ncb;            // wavefronts per column block
+      const int cbw = wave % ncb, gi = wave / ncb;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int r = 0; r < Lb; ++r) {
+          const int R = pass == 0 ? r : Lb - 1 - r;
+          if (gi < ng) {
+            f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+            if (pass == 0) {   // sum_{K<R} L_RK Y_K
+              block_sum(gi, R, ng, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+                const float2 *lrk = pblk(sig, R, K);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float2 y = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
-          tr[v] = y.x;
-          ti[v] = y.y;
-        }
-        for (int K = 0; K < I; ++K) {
-          const float2 *lik = pblk(sig, I, K);
-          float2 a4[4], b4[4];
+                for (int ks = 0; ks < 4; ++ks) {
+                  const int k = 4 * ks + lq;
+                  a4[ks] = lrk[k * 16 + l16];
+                  b4[ks] = Yt[(16 * K + k) * PT + 16 * cbw + l16];
+                }
+              });
+            } else {           // sum_{K>R} L_KR^H B_K
+              block_sum(R + 1 + gi, Lb, ng, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+                const float2 *lkr = pblk(sig, K, R);
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lq;
-            const float2 l = lik[k * 16 + l16];
-            a4[ks] = make_float2(-l.x, -l.y);
-            b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
+                for (int ks = 0; ks < 4; ++ks) {
+                  const int k = 4 * ks + lq;
+                  const float2 x = lkr[l16 * 16 + k];   // L_KR[k][l16]; A = conj of it
+                  a4[ks] = make_float2(x.x, -x.y);
+                  b4[ks] = Yt[(16 * K + k) * PT + 16 * cbw + l16];
+                }
+              });
+            }
+            float2 *T = scr + wave * 256;   // row-major partial sums
+#pragma unroll
+            for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = make_float2(cr[v], ci[v]);
           }
+          __syncthreads();
+          if (wave < ncb) {   // T = rhs_R - sum of the partials, then the diagonal block
+            float2 tv[4];
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], tr, ti);
-        }
-        float2 *T = scr + wave * 256;   // row-major staging of the right-hand side
+            for (int v = 0; v < 4; ++v) {
+              float2 acc = Yt[(16 * R + 4 * lq + v) * PT + 16 * wave + l16];
+              for (int h = 0; h < ng; ++h) {
+                const float2 x = scr[(wave + h * ncb) * 256 + (4 * lq + v) * 16 + l16];
+                acc.x -= x.x;
+                acc.y -= x.y;
+              }
+              tv[v] = acc;
+            }
+            wave_lds_sync();
+            float2 *T = scr + wave * 256;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = make_float2(tr[v], ti[v]);
-        wave_lds_sync();
-        f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-        float2 a4[4], b4[4];
+            for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = tv[v];
+            wave_lds_sync();
+            f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+            float2 a4[4], b4[4];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int k = 4 * ks + lq;
-          a4[ks] = Wd[I * 256 + k * 16 + l16];   // W_II[l16][k]
-          b4[ks] = T[k * 16 + l16];
-        }
+            for (int ks = 0; ks < 4; ++ks) {
+              const int k = 4 * ks + lq;
+              if (pass == 0) {
+                a4[ks] = Wd[R * 256 + k * 16 + l16];            // W_RR[l16][k]
+              } else {
+                const float2 w = Wd[R * 256 + l16 * 16 + k];    // W_RR[k][l16]; A = conj of it
+                a4[ks] = make_float2(w.x, -w.y);
+              }
+              b4[ks] = T[k * 16 + l16];
+            }
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
+            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(yr[v], yi[v]);
-        wave_lds_sync();
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < Lb * NT; e += THREADS) {   // q per row block and column
-      const int I = e / NT, c = e - I * NT;
-      float acc = 0.0f;
-      for (int i = 16 * I; i < 16 * I + 16; ++i) {
-        const float2 y = Yt[i * PT + c];
-        acc += y.x * y.x + y.y * y.y;
-      }
-      red_q[I * NT + c] = acc;
-    }
-    __syncthreads();
-    PSCA_MARK(it, 6);
-    for (int I = Lb - 1; I >= 0; --I) {   // backward: B_I = W_II^H (Y_I - sum_{K>I} L_KI^H B_K)
-      for (int cb = wave; cb < ncb; cb += kWaves) {
-        f4 tr, ti;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float2 y = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
-          tr[v] = y.x;
-          ti[v] = y.y;
-        }
-        for (int K = I + 1; K < Lb; ++K) {
-          const float2 *lki = pblk(sig, K, I);
-          float2 a4[4], b4[4];
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lq;
-            const float2 l = lki[l16 * 16 + k];   // L_KI[k][l16]; A = -conj of it
-            a4[ks] = make_float2(-l.x, l.y);
-            b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
+            for (int v = 0; v < 4; ++v) Yt[(16 * R + 4 * lq + v) * PT + 16 * wave + l16] = make_float2(yr[v], yi[v]);
           }
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], tr, ti);
+          __syncthreads();
         }
-        float2 *T = scr + wave * 256;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = make_float2(tr[v], ti[v]);
-        wave_lds_sync();
-        f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-        float2 a4[4], b4[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int k = 4 * ks + lq;
-          const float2 w = Wd[I * 256 + l16 * 16 + k];   // W_II[k][l16]; A = conj of it
-          a4[ks] = make_float2(w.x, -w.y);
-          b4[ks] = T[k * 16 + l16];
+        if (pass == 0) {   // q per row block and column
+          for (int e = tid; e < Lb * NT; e += THREADS) {
+            const int I = e / NT, c = e - I * NT;
+            float acc = 0.0f;
+            for (int i = 16 * I; i < 16 * I + 16; ++i) {
+              const float2 y = Yt[i * PT + c];
+              acc += y.x * y.x + y.y * y.y;
+            }
+            red_q[I * NT + c] = acc;
+          }
+          __syncthreads();
         }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(yr[v], yi[v]);
-        wave_lds_sync();
       }
-      __syncthreads();
     }
-    // q - r = b^H (Sigma - SigmaHat) b
     PSCA_MARK(it, 8);
+    // q - r = b^H (Sigma - SigmaHat) b, Sigma - SigmaHat from phase B
     for (int t = wave; t < Lb * ncb; t += kWaves) {
       const int I = t / ncb, cb = t - I * ncb;
       f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-      for (int K = 0; K < Lb; ++K) {
-        float2 a4[4], b4[4];
+      block_sum(0, Lb, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+        const float2 *dk = I >= K ? pblk(Lg.delta, I, K) : pblk(Lg.delta, K, I);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-          const int i = 16 * I + l16, k = 16 * K + 4 * ks + lq;
-          float2 sg;
+          const int k = 4 * ks + lq;
           if (I >= K) {
-            sg = Lg.sigma_copy[(size_t)blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
+            a4[ks] = dk[k * 16 + l16];
           } else {
-            const float2 tt = Lg.sigma_copy[(size_t)blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
-            sg = make_float2(tt.x, -tt.y);
+            const float2 x = dk[l16 * 16 + k];
+            a4[ks] = make_float2(x.x, -x.y);
           }
-          const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
-          a4[ks] = make_float2(sg.x - sh.x, sg.y - sh.y);
-          b4[ks] = Yt[k * PT + 16 * cb + l16];
+          b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
         }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
-      }
+      });
       float rp = 0.0f;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -2032,7 +2059,8 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   a.c.bar.release = (unsigned *)(base + o_rel);
   a.c.bar.abort_flag = (int32_t *)(base + o_abt);
   if (!a.c.status) a.c.status = (int32_t *)(base + o_st);
-  a.sigma_copy = (float2 *)(base + o_cp);
+  a.delta = (float2 *)(base + o_cp);
+
   a.c.a.xg = (float *)(base + o_xg);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.c.bar.arrive, p.G, a.c.bar.release,
                      a.c.bar.abort_flag, a.c.status);
