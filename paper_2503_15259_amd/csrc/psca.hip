@@ -680,6 +680,37 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
     }
   }
   __syncthreads();
+  // Row J of W (W_JK = -W_JJ sum_{M=K..J-1} L_JM W_MK, K < J) is computed in
+  // step J by the wavefronts that do not factor the next leaf, after their
+  // trailing updates: W_JJ is that step's leaf, L_JM is final and the rows
+  // of W above are in place.  Each such block is held in registers and
+  // written over L_JK after the step's closing barrier (L_JK is read by
+  // the row's other blocks until then, and by nothing later).
+  auto w_row_block = [&](int Jr, int K, f4 &wr, f4 &wi) {
+    f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
+    for (int M = K; M < Jr; ++M)
+      cblock_mma(WS + (16 * M) * P + 16 * Jr, WS + (16 * K) * P + 16 * M, P, l16, lq, tr, ti);
+    float2 *T = scr + wave * 256;          // column-major, pitch 16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
+    wave_lds_sync();
+    float2 a[4], b[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const float2 w = WS[(16 * Jr + 4 * ks + lq) * P + 16 * Jr + l16];   // W_JJ[l16][k]
+      a[ks] = make_float2(-w.x, -w.y);
+      b[ks] = T[l16 * 16 + 4 * ks + lq];                                   // T[k][l16]
+    }
+    wr = (f4){0.f, 0.f, 0.f, 0.f};
+    wi = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) cmfma(a[ks], b[ks], wr, wi);
+    wave_lds_sync();
+  };
+  auto w_store = [&](int Jr, int K, const f4 &wr, const f4 &wi) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) WS[(16 * K + l16) * P + 16 * Jr + 4 * lq + v] = make_float2(wr[v], wi[v]);
+  };
   for (int J = 0; J < Lb; ++J) {
     PSCA_SUB_MARK(it, J, 0);
     if (!s_pd[J]) return false;   // uniform: every workgroup factors the same Sigma
@@ -687,6 +718,8 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
     for (int I = J + 1 + wave; I < Lb; I += kWaves) chol_panel(WS, P, J, I, l16, lq);
     __syncthreads();
     PSCA_SUB_MARK(it, J, 1);
+    int wk = -1;                  // the block K < J of W's row J this wavefront holds
+    f4 wr, wi;
     if (wave == 0) {
       chol_trail(WS, P, J, J + 1, J + 1, l16, lq);
       wave_lds_sync();
@@ -699,37 +732,26 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
       for (int I = J + 2; I < Lb; ++I)
         for (int K = J + 1; K <= I; ++K)
           if (q++ % (kWaves - 1) == wave - 1) chol_trail(WS, P, J, I, K, l16, lq);
+      for (int K = 0; K < J; ++K)
+        if ((q + K) % (kWaves - 1) == wave - 1) {
+          w_row_block(J, K, wr, wi);
+          wk = K;
+        }
     }
     __syncthreads();
+    if (wk >= 0) w_store(J, wk, wr, wi);
   }
   PSCA_MARK(it, 5);
-  // C2. Off-diagonal blocks of W, right to left:
-  // W_IJ = -(sum_{K=J+1..I} W_IK L_KJ) W_JJ, written over L_IJ.
-  for (int J = Lb - 2; J >= 0; --J) {
-    f4 rr = {0.f, 0.f, 0.f, 0.f}, ri = {0.f, 0.f, 0.f, 0.f};
-    const int I = J + 1 + wave;
-    if (I < Lb) {
-      f4 tr = {0.f, 0.f, 0.f, 0.f}, ti = {0.f, 0.f, 0.f, 0.f};
-      for (int K = J + 1; K <= I; ++K)
-        cblock_mma(WS + (16 * K) * P + 16 * I, WS + (16 * J) * P + 16 * K, P, l16, lq, tr, ti);
-      float2 *T = scr + wave * 256;          // column-major, pitch 16
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[l16 * 16 + 4 * lq + v] = make_float2(tr[v], ti[v]);
-      wave_lds_sync();
-      float2 ta[4], wb[4];
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        ta[ks] = T[(4 * ks + lq) * 16 + l16];
-        wb[ks] = WS[(16 * J + l16) * P + 16 * J + 4 * ks + lq];
-      }
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) cmfma(ta[ks], wb[ks], rr, ri);
+  // The last row of W, then W is complete.
+  if (Lb > 1) {
+    int wk = -1;
+    f4 wr, wi;
+    for (int K = wave; K < Lb - 1; K += kWaves) {
+      w_row_block(Lb - 1, K, wr, wi);
+      wk = K;
     }
     __syncthreads();
-    if (I < Lb) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) WS[(16 * J + l16) * P + 16 * I + 4 * lq + v] = make_float2(-rr[v], -ri[v]);
-    }
+    if (wk >= 0) w_store(Lb - 1, wk, wr, wi);
     __syncthreads();
   }
   // C3. Sigma^-1 = W^H W (MFMA), stored full column-major in WS.
