@@ -97,14 +97,17 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ d4 mfma4d(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-// Complex 16x16x4 block product accumulated in FP64 (real 4-product split).
-// Operand layout as the FP32 form (A[i][k] in lane i + 16k, B[k][j] in lane
-// j + 16k); the result differs: C[i][j] sits in lane j + 16 (i % 4), element i / 4.
-__device__ __forceinline__ void cmfma_d(double2 a, double2 b, d4 &cr, d4 &ci) {
-  cr = mfma4d(a.x, b.x, cr);
-  cr = mfma4d(-a.y, b.y, cr);
-  ci = mfma4d(a.x, b.y, ci);
-  ci = mfma4d(a.y, b.x, ci);
+// Complex 16x16x4 block product accumulated in FP64 with three real products
+// (Gauss): t1 += ar br, t2 += ai bi, t3 += (ar + ai)(br + bi); then
+// re = t1 - t2 and im = t3 - t1 - t2.  Operand layout as the FP32 form
+// (A[i][k] in lane i + 16k, B[k][j] in lane j + 16k); the result differs:
+// C[i][j] sits in lane j + 16 (i % 4), element i / 4.  With FP32-valued
+// operands the products are exact in FP64, and the cancellation in im costs
+// about 1e-16 of |a||b|.
+__device__ __forceinline__ void cmfma_d3(double2 a, double2 b, d4 &t1, d4 &t2, d4 &t3) {
+  t1 = mfma4d(a.x, b.x, t1);
+  t2 = mfma4d(a.y, b.y, t2);
+  t3 = mfma4d(a.x + a.y, b.x + b.y, t3);
 }
 
 // Keeps the enclosing block a real (scalar) branch: the compiler may not
@@ -547,7 +550,7 @@ __device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, con
     if (b < NB) {
       int I, J;
       blk_coords(b, I, J);
-      d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+      d4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
       for (int cb = 0; cb < ncb; ++cb) {
         double2 av4[4], bv4[4];
 #pragma unroll
@@ -560,11 +563,11 @@ __device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, con
           bv4[ks] = make_double2(w * s.x, -w * s.y);
         }
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma_d(av4[ks], bv4[ks], cr, ci);
+        for (int ks = 0; ks < 4; ++ks) cmfma_d3(av4[ks], bv4[ks], t1, t2, t3);
       }
       float2 *o = dst + b * 256 + l16 * 16 + lq;   // rows lq + 4v of column l16
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)cr[v], (float)ci[v]);
+      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)(t1[v] - t2[v]), (float)(t3[v] - t1[v] - t2[v]));
     }
   }
 }
@@ -1432,7 +1435,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     for (int b = wave; b < NB; b += kWaves) {
       int I, J;
       blk_coords(b, I, J);
-      d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};   // FP64, as tile_gram
+      d4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;   // FP64, as tile_gram
       for (int cb = 0; cb < ncb; ++cb) {
         double2 av4[4], bv4[4];
 #pragma unroll
@@ -1445,11 +1448,11 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
           bv4[ks] = make_double2(w * sv.x, -w * sv.y);
         }
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma_d(av4[ks], bv4[ks], cr, ci);
+        for (int ks = 0; ks < 4; ++ks) cmfma_d3(av4[ks], bv4[ks], t1, t2, t3);
       }
       float2 *o = A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + lq;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)cr[v], (float)ci[v]);
+      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)(t1[v] - t2[v]), (float)(t3[v] - t1[v] - t2[v]));
     }
     PSCA_MARK(it, 1);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
