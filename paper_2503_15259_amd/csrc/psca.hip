@@ -345,11 +345,14 @@ struct CoopArgs {
 };
 
 // LDS footprint in bytes of k_psca<Lp, 64 * waves> for NT columns per workgroup
+// 16-column blocks of the B tile per round of C4: two where LDS allows.
+__host__ __device__ constexpr int b_tile_blocks(int Lp) { return Lp <= 80 ? 2 : 1; }
+
 __host__ __device__ inline size_t lds_bytes(int Lp, int NT, int waves) {
   const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
   const bool sh_lds = Lp <= 64;
-  const size_t f2 = (size_t)Lp * pt + (size_t)Lp * 17 + (size_t)Lp * P + (sh_lds ? (size_t)Lp * P : 0) +
-                    (size_t)waves * 256;
+  const size_t f2 = (size_t)Lp * pt + (size_t)Lp * (16 * b_tile_blocks(Lp) + 1) + (size_t)Lp * P +
+                    (sh_lds ? (size_t)Lp * P : 0) + (size_t)waves * 256;
   const size_t f4b = 3 * (size_t)NT + 2 * Lb * NT;   // floats
   return f2 * sizeof(float2) + f4b * 4;
 }
@@ -812,13 +815,14 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int Lp = LPMAX, Lb = LPMAX / kBlk, NB = Lb * (Lb + 1) / 2;   // padded pilot length
   constexpr int P = Lp + 1;                                             // pitch of the L x L LDS matrix
   constexpr bool kShLds = LPMAX <= 64;                                  // SigmaHat resident in LDS
-  constexpr int kRowBlocksPerWave = (Lb + kWaves - 1) / kWaves;
   extern __shared__ float4 smem_raw[];
   __shared__ int s_ok, s_pd[LPMAX / 16];
   const int NT = A.NT, PT = A.NT + 1;
   float2 *St = (float2 *)smem_raw;          // [Lp][PT]  S tile, row i at i * PT
-  constexpr int kPB = 17;                   // pitch of the B tile
-  float2 *Bt = St + Lp * PT;                // [Lp][kPB] B tile of one 16-column block
+  constexpr int kBW = b_tile_blocks(LPMAX); // 16-column blocks per round of C4
+  constexpr int kTPW = (Lb * kBW + kWaves - 1) / kWaves;   // C4 tasks per wavefront
+  constexpr int kPB = 16 * kBW + 1;         // pitch of the B tile
+  float2 *Bt = St + Lp * PT;                // [Lp][kPB] B tile of kBW 16-column blocks
   float2 *WS = Bt + Lp * kPB;               // [Lp][P]   column-major: Cholesky factor, W, Sigma^-1
   float2 *ShL = WS + Lp * P;                // [Lp][P]   Sigma - SigmaHat of the iteration (kShLds)
   float2 *scr = ShL + (kShLds ? Lp * P : 0);// [kWaves][256] per-wave 16x16 scratch
@@ -892,34 +896,39 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
     // relative accuracy for weak devices, whose q is small next to
     // ||Sigma^-1||.
     PSCA_MARK(it, 7);
-    for (int cb = 0; cb < A.ncb; ++cb) {
+    // Up to kBW column blocks per round, one (block row, column block) task
+    // per wavefront.
+    for (int cb0 = 0; cb0 < A.ncb; cb0 += kBW) {
+      const int nb = min(kBW, A.ncb - cb0), ntask = Lb * nb;
 #pragma unroll
-      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
-        const int I = wave + kWaves * rb;
-        if (I < Lb) {
+      for (int j = 0; j < kTPW; ++j) {   // Y = W S (lower triangular W)
+        const int t = wave + kWaves * j;
+        if (t < ntask) {
+          const int I = t / nb, c = t - I * nb;
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-          for (int K = 0; K <= I; ++K)   // W is lower triangular
-            cblock_mma_rm(WS + 16 * I, P, St + 16 * cb, PT, 16 * K, l16, lq, cr, ci);
+          for (int K = 0; K <= I; ++K)
+            cblock_mma_rm(WS + 16 * I, P, St + 16 * (cb0 + c), PT, 16 * K, l16, lq, cr, ci);
           float qp = 0.0f;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             qp += cr[v] * cr[v] + ci[v] * ci[v];
-            Bt[(16 * I + 4 * lq + v) * kPB + l16] = make_float2(cr[v], ci[v]);
+            Bt[(16 * I + 4 * lq + v) * kPB + 16 * c + l16] = make_float2(cr[v], ci[v]);
           }
           qp += __shfl_xor(qp, 16);
           qp += __shfl_xor(qp, 32);
-          if (lq == 0) red_q[I * NT + 16 * cb + l16] = qp;
+          if (lq == 0) red_q[I * NT + 16 * (cb0 + c) + l16] = qp;
         }
       }
       __syncthreads();
       {   // B = W^H Y, in registers until every wavefront has read Y
-        f4 br[kRowBlocksPerWave], bi[kRowBlocksPerWave];
+        f4 br[kTPW], bi[kTPW];
 #pragma unroll
-        for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
-          br[rb] = (f4){0.f, 0.f, 0.f, 0.f};
-          bi[rb] = (f4){0.f, 0.f, 0.f, 0.f};
-          const int I = wave + kWaves * rb;
-          if (I < Lb) {
+        for (int j = 0; j < kTPW; ++j) {
+          br[j] = (f4){0.f, 0.f, 0.f, 0.f};
+          bi[j] = (f4){0.f, 0.f, 0.f, 0.f};
+          const int t = wave + kWaves * j;
+          if (t < ntask) {
+            const int I = t / nb, c = t - I * nb;
             for (int K = I; K < Lb; ++K) {   // A[i][k] = conj(W[k][i])
               float2 a4[4], b4[4];
 #pragma unroll
@@ -927,29 +936,31 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
                 const int k = 16 * K + 4 * ks + lq;
                 const float2 wv = WS[(16 * I + l16) * P + k];
                 a4[ks] = make_float2(wv.x, -wv.y);
-                b4[ks] = Bt[k * kPB + l16];
+                b4[ks] = Bt[k * kPB + 16 * c + l16];
               }
 #pragma unroll
-              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], br[rb], bi[rb]);
+              for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], br[j], bi[j]);
             }
           }
         }
         __syncthreads();
 #pragma unroll
-        for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
-          const int I = wave + kWaves * rb;
-          if (I < Lb) {
+        for (int j = 0; j < kTPW; ++j) {
+          const int t = wave + kWaves * j;
+          if (t < ntask) {
+            const int I = t / nb, c = t - I * nb;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              Bt[(16 * I + 4 * lq + v) * kPB + l16] = make_float2(br[rb][v], bi[rb][v]);
+              Bt[(16 * I + 4 * lq + v) * kPB + 16 * c + l16] = make_float2(br[j][v], bi[j][v]);
           }
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int rb = 0; rb < kRowBlocksPerWave; ++rb) {
-        const int I = wave + kWaves * rb;
-        if (I < Lb) {
+      for (int j = 0; j < kTPW; ++j) {
+        const int t = wave + kWaves * j;
+        if (t < ntask) {
+          const int I = t / nb, c = t - I * nb;
           // D' = (Sigma - SigmaHat) B: then b^H D' = q - r with an error that
           // scales with Sigma - SigmaHat (small near a stationary point)
           // rather than with q and r themselves.  Sigma from its packed
@@ -957,7 +968,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
           if constexpr (kShLds) {   // ShL holds Sigma - SigmaHat for this iteration
 #pragma unroll
-            for (int K = 0; K < Lb; ++K) cblock_mma_rm(ShL + 16 * I, P, Bt, kPB, 16 * K, l16, lq, cr, ci);
+            for (int K = 0; K < Lb; ++K) cblock_mma_rm(ShL + 16 * I, P, Bt + 16 * c, kPB, 16 * K, l16, lq, cr, ci);
           } else {
 #pragma unroll
             for (int K = 0; K < Lb; ++K) {
@@ -969,12 +980,12 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
                 if (I >= K) {
                   sg = A.sigma[blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
                 } else {
-                  const float2 t = A.sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
-                  sg = make_float2(t.x, -t.y);
+                  const float2 t2 = A.sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
+                  sg = make_float2(t2.x, -t2.y);
                 }
                 const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
                 a4[ks] = make_float2(sg.x - sh.x, sg.y - sh.y);
-                b4[ks] = Bt[k * kPB + l16];
+                b4[ks] = Bt[k * kPB + 16 * c + l16];
               }
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
@@ -983,12 +994,12 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
           float rp = 0.0f;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float2 bv = Bt[(16 * I + 4 * lq + v) * kPB + l16];
+            const float2 bv = Bt[(16 * I + 4 * lq + v) * kPB + 16 * c + l16];
             rp += bv.x * cr[v] + bv.y * ci[v];
           }
           rp += __shfl_xor(rp, 16);
           rp += __shfl_xor(rp, 32);
-          if (lq == 0) red_r[I * NT + 16 * cb + l16] = rp;
+          if (lq == 0) red_r[I * NT + 16 * (cb0 + c) + l16] = rp;
         }
       }
       __syncthreads();
