@@ -608,7 +608,18 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
     if (tid < cnt * Pp) {
       const int e = start + tid % cnt, part = tid / cnt;
       double2 acc = make_double2(0.0, 0.0);
-      for (int h = part; h < G; h += Pp) {
+      int h = part;
+      for (; h + 3 * Pp < G; h += 4 * Pp) {   // four loads in flight, then the adds in order
+        float2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = partials[(size_t)(h + u * Pp) * pstride + e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc.x += v[u].x;
+          acc.y += v[u].y;
+        }
+      }
+      for (; h < G; h += Pp) {
         const float2 v = partials[(size_t)h * pstride + e];
         acc.x += v.x;
         acc.y += v.y;
@@ -671,18 +682,35 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
     const bool ok = leaf_chol(WS, P, lane);
     if (lane == 0) s_pd[0] = ok ? 1 : 0;
   } else if (delta) {
-    for (int e = tid - 64; e < LP * LP; e += THREADS - 64) {
-      const int k = e / LP, i = e - k * LP;   // column k, row i
-      const int I = i >> 4, K = k >> 4;
-      float2 sg;   // from the packed copy: wavefront 0 overwrites block (0, 0) of WS
-      if (I >= K) {
-        sg = sigma[blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
-      } else {
-        const float2 t = sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
-        sg = make_float2(t.x, -t.y);
+    // from the packed copy (wavefront 0 overwrites block (0, 0) of WS); four
+    // elements per thread with their loads in flight together
+    constexpr int kU = 4, nt = THREADS - 64;
+    for (int e0 = tid - 64; e0 < LP * LP; e0 += kU * nt) {
+      float2 sg[kU], sh[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        sg[u] = sh[u] = make_float2(0.f, 0.f);
+        if (e < LP * LP) {
+          const int k = e / LP, i = e - k * LP;   // column k, row i
+          const int I = i >> 4, K = k >> 4;
+          if (I >= K) {
+            sg[u] = sigma[blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
+          } else {
+            const float2 t = sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
+            sg[u] = make_float2(t.x, -t.y);
+          }
+          if (i < L && k < L) sh[u] = shat[(size_t)k * L + i];
+        }
       }
-      const float2 sh = (i < L && k < L) ? shat[(size_t)k * L + i] : make_float2(0.f, 0.f);
-      delta[k * P + i] = make_float2(sg.x - sh.x, sg.y - sh.y);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        if (e < LP * LP) {
+          const int k = e / LP, i = e - k * LP;
+          delta[k * P + i] = make_float2(sg[u].x - sh[u].x, sg[u].y - sh[u].y);
+        }
+      }
     }
   }
   __syncthreads();
