@@ -465,6 +465,72 @@ def run_net(args):
 
 
 # ---------------------------------------------------------------------------
+# Training step of the unrolled network: forward with recorded iterates,
+# BCE, hand-written per-layer backward, Adam, on one minibatch
+# ---------------------------------------------------------------------------
+def run_train(args):
+    import numpy as np
+    import torch
+    from paper_2503_15259_amd import instances as I
+    from paper_2503_15259_amd import net as NET
+    from paper_2503_15259_amd import psca as P
+
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    K, N, L, M, p = 20, 1000, 64, 128, 0.1
+    variant = P.MAP_UR
+    wid = I.WORKLOAD_IDS["net"]
+    ctx = P.Context(0)
+    B = args.batch
+
+    def load(index):
+        inst = I.make_instance(wid, index, N, L, M, p)
+        S = P.colmajor(torch.from_numpy(inst.S.astype(np.complex64)).to(dev))
+        Y = P.colmajor(torch.from_numpy(inst.Y.astype(np.complex64)).to(dev))
+        g = torch.from_numpy(inst.g.astype(np.float32)).to(dev)
+        prm = P.Params(variant=variant, iters=K, sigma2=inst.sigma2, M=inst.M, d_lo=inst.d_lo, d_hi=inst.d_hi,
+                       pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS)
+        alpha = torch.from_numpy(inst.alpha.astype(np.float32)).to(dev)
+        return P.sample_cov(Y, ctx=ctx), S, prm, alpha, g
+
+    batch = [load(i) for i in range(B)]
+    model = NET.PscaNet(K, batch[0][2], ctx=ctx)
+    opt = torch.optim.Adam(model.parameters(), lr=1e-3)
+    for _ in range(args.warmup):
+        NET.train_step(model, opt, batch)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        NET.train_step(model, opt, batch)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # forward K iterations plus the backward's recomputation and two Gram
+    # reductions, about 2.2 forwards (the survey's count)
+    flops = B * K * iteration_flops(N, L) * 3.2
+    achieved = flops / (ms / 1e3) / 1e12
+    line = {
+        "metric": "unrolled-network training instances/sec (forward + backward + Adam), 1 MI355X",
+        "value": round(B / (ms / 1e3), 3), "unit": "instances/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"MAP-UR network training step: K={K} layers, minibatch {B} instances of "
+                               f"N={N}, L={L}, M={M}, p={p}; BCE on gamma~/g; per-layer hand-written backward",
+                   "K": K, "batch": B},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
+                     "kernel": "k_psca (network forward) + k_psca_back (layer backward)",
+                     "flops_per_launch": flops, "avg_launch_ms": round(ms, 3)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
 # GPU leg
 # ---------------------------------------------------------------------------
 
@@ -476,10 +542,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain copy kernel of this many MiB (profiler calibration)")
-    ap.add_argument("--workload", choices=["single", "uneven", "net", "large"], default="single",
+    ap.add_argument("--workload", choices=["single", "uneven", "net", "large", "train"], default="single",
                     help="single: the four estimators on N=1000, L=64 (default); uneven: a batch of "
                          "independent ML-UD instances of mixed sizes in one persistent launch")
     ap.add_argument("--instances", type=int, default=4096, help="uneven workload: instances per batch")
+    ap.add_argument("--batch", type=int, default=512, help="train workload: instances per minibatch")
     ap.add_argument("--net-variant", default="MAP-UR", help="net workload: estimator of the trained network")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="skip the team-size autotuner that runs before timing")
@@ -503,6 +570,9 @@ def main():
         return
     if args.workload == "large":
         run_large(args)
+        return
+    if args.workload == "train":
+        run_train(args)
         return
 
     cpu_info, cpu_x, cpu_x64 = (None, {}, {})

@@ -96,15 +96,15 @@ class PscaNet(torch.nn.Module):
 def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch) -> float:
     """One Adam step on a minibatch of (Sigma_hat, S, params, alpha, g)."""
     opt.zero_grad()
-    total = 0.0
+    total = None
     for Sh, S, prm, alpha, g in batch:
         x = net(Sh, S, prm)
         loss = bce(x, alpha, g, net.known) / len(batch)
         loss.backward()
-        total += float(loss.detach())
+        total = loss.detach() if total is None else total + loss.detach()
     opt.step()
     net.project()
-    return total
+    return float(total) if total is not None else 0.0
 
 
 def choose_threshold(scores, truths) -> float:
