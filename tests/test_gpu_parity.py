@@ -124,7 +124,7 @@ def test_detect_single_instance_workload(P, variant):
 
 
 @pytest.mark.parametrize("N,L,M", [(1, 1, 4), (1, 8, 16), (65, 13, 9), (129, 3, 40), (200, 96, 64),
-                                   (300, 96, 256), (64, 64, 64), (1000, 33, 128)])
+                                   (300, 96, 256), (64, 64, 64), (1000, 33, 128), (250, 72, 64), (90, 80, 32)])
 def test_detect_ragged_and_edge_shapes(P, N, L, M):
     inst = I.make_instance(5, N * 1000 + L, N, L, M, 0.2).fp32_inputs()
     for variant in (O.ML_K, O.ML_UD):
@@ -212,7 +212,8 @@ def test_batch_mixed_instances_match_oracle_and_single_calls(P):
              (O.MAP_K, I.make_instance(5, 11, 300, 20, 16, 0.15).fp32_inputs(), 25),
              (O.ML_UD, I.make_instance(5, 12, 700, 96, 64, 0.1).fp32_inputs(), 20),
              (O.MAP_UR, I.workload_instance("small", 0).fp32_inputs(), 60),
-             (O.ML_UD, I.make_instance(5, 13, 17, 5, 8, 0.3).fp32_inputs(), 10)]
+             (O.ML_UD, I.make_instance(5, 13, 17, 5, 8, 0.3).fp32_inputs(), 10),
+             (O.ML_K, I.make_instance(5, 14, 400, 72, 64, 0.1).fp32_inputs(), 30)]
     probs, refs, singles = [], [], []
     for variant, inst, iters in cases:
         Sh = P.sample_cov(c64(inst.Y))
