@@ -181,6 +181,28 @@ int psca_layer_backward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32
                         const psca_params *prm, float rho, const float *x_in, const float *v, float *grad_x,
                         float *grad_rho, int32_t *status, void *stream);
 
+/* One instance of a batched layer backward: the arguments of
+ * psca_layer_backward (all DEVICE pointers; status optional). */
+typedef struct {
+  const psca_c32 *Sigma_hat;  /* L x L, column-major */
+  const psca_c32 *S;          /* L x N, column-major */
+  int32_t L, N;
+  psca_params prm;            /* variant, sigma2, M, g, p, prior; iters and rho ignored */
+  const float *x_in;          /* [N] the layer's input iterate */
+  const float *v;             /* [N] dL/dx' */
+  float *grad_x;              /* [N] dL/dx */
+  float *grad_rho;            /* one float: this instance's dL/drho */
+  int32_t *status;            /* PSCA_OK / PSCA_ENOTPD / PSCA_ESYNC, or NULL */
+} psca_back_problem;
+
+/* B layer backwards with the same step size rho in ONE persistent launch
+ * (teams of workgroups as in psca_detect_batch), equivalent to B calls of
+ * psca_layer_backward: the backward of one layer of the unrolled network
+ * over a minibatch.  `problems` is a HOST array read before the call
+ * returns.  Every instance is validated first (L <= 64; MAP-K2 has no
+ * backward: PSCA_ENOTSUP). */
+int psca_layer_backward_batch(psca_ctx *ctx, int B, const psca_back_problem *problems, float rho, void *stream);
+
 /* One instance of a batch: the arguments of psca_detect.  All pointers are
  * DEVICE pointers on the context's GPU; status is optional (NULL). */
 typedef struct {
@@ -190,6 +212,7 @@ typedef struct {
   psca_params prm;            /* variant, iters, schedule, sigma2, M, g, p, prior */
   float *x_out;               /* [N] */
   int32_t *status;            /* PSCA_OK / PSCA_ENOTPD / PSCA_ESYNC, or NULL */
+  float *x_hist;              /* optional [(prm.iters + 1) x N]: every iterate, as psca_net_forward */
 } psca_problem;
 
 /* B independent detections (Algorithm 1 from x = 0 for each), equivalent to

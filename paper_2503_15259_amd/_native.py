@@ -25,7 +25,7 @@ EXPORTED = (
     "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
     "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold", "psca_detect_batch",
     "psca_autotune_batch", "psca_plan_create", "psca_plan_launch", "psca_plan_team_size", "psca_plan_destroy",
-    "psca_net_forward", "psca_layer_backward",
+    "psca_net_forward", "psca_layer_backward", "psca_layer_backward_batch",
 )
 
 
@@ -61,6 +61,22 @@ class PscaProblem(ctypes.Structure):
         ("N", ctypes.c_int32),
         ("prm", PscaParams),
         ("x_out", ctypes.c_void_p),
+        ("status", ctypes.c_void_p),
+        ("x_hist", ctypes.c_void_p),
+    ]
+
+
+class PscaBackProblem(ctypes.Structure):
+    _fields_ = [
+        ("Sigma_hat", ctypes.c_void_p),
+        ("S", ctypes.c_void_p),
+        ("L", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("prm", PscaParams),
+        ("x_in", ctypes.c_void_p),
+        ("v", ctypes.c_void_p),
+        ("grad_x", ctypes.c_void_p),
+        ("grad_rho", ctypes.c_void_p),
         ("status", ctypes.c_void_p),
     ]
 
@@ -104,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "psca_plan_destroy": ([vp], i32),
         "psca_net_forward": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
         "psca_layer_backward": ([vp, vp, vp, i32, i32, P, f32, vp, vp, vp, vp, vp, vp], i32),
+        "psca_layer_backward_batch": ([vp, i32, ctypes.POINTER(PscaBackProblem), f32, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

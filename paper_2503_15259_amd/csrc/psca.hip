@@ -1091,6 +1091,7 @@ __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
 // Sigma^-1 is recomputed from x, not stored by the forward pass.
 struct BackArgs {
   CoopArgs c;           // instance, tile plan, x_in = the layer's input, work buffers, barrier
+  float *grad_rho;      // dL/drho (batched launches sum rho_part into it)
   float rho;
   const float *v;       // [N] dL/dx'
   float *grad_x;        // [N] dL/dx
@@ -1335,6 +1336,59 @@ __device__ __forceinline__ void psca_back_body(const BackArgs &Bk, const int g) 
 template <int LP>
 __global__ void __launch_bounds__(512) k_psca_back(BackArgs Bk) {
   psca_back_body<LP, 512>(Bk, blockIdx.x);
+}
+
+// Batched layer backward: teams of T workgroups work through their lists of
+// instances as k_psca_teams does (every member takes part in every instance
+// of its team; tiles past N are empty).
+template <int LP>
+__device__ __noinline__ void back_member(const BackArgs *__restrict__ desc, int g) {
+  psca_back_body<LP, 512>(*desc, g);
+}
+
+__global__ void __launch_bounds__(512) k_psca_back_teams(const BackArgs *__restrict__ descs,
+                                                         const int *__restrict__ lists,
+                                                         const int *__restrict__ offsets, int T) {
+  const int t = blockIdx.x / T, g = blockIdx.x - t * T;
+  const int i1 = offsets[t + 1];
+  for (int idx = offsets[t]; idx < i1; ++idx) {
+    const BackArgs *desc = descs + lists[idx];
+    if (g < desc->c.G) {
+      switch ((desc->c.L + 15) & ~15) {
+        case 16: back_member<16>(desc, g); break;
+        case 32: back_member<32>(desc, g); break;
+        case 48: back_member<48>(desc, g); break;
+        default: back_member<64>(desc, g); break;
+      }
+    }
+    __syncthreads();   // the next instance reuses the LDS
+  }
+}
+
+// Barrier words and status of every instance of a batched backward.
+__global__ void k_prepare_back_batch(const BackArgs *__restrict__ descs) {
+  const CoopArgs &A = descs[blockIdx.x].c;
+  for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
+  if (threadIdx.x == 0) {
+    *A.bar.release = 0u;
+    *A.bar.abort_flag = 0;
+    *A.status = PSCA_OK;
+  }
+}
+
+// dL/drho of every instance: the sum of its workgroups' parts (one block each).
+__global__ void k_sum_parts_batch(const BackArgs *__restrict__ descs) {
+  __shared__ float sh[256];
+  const BackArgs &d = descs[blockIdx.x];
+  float t = 0.0f;
+  for (int i = threadIdx.x; i < d.c.G; i += blockDim.x) t += d.rho_part[i];
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 128; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *d.grad_rho = sh[0];
 }
 
 // dL/drho = the sum of the per-workgroup parts (one workgroup)
@@ -2260,6 +2314,7 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
   b.c.bar.release = (unsigned *)(base + o_rel);
   b.c.bar.abort_flag = (int32_t *)(base + o_abt);
   if (!b.c.status) b.c.status = (int32_t *)(base + o_st);
+  b.grad_rho = grad_rho;
   b.rho = rho;
   b.v = v;
   b.grad_x = grad_x;
@@ -2414,6 +2469,7 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
     if (!a.status) a.status = (int32_t *)w;
     w += align_up(sizeof(unsigned));
     a.a.xg = (float *)w;                  // [2][N] iterate exchange (MAP-K2)
+    a.x_hist = q.x_hist;
     // every rank of a team owns the same slot for all of the team's instances:
     // a rank that sits out an instance may start the next one early
     a.partials = (float2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
@@ -2491,6 +2547,149 @@ int validate_batch(int B, const psca_problem *pr) {
     if (q.L > kMaxLdsL) return PSCA_ENOTSUP;   // batches keep the L x L matrix in LDS
   }
   return PSCA_OK;
+}
+
+// ---- batched layer backward ----------------------------------------------
+// Largest column tile (multiple of 16) whose backward LDS fits a workgroup.
+int max_back_tile(int Lp) {
+  for (int ncb = kMaxNcb; ncb >= 1; --ncb)
+    if (lds_back_bytes(Lp, 16 * ncb, 8) <= kMaxLds) return 16 * ncb;
+  return 0;
+}
+
+struct BackBatchPlan {
+  int B = 0, T = 0, n_teams = 0;
+  size_t lds = 0;
+  std::vector<InstPlan> ip;
+  std::vector<int> team_of, lists, offsets;
+  std::vector<size_t> ws_off;
+  size_t part_off = 0, part_stride = 0, E_max = 0, ws_bytes = 0;
+};
+
+// Workspace of one instance: Sigma, G_a, G_b, barrier words, release,
+// abort, status, the per-workgroup parts of dL/drho.
+size_t back_inst_ws(int Lp, int G) {
+  return 3 * align_up(packed_entries(Lp) * sizeof(float2)) + align_up((size_t)G * 16 * sizeof(unsigned)) +
+         3 * align_up(sizeof(unsigned)) + align_up((size_t)G * sizeof(float));
+}
+
+int make_back_plan(int B, const psca_back_problem *pr, int cap, BackBatchPlan &plan) {
+  int T0 = 1, want = 1;
+  for (int b = 0; b < B; ++b) {
+    const int nt = max_back_tile((pr[b].L + 15) & ~15);
+    if (nt == 0) return PSCA_ENOTSUP;
+    T0 = std::max(T0, (pr[b].N + nt - 1) / nt);
+    want = std::max(want, (pr[b].N + 15) / 16);
+  }
+  if (T0 > cap) return PSCA_ENOTSUP;
+  const int T = ((long long)B * T0 <= cap) ? std::max(T0, std::min(cap / B, want)) : T0;
+  plan = BackBatchPlan();
+  plan.B = B;
+  plan.T = T;
+  plan.n_teams = std::max(1, std::min(cap / T, B));
+  plan.ip.resize(B);
+  std::vector<double> cost(B);
+  for (int b = 0; b < B; ++b) {
+    InstPlan &q = plan.ip[b];
+    q.Lp = (pr[b].L + 15) & ~15;
+    const int per = (pr[b].N + T - 1) / T;
+    q.NT = std::max(16, (per + 15) & ~15);
+    if (q.NT > max_back_tile(q.Lp)) return PSCA_ENOTSUP;
+    q.ncb = q.NT / 16;
+    q.G = T;
+    q.lds = lds_back_bytes(q.Lp, q.NT, 8);
+    q.ws = back_inst_ws(q.Lp, q.G);
+    plan.lds = std::max(plan.lds, q.lds);
+    const double Lb = q.Lp / 16;
+    cost[b] = 3.0 * Lb + 0.1 * q.ncb * Lb * Lb + 8.0;
+    plan.E_max = std::max(plan.E_max, packed_entries(q.Lp));
+  }
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<double> load(plan.n_teams, 0.0);
+  std::vector<std::vector<int>> team(plan.n_teams);
+  plan.team_of.resize(B);
+  for (int b : order) {
+    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    team[t].push_back(b);
+    plan.team_of[b] = t;
+    load[t] += cost[b];
+  }
+  plan.offsets.push_back(0);
+  for (int t = 0; t < plan.n_teams; ++t) {
+    for (int b : team[t]) plan.lists.push_back(b);
+    plan.offsets.push_back((int)plan.lists.size());
+  }
+  size_t off = 0;
+  plan.ws_off.resize(B);
+  for (int b = 0; b < B; ++b) {
+    plan.ws_off[b] = off;
+    off += plan.ip[b].ws;
+  }
+  plan.part_off = off;
+  // per team: partials of Sigma / G_a, then of G_b, T ranks of E_max entries each
+  plan.part_stride = 2 * align_up((size_t)T * plan.E_max * sizeof(float2));
+  plan.ws_bytes = off + plan.part_stride * plan.n_teams;
+  return PSCA_OK;
+}
+
+size_t back_image_bytes(const BackBatchPlan &plan) {
+  return align_up(plan.B * sizeof(BackArgs)) + align_up(plan.lists.size() * sizeof(int)) +
+         align_up(plan.offsets.size() * sizeof(int));
+}
+
+void write_back_image(const BackBatchPlan &plan, const psca_back_problem *pr, float rho, char *base, char *img) {
+  BackArgs *out = (BackArgs *)img;
+  for (int b = 0; b < plan.B; ++b) {
+    const psca_back_problem &q = pr[b];
+    const InstPlan &ip = plan.ip[b];
+    BackArgs d;
+    fill_args(d.c, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, 1, rho, q.x_in, nullptr,
+              nullptr, nullptr, nullptr, q.status, ip);
+    char *w = base + plan.ws_off[b];
+    const size_t pe = align_up(packed_entries(ip.Lp) * sizeof(float2));
+    d.c.sigma = (float2 *)w;        w += pe;
+    d.gram_a = (float2 *)w;         w += pe;
+    d.gram_b = (float2 *)w;         w += pe;
+    d.c.bar.arrive = (unsigned *)w; w += align_up((size_t)ip.G * 16 * sizeof(unsigned));
+    d.c.bar.release = (unsigned *)w; w += align_up(sizeof(unsigned));
+    d.c.bar.abort_flag = (int32_t *)w; w += align_up(sizeof(unsigned));
+    if (!d.c.status) d.c.status = (int32_t *)w;
+    w += align_up(sizeof(unsigned));
+    d.rho_part = (float *)w;
+    char *pt = base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride;
+    d.c.partials = (float2 *)pt;
+    d.partials_b = (float2 *)(pt + plan.part_stride / 2);
+    d.c.pstride = plan.E_max;
+    d.grad_rho = q.grad_rho;
+    d.rho = rho;
+    d.v = q.v;
+    d.grad_x = q.grad_x;
+    out[b] = d;
+  }
+  char *p = img + align_up(plan.B * sizeof(BackArgs));
+  memcpy(p, plan.lists.data(), plan.lists.size() * sizeof(int));
+  p += align_up(plan.lists.size() * sizeof(int));
+  memcpy(p, plan.offsets.data(), plan.offsets.size() * sizeof(int));
+}
+
+int launch_back_batch(const BackBatchPlan &plan, const char *dimg, hipStream_t st) {
+  const BackArgs *descs = (const BackArgs *)dimg;
+  const int *lists = (const int *)(dimg + align_up(plan.B * sizeof(BackArgs)));
+  const int *offsets = (const int *)((const char *)lists + align_up(plan.lists.size() * sizeof(int)));
+  int T = plan.T;
+  hipLaunchKernelGGL(k_prepare_back_batch, dim3(plan.B), dim3(256), 0, st, descs);
+  int rc = launch_ok();
+  if (rc != PSCA_OK) return rc;
+  void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&T};
+  if (hipLaunchCooperativeKernel((const void *)k_psca_back_teams, dim3(plan.n_teams * plan.T), dim3(512), args,
+                                 (unsigned)plan.lds, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  hipLaunchKernelGGL(k_sum_parts_batch, dim3(plan.B), dim3(256), 0, st, descs);
+  return launch_ok();
 }
 
 }  // namespace
@@ -2822,6 +3021,41 @@ int psca_phase_trace(unsigned long long *host, int count) {
                  hipSuccess ? PSCA_OK : PSCA_EHIP;
 }
 #endif
+
+int psca_layer_backward_batch(psca_ctx *ctx, int B, const psca_back_problem *problems, float rho, void *stream) {
+  if (!ctx || B < 0 || (B > 0 && !problems)) return PSCA_EINVAL;
+  if (!(rho >= 0.0f) || rho > 1.0f) return PSCA_EINVAL;
+  for (int b = 0; b < B; ++b) {
+    const psca_back_problem &q = problems[b];
+    if (!q.Sigma_hat || !q.S || !q.x_in || !q.v || !q.grad_x || !q.grad_rho) return PSCA_EINVAL;
+    const int rc = validate_params(&q.prm, q.L, q.N, false);
+    if (rc != PSCA_OK) return rc;
+    if (q.L > 64 || q.prm.variant == PSCA_MAP_K2) return PSCA_ENOTSUP;
+  }
+  if (B == 0) return PSCA_OK;
+  DeviceGuard guard(ctx->device);
+  if (!guard.ok) return PSCA_EHIP;
+  hipStream_t st = as_stream(stream);
+  const KernelChoice kc{(const void *)k_psca_back_teams, 512, 64};
+  const int cap = max_coresident(ctx, kc, kMaxLds);
+  if (cap <= 0) return PSCA_ENOTSUP;
+  BackBatchPlan plan;
+  int rc = make_back_plan(B, problems, cap, plan);
+  if (rc != PSCA_OK) return rc;
+  if (max_coresident(ctx, kc, plan.lds) < plan.n_teams * plan.T) return PSCA_ENOTSUP;
+  if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) return rc;
+  const size_t bytes = back_image_bytes(plan);
+  char *host = nullptr;
+  if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) return rc;
+  write_back_image(plan, problems, rho, (char *)ctx->ws, host);
+  if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  if (hipEventRecord(ctx->desc_done, st) != hipSuccess) return PSCA_EHIP;
+  ctx->desc_pending = true;
+  return launch_back_batch(plan, (const char *)ctx->ddesc, st);
+}
 
 int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *stream) {
   if (!x || !support || N < 1) return PSCA_EINVAL;

@@ -58,6 +58,43 @@ class _Unrolled(torch.autograd.Function):
         return d_rho, None, None, None, None
 
 
+class _UnrolledBatch(torch.autograd.Function):
+    """x^(K) of every instance of a minibatch as functions of the shared step
+    sizes: the forward is one persistent batch launch with every iterate
+    recorded (psca_detect_batch), the backward one batched launch per layer
+    (psca_layer_backward_batch)."""
+
+    @staticmethod
+    def forward(fctx, rhos, items, pctx):
+        K = rhos.numel()
+        dev = items[0][1].device
+        rho_dev = rhos.detach().to(dev, torch.float32).contiguous()
+        probs = []
+        for Sh, S, params in items:
+            hist = torch.empty((K + 1, S.shape[1]), dtype=torch.float32, device=dev)
+            probs.append(P.Problem(Sigma_hat=Sh, S=S, params=replace(params, iters=K, rho=rho_dev), hist=hist))
+        P.detect_batch(probs, ctx=pctx)
+        fctx.hists = [pb.hist for pb in probs]
+        fctx.rhos = rho_dev.clone()
+        fctx.rho_device = rhos.device
+        fctx.items = items
+        fctx.pctx = pctx
+        return tuple(pb.hist[-1].clone() for pb in probs)
+
+    @staticmethod
+    def backward(fctx, *grad_outs):
+        host_rhos = fctx.rhos.cpu().tolist()
+        vs = [torch.zeros_like(h[-1]) if g is None else g.contiguous().float()
+              for g, h in zip(grad_outs, fctx.hists)]
+        grads = []
+        bb = P.BackBatch(fctx.items, ctx=fctx.pctx)
+        for k in range(len(host_rhos) - 1, -1, -1):
+            vs, gr = bb.run([h[k] for h in fctx.hists], vs, float(host_rhos[k]))
+            grads.append(gr.sum().reshape(1))
+        d_rho = torch.cat(grads[::-1]).to(fctx.rho_device)
+        return d_rho, None, None
+
+
 def bce(x: torch.Tensor, alpha: torch.Tensor, g: Optional[torch.Tensor], known: bool, clamp: float = 1e-7):
     """Eq. Loss_alpha (known pathloss: z = alpha~) or eq. Loss_gamma
     (z = gamma~ / g), mean over devices; z clamped to [clamp, 1 - clamp].
@@ -87,21 +124,35 @@ class PscaNet(torch.nn.Module):
         prm = params or self.params
         return _Unrolled.apply(self.rho, Sigma_hat, S, prm, self.ctx or P.default_context(S.device))
 
+    def forward_batch(self, items):
+        """x^(K) of every (Sigma_hat, S, params) of a minibatch, in batched launches."""
+        if not items:
+            return ()
+        return _UnrolledBatch.apply(self.rho, list(items), self.ctx or P.default_context(items[0][1].device))
+
     def project(self):
         """Keep every step size in [0, 1] after an optimiser step."""
         with torch.no_grad():
             self.rho.clamp_(0.0, 1.0)
 
 
-def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch) -> float:
-    """One Adam step on a minibatch of (Sigma_hat, S, params, alpha, g)."""
+def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch, batched: bool = True) -> float:
+    """One Adam step on a minibatch of (Sigma_hat, S, params, alpha, g): the
+    mean BCE over the minibatch.  batched: forward and backward of the whole
+    minibatch in batched launches (L <= 64), else instance by instance."""
     opt.zero_grad()
-    total = None
-    for Sh, S, prm, alpha, g in batch:
-        x = net(Sh, S, prm)
-        loss = bce(x, alpha, g, net.known) / len(batch)
+    if batched:
+        xs = net.forward_batch([(Sh, S, prm) for Sh, S, prm, _, _ in batch])
+        loss = sum(bce(x, alpha, g, net.known) for x, (_, _, _, alpha, g) in zip(xs, batch)) / len(batch)
         loss.backward()
-        total = loss.detach() if total is None else total + loss.detach()
+        total = loss.detach()
+    else:
+        total = None
+        for Sh, S, prm, alpha, g in batch:
+            x = net(Sh, S, prm)
+            loss = bce(x, alpha, g, net.known) / len(batch)
+            loss.backward()
+            total = loss.detach() if total is None else total + loss.detach()
     opt.step()
     net.project()
     return float(total) if total is not None else 0.0

@@ -219,6 +219,7 @@ class Problem:
     params: Params
     out: Optional[torch.Tensor] = None
     status: Optional[torch.Tensor] = None
+    hist: Optional[torch.Tensor] = None   # optional [(iters + 1), N]: every iterate
 
 
 def _problem_array(problems, ctx):
@@ -249,6 +250,11 @@ def _problem_array(problems, ctx):
         e.prm = pb.params.to_c()
         e.x_out = x.data_ptr()
         e.status = None if pb.status is None else pb.status.data_ptr()
+        if pb.hist is not None:
+            _need(pb.hist, torch.float32, ctx.device, "hist")
+            if pb.hist.numel() < (pb.params.iters + 1) * n or not pb.hist.is_contiguous():
+                raise ValueError("hist must be a contiguous float32 tensor of (iters + 1) x N")
+        e.x_hist = None if pb.hist is None else pb.hist.data_ptr()
     return arr, outs, keep
 
 
@@ -370,6 +376,66 @@ def layer_backward(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, rho
                                          ctypes.c_float(rho), _ptr(x_in), _ptr(v), _ptr(gx), _ptr(gr),
                                          _ptr(status), _stream(ctx.device, stream)), "psca_layer_backward")
     return gx, gr
+
+
+class BackBatch:
+    """A minibatch for psca_layer_backward_batch: the instances (Sigma_hat, S,
+    params) are validated and marshalled once; run() supplies each layer's
+    inputs x_in and upstream gradients v."""
+
+    def __init__(self, items, ctx: Optional[Context] = None, status=None):
+        if not items:
+            raise ValueError("empty minibatch")
+        self.ctx = ctx or default_context(items[0][1].device)
+        self.B = len(items)
+        self.arr = (N.PscaBackProblem * self.B)()
+        self.keep, self.n = [], []
+        self.gr = torch.empty(self.B, dtype=torch.float32, device=self.ctx.device)
+        for k, (Sh, S, params) in enumerate(items):
+            _need(S, torch.complex64, self.ctx.device, "S")
+            _need(Sh, torch.complex64, self.ctx.device, "Sigma_hat")
+            S = colmajor(S)
+            Sh = colmajor(Sh)
+            L, n = S.shape
+            if Sh.shape != (L, L):
+                raise ValueError("Sigma_hat must be L x L")
+            params.check_tensors(self.ctx.device, n)
+            self.keep += [S, Sh]
+            self.n.append(n)
+            e = self.arr[k]
+            e.Sigma_hat, e.S, e.L, e.N = Sh.data_ptr(), S.data_ptr(), L, n
+            e.prm = params.to_c()
+            e.grad_rho = self.gr.data_ptr() + 4 * k
+            e.status = None if status is None else status[k].data_ptr()
+
+    def run(self, x_ins, vs, rho: float, stream=None):
+        """Returns ([dL/dx per instance], dL/drho per instance as a tensor [B])."""
+        gxs, hold = [], []
+        for k, (x_in, v) in enumerate(zip(x_ins, vs)):
+            n = self.n[k]
+            _need(x_in, torch.float32, self.ctx.device, "x_in")
+            _need(v, torch.float32, self.ctx.device, "v")
+            if x_in.numel() != n or v.numel() != n or not x_in.is_contiguous() or not v.is_contiguous():
+                raise ValueError("x_in and v must be contiguous float32 vectors of length N")
+            gx = torch.empty(n, dtype=torch.float32, device=self.ctx.device)
+            gxs.append(gx)
+            hold += [x_in, v]
+            e = self.arr[k]
+            e.x_in, e.v, e.grad_x = x_in.data_ptr(), v.data_ptr(), gx.data_ptr()
+        N.check(self.ctx._lib.psca_layer_backward_batch(self.ctx.handle, self.B, self.arr, ctypes.c_float(rho),
+                                                        _stream(self.ctx.device, stream)),
+                "psca_layer_backward_batch")
+        return gxs, self.gr.clone()
+
+
+def layer_backward_batch(items, rho: float, ctx: Optional[Context] = None, stream=None, status=None):
+    """psca_layer_backward_batch: one layer's backward over a minibatch in one
+    persistent launch.  items: list of (Sigma_hat, S, params, x_in, v).
+    Returns ([dL/dx per item], dL/drho per item as a device tensor [B])."""
+    if not items:
+        return [], None
+    bb = BackBatch([(Sh, S, prm) for Sh, S, prm, _, _ in items], ctx=ctx, status=status)
+    return bb.run([it[3] for it in items], [it[4] for it in items], rho, stream=stream)
 
 
 def threshold(x: torch.Tensor, theta: float, stream=None) -> torch.Tensor:

@@ -57,11 +57,13 @@ def test_params_struct_layout_matches_header(tmp_path):
         pytest.skip("no C compiler")
     fields = [f for f, _ in N.PscaParams._fields_]
     pfields = [f for f, _ in N.PscaProblem._fields_]
+    bfields = [f for f, _ in N.PscaBackProblem._fields_]
     src = tmp_path / "layout.c"
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "psca.h"', "int main(void) {",
-             'printf("%zu %zu\\n", sizeof(psca_params), sizeof(psca_problem));']
+             'printf("%zu %zu %zu\\n", sizeof(psca_params), sizeof(psca_problem), sizeof(psca_back_problem));']
     lines += [f'printf("%zu\\n", offsetof(psca_params, {f}));' for f in fields]
     lines += [f'printf("%zu\\n", offsetof(psca_problem, {f}));' for f in pfields]
+    lines += [f'printf("%zu\\n", offsetof(psca_back_problem, {f}));' for f in bfields]
     lines += ["return 0; }"]
     src.write_text("\n".join(lines))
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
@@ -71,8 +73,13 @@ def test_params_struct_layout_matches_header(tmp_path):
     vals = [int(v) for v in out]
     assert vals[0] == ctypes.sizeof(N.PscaParams)
     assert vals[1] == ctypes.sizeof(N.PscaProblem)
-    assert vals[2:2 + len(fields)] == [getattr(N.PscaParams, f).offset for f in fields]
-    assert vals[2 + len(fields):] == [getattr(N.PscaProblem, f).offset for f in pfields]
+    assert vals[2] == ctypes.sizeof(N.PscaBackProblem)
+    o = 3
+    assert vals[o:o + len(fields)] == [getattr(N.PscaParams, f).offset for f in fields]
+    o += len(fields)
+    assert vals[o:o + len(pfields)] == [getattr(N.PscaProblem, f).offset for f in pfields]
+    o += len(pfields)
+    assert vals[o:] == [getattr(N.PscaBackProblem, f).offset for f in bfields]
 
 
 def test_missing_library_fails_loudly(tmp_path):

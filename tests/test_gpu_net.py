@@ -129,3 +129,80 @@ def test_training_lowers_the_loss(P):
     assert losses[-1] < losses[0], losses
     r = model.rho.detach().cpu().numpy()
     assert np.all(r >= 0.0) and np.all(r <= 1.0)
+
+
+def test_layer_backward_batch_matches_oracle_and_single_calls(P):
+    """psca_layer_backward_batch over instances of different N, L and variant
+    (one step size): each result meets the oracle bar of the single-instance
+    backward and agrees with the single call to the same bar."""
+    cases = [(O.ML_K, 300, 64, 128), (O.MAP_K, 100, 20, 32), (O.ML_UD, 700, 48, 64), (O.MAP_UR, 60, 16, 64),
+             (O.ML_UD, 20, 8, 64), (O.ML_K, 1000, 64, 128)]
+    rho = 0.35
+    items, refs, singles = [], [], []
+    for k, (variant, N, L, M) in enumerate(cases):
+        inst = I.make_instance(3, 800 + k, N, L, M, 0.2).fp32_inputs()
+        prob = O.problem_from_instance(inst, variant, eps=EPS)
+        _, hist = O.psca(prob, 6, record=True)
+        x = np.asarray(hist[5].x, np.float32).astype(np.float64)
+        v = np.random.default_rng(k).standard_normal(N).astype(np.float32).astype(np.float64)
+        refs.append((O.layer_vjp(prob, x, rho, v), x, v))
+        Sh = P.sample_cov(c64(inst.Y))
+        prm = params_for(P, inst, variant)
+        items.append((Sh, c64(inst.S), prm, f32(x), f32(v)))
+        singles.append(P.layer_backward(Sh, c64(inst.S), prm, rho, f32(x), f32(v)))
+    status = torch.full((len(cases),), 7, dtype=torch.int32, device=dev())
+    print("[layer backward batch of 6]", flush=True)
+    gxs, gr = P.layer_backward_batch(items, rho, status=status)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * len(cases)
+    for k, (variant, N, L, M) in enumerate(cases):
+        (dx_ref, drho_ref), x, v = refs[k]
+        gx = gxs[k].cpu().numpy().astype(np.float64)
+        scale = np.max(np.abs(dx_ref))
+        assert np.max(np.abs(gx - dx_ref)) / scale < 2e-3, (k, O.VARIANT_NAMES[variant])
+        assert np.max(np.abs(gx - singles[k][0].cpu().numpy())) / scale < 2e-3, k
+        tol = 1e-6 * np.sum(np.abs(v)) * np.max(np.abs(x))
+        assert float(gr[k].item()) == pytest.approx(drho_ref, rel=2e-3, abs=tol), k
+        assert float(gr[k].item()) == pytest.approx(float(singles[k][1].item()), rel=2e-3, abs=tol), k
+
+
+def test_layer_backward_batch_validation(P):
+    inst = I.make_instance(3, 5, 30, 80, 16, 0.2).fp32_inputs()
+    Sh = P.sample_cov(c64(inst.Y))
+    item = (Sh, c64(inst.S), params_for(P, inst, O.ML_UD), f32(np.zeros(30)), f32(np.ones(30)))
+    with pytest.raises(P.PscaError) as e:
+        P.layer_backward_batch([item], 0.5)
+    assert e.value.code == -5   # L > 64: PSCA_ENOTSUP
+    inst2 = I.make_instance(3, 6, 30, 16, 16, 0.2).fp32_inputs()
+    item2 = (P.sample_cov(c64(inst2.Y)), c64(inst2.S), params_for(P, inst2, O.ML_UD), f32(np.zeros(30)),
+             f32(np.ones(30)))
+    with pytest.raises(P.PscaError) as e:
+        P.layer_backward_batch([item2], 1.5)
+    assert e.value.code == -1   # rho outside [0, 1]
+
+
+@pytest.mark.parametrize("variant", [O.ML_K, O.ML_UD])
+def test_batched_network_gradient_matches_oracle(P, variant):
+    """Forward (one batch launch with recorded iterates) and backward (one
+    batched launch per layer) of a minibatch: the mean loss and its step-size
+    gradient against the oracle's reverse accumulation, instance by instance."""
+    from paper_2503_15259_amd import net as NET
+    K = 5
+    insts = [I.make_instance(3, 950 + 10 * variant + k, n, 16, 64, 0.2).fp32_inputs()
+             for k, n in enumerate((60, 90, 40))]
+    rhos = np.asarray(NET.schedule(K), np.float32).astype(np.float64)
+    refs = [O.net_loss_and_grad(O.problem_from_instance(inst, variant, eps=EPS), rhos, inst.alpha, inst.g)
+            for inst in insts]
+    loss_ref = np.mean([r[0] for r in refs])
+    g_ref = np.mean([r[1] for r in refs], axis=0)
+    model = NET.PscaNet(K, params_for(P, insts[0], variant))
+    batch = [(P.sample_cov(c64(inst.Y)), c64(inst.S), params_for(P, inst, variant), f32(inst.alpha), f32(inst.g))
+             for inst in insts]
+    print(f"[batched network gradient {O.VARIANT_NAMES[variant]}]", flush=True)
+    xs = model.forward_batch([(Sh, S, prm) for Sh, S, prm, _, _ in batch])
+    loss = sum(NET.bce(x, a, g, model.known) for x, (_, _, _, a, g) in zip(xs, batch)) / len(batch)
+    loss.backward()
+    torch.cuda.synchronize()
+    assert loss.item() == pytest.approx(loss_ref, rel=1e-3)
+    got = model.rho.grad.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, g_ref, rtol=5e-3, atol=5e-3 * np.max(np.abs(g_ref)))
