@@ -523,7 +523,7 @@ def run_train(args):
                    "K": K, "batch": B},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
-                     "kernel": "k_psca (network forward) + k_psca_back (layer backward)",
+                     "kernel": "k_psca_teams (network forward) + k_psca_back_teams (layer backward)",
                      "flops_per_launch": flops, "avg_launch_ms": round(ms, 3)},
         "cpu_baseline": None,
     }
