@@ -1410,9 +1410,9 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
 // device memory (packed lower 16x16 blocks) and the factorisation is spread
 // over the instance's workgroups.  Block step J: every workgroup factors the
 // diagonal block J redundantly in registers and keeps W_JJ = L_JJ^-1 in LDS;
-// the panel blocks L_IJ = A_IJ W_JJ^H and then the trailing updates
-// A_IK -= L_IJ L_KJ^H are spread over all wavefronts of the instance, with a
-// device-wide barrier after each.  Each workgroup then solves its own tile,
+// the trailing updates A_IK -= L_IJ L_KJ^H are spread over all wavefronts
+// of the instance, each forming the panel blocks L_IJ = A_IJ W_JJ^H it
+// needs, with one device-wide barrier per block step.  Each workgroup then solves its own tile,
 // Y = L^-1 S_t (q = |y|^2) and B = L^-H Y, one block row per round with the
 // row's block products split over its wavefronts, and forms
 // q - r = b^H (Sigma - SigmaHat) b, the difference taken in phase B from the
@@ -1420,8 +1420,9 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
 constexpr int kLargeMaxLp = 256;
 
 struct LargeArgs {
-  CoopArgs c;             // sigma: packed Sigma, factored in place into L
+  CoopArgs c;             // sigma: packed Sigma, updated in place by the trailing steps
   float2 *delta;          // packed Sigma - SigmaHat of the iteration
+  float2 *lbuf;           // packed off-diagonal blocks of the factor L
 };
 
 // Touches n float2 at p (16-byte loads spread over `nthreads` threads from
@@ -1614,31 +1615,45 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
         break;
       }
       if (J + 1 == Lb) break;
-      for (int I = J + 1 + gwave; I < Lb; I += nwaves) {   // panel L_IJ = A_IJ W_JJ^H, in place
-        float2 *blk = sig + (size_t)blk_index(I, J) * 256;
-        f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-        float2 a4[4], b4[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int k = 4 * ks + lq;
-          a4[ks] = blk[k * 16 + l16];
-          const float2 w = Wj[k * 16 + l16];
-          b4[ks] = make_float2(w.x, -w.y);
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) blk[l16 * 16 + 4 * lq + v] = make_float2(cr[v], ci[v]);
-      }
-      if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
-      {   // trailing A_IK -= L_IJ L_KJ^H, J < K <= I
+      {   // trailing A_IK -= L_IJ L_KJ^H (J < K <= I).  Each task forms the panel
+          // blocks it needs itself, L^T = conj(W_JJ) A^T, which leaves L[j][4q + v]
+          // in lane (j, q): the layout of an MFMA operand over the permuted index
+          // k = 4q + chunk.  So one barrier per block step; the task (I, J + 1)
+          // stores L_IJ for the solves.
         const int m = Lb - 1 - J;
+        auto panel_t = [&](int I, f4 &dr, f4 &di) {
+          const float2 *blk = pblk(sig, I, J);
+          dr = (f4){0.f, 0.f, 0.f, 0.f};
+          di = (f4){0.f, 0.f, 0.f, 0.f};
+          float2 a4[4], b4[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lq;
+            const float2 w = Wj[k * 16 + l16];   // W_JJ[l16][k]
+            a4[ks] = make_float2(w.x, -w.y);
+            b4[ks] = blk[k * 16 + l16];           // A_IJ[l16][k] = A^T[k][l16]
+          }
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], dr, di);
+        };
         for (int t = gwave; t < m * (m + 1) / 2; t += nwaves) {
           int ii = 0;
           while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
           const int I = J + 1 + ii, K = J + 1 + (t - ii * (ii + 1) / 2);
+          f4 lir, lii, lkr, lki;
+          panel_t(I, lir, lii);
+          if (K == I) {
+            lkr = lir;
+            lki = lii;
+          } else {
+            panel_t(K, lkr, lki);
+          }
+          if (K == J + 1) {
+            float2 *lb = Lg.lbuf + (size_t)blk_index(I, J) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lb[(4 * lq + v) * 16 + l16] = make_float2(lir[v], lii[v]);
+          }
           float2 *dst = sig + (size_t)blk_index(I, K) * 256;
-          const float2 *lij = pblk(sig, I, J), *lkj = pblk(sig, K, J);
           f4 cr, ci;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -1649,11 +1664,8 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
           float2 a4[4], b4[4];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lq;
-            const float2 l = lij[k * 16 + l16];
-            a4[ks] = make_float2(-l.x, -l.y);
-            const float2 r = lkj[k * 16 + l16];
-            b4[ks] = make_float2(r.x, -r.y);
+            a4[ks] = make_float2(-lir[ks], -lii[ks]);   // L_IJ[l16][4 lq + ks]
+            b4[ks] = make_float2(lkr[ks], -lki[ks]);    // conj(L_KJ[l16][4 lq + ks])
           }
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
@@ -1671,7 +1683,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     // each fetching four blocks at a time); one wavefront per column block adds
     // the partial sums and applies the diagonal W_RR (or W_RR^H).
     PSCA_MARK(it, 5);   // Yt still holds the S tile of phase A
-    warm_l2(sig, E, tid, THREADS);   // the factor L, read block by block below
+    warm_l2(Lg.lbuf, E, tid, THREADS);   // the factor L, read block by block below
     {
       const int ng = kWaves / ncb;            // wavefronts per column block
       const int cbw = wave % ncb, gi = wave / ncb;
@@ -1682,7 +1694,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
             f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
             if (pass == 0) {   // sum_{K<R} L_RK Y_K
               block_sum(gi, R, ng, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-                const float2 *lrk = pblk(sig, R, K);
+                const float2 *lrk = pblk(Lg.lbuf, R, K);
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                   const int k = 4 * ks + lq;
@@ -1692,7 +1704,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
               });
             } else {           // sum_{K>R} L_KR^H B_K
               block_sum(R + 1 + gi, Lb, ng, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-                const float2 *lkr = pblk(sig, K, R);
+                const float2 *lkr = pblk(Lg.lbuf, K, R);
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                   const int k = 4 * ks + lq;
@@ -2158,7 +2170,8 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   const size_t o_pa = 0;
   const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
   const size_t o_cp = align_up(o_sig + E * sizeof(float2));
-  const size_t o_arr = align_up(o_cp + E * sizeof(float2));
+  const size_t o_lb = align_up(o_cp + E * sizeof(float2));
+  const size_t o_arr = align_up(o_lb + E * sizeof(float2));
   const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
   const size_t o_abt = align_up(o_rel + sizeof(unsigned));
   const size_t o_st = align_up(o_abt + sizeof(unsigned));
@@ -2178,6 +2191,7 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   a.c.bar.abort_flag = (int32_t *)(base + o_abt);
   if (!a.c.status) a.c.status = (int32_t *)(base + o_st);
   a.delta = (float2 *)(base + o_cp);
+  a.lbuf = (float2 *)(base + o_lb);
 
   a.c.a.xg = (float *)(base + o_xg);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.c.bar.arrive, p.G, a.c.bar.release,
