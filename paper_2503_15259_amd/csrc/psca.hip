@@ -1771,21 +1771,20 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       }
     }
     PSCA_MARK(it, 8);
-    // q - r = b^H (Sigma - SigmaHat) b, Sigma - SigmaHat from phase B
+    // q - r = b^H (Sigma - SigmaHat) b, Sigma - SigmaHat from phase B.  The
+    // difference is Hermitian, so b^H D b = sum_I b_I^H D_II b_I
+    // + 2 Re sum_{K<I} b_I^H D_IK b_K: lower blocks only.
     for (int t = wave; t < Lb * ncb; t += kWaves) {
-      const int I = t / ncb, cb = t - I * ncb;
+      const int I = Lb - 1 - t / ncb, cb = t % ncb;   // longest rows first
       f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-      block_sum(0, Lb, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-        const float2 *dk = I >= K ? pblk(Lg.delta, I, K) : pblk(Lg.delta, K, I);
+      block_sum(0, I + 1, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+        const float2 *dk = pblk(Lg.delta, I, K);
+        const float f = K < I ? 2.0f : 1.0f;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
           const int k = 4 * ks + lq;
-          if (I >= K) {
-            a4[ks] = dk[k * 16 + l16];
-          } else {
-            const float2 x = dk[l16 * 16 + k];
-            a4[ks] = make_float2(x.x, -x.y);
-          }
+          const float2 x = dk[k * 16 + l16];
+          a4[ks] = make_float2(f * x.x, f * x.y);
           b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
         }
       });
