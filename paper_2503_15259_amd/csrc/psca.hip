@@ -1678,98 +1678,83 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     if (failed || aborted) break;
 
     // ---- C4. local solves Y = L^-1 S_t (q = |y|^2), then B = L^-H Y, in place
-    // of the S tile, one block row per round.  In round R the block products
-    // of the row's sum are split over the wavefronts (ng per column block,
-    // each fetching four blocks at a time); one wavefront per column block adds
-    // the partial sums and applies the diagonal W_RR (or W_RR^H).
+    // of the S tile.  The column blocks of the tile are independent, so each
+    // is solved by one wavefront from top to bottom and back with no
+    // workgroup barrier; a block row's products fetch four blocks at a time,
+    // then the diagonal W_RR (or W_RR^H) applies through a 16x16 stage.
     PSCA_MARK(it, 5);   // Yt still holds the S tile of phase A
     warm_l2(Lg.lbuf, E, tid, THREADS);   // the factor L, read block by block below
-    {
-      const int ng = kWaves / ncb;            // wavefronts per column block
-      const int cbw = wave % ncb, gi = wave / ncb;
+    for (int cb = wave; cb < ncb; cb += kWaves) {
+      float2 *T = scr + wave * 256;   // row-major stage
       for (int pass = 0; pass < 2; ++pass) {
         for (int r = 0; r < Lb; ++r) {
           const int R = pass == 0 ? r : Lb - 1 - r;
-          if (gi < ng) {
-            f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-            if (pass == 0) {   // sum_{K<R} L_RK Y_K
-              block_sum(gi, R, ng, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-                const float2 *lrk = pblk(Lg.lbuf, R, K);
+          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+          if (pass == 0) {   // sum_{K<R} L_RK Y_K
+            block_sum(0, R, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+              const float2 *lrk = pblk(Lg.lbuf, R, K);
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                  const int k = 4 * ks + lq;
-                  a4[ks] = lrk[k * 16 + l16];
-                  b4[ks] = Yt[(16 * K + k) * PT + 16 * cbw + l16];
-                }
-              });
-            } else {           // sum_{K>R} L_KR^H B_K
-              block_sum(R + 1 + gi, Lb, ng, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-                const float2 *lkr = pblk(Lg.lbuf, K, R);
+              for (int ks = 0; ks < 4; ++ks) {
+                const int k = 4 * ks + lq;
+                a4[ks] = lrk[k * 16 + l16];
+                b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
+              }
+            });
+          } else {           // sum_{K>R} L_KR^H B_K
+            block_sum(R + 1, Lb, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+              const float2 *lkr = pblk(Lg.lbuf, K, R);
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                  const int k = 4 * ks + lq;
-                  const float2 x = lkr[l16 * 16 + k];   // L_KR[k][l16]; A = conj of it
-                  a4[ks] = make_float2(x.x, -x.y);
-                  b4[ks] = Yt[(16 * K + k) * PT + 16 * cbw + l16];
-                }
-              });
-            }
-            float2 *T = scr + wave * 256;   // row-major partial sums
-#pragma unroll
-            for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = make_float2(cr[v], ci[v]);
+              for (int ks = 0; ks < 4; ++ks) {
+                const int k = 4 * ks + lq;
+                const float2 x = lkr[l16 * 16 + k];   // L_KR[k][l16]; A = conj of it
+                a4[ks] = make_float2(x.x, -x.y);
+                b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
+              }
+            });
           }
-          __syncthreads();
-          if (wave < ncb) {   // T = rhs_R - sum of the partials, then the diagonal block
-            float2 tv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {   // T = rhs_R - sum
+            const float2 y = Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16];
+            T[(4 * lq + v) * 16 + l16] = make_float2(y.x - cr[v], y.y - ci[v]);
+          }
+          wave_lds_sync();
+          f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+          float2 a4[4], b4[4];
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lq;
+            if (pass == 0) {
+              a4[ks] = Wd[R * 256 + k * 16 + l16];            // W_RR[l16][k]
+            } else {
+              const float2 w = Wd[R * 256 + l16 * 16 + k];    // W_RR[k][l16]; A = conj of it
+              a4[ks] = make_float2(w.x, -w.y);
+            }
+            b4[ks] = T[k * 16 + l16];
+          }
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(yr[v], yi[v]);
+          wave_lds_sync();
+        }
+        if (pass == 0) {   // q of this column block, per row block
+          for (int I = 0; I < Lb; ++I) {
+            float qv = 0.0f;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              float2 acc = Yt[(16 * R + 4 * lq + v) * PT + 16 * wave + l16];
-              for (int h = 0; h < ng; ++h) {
-                const float2 x = scr[(wave + h * ncb) * 256 + (4 * lq + v) * 16 + l16];
-                acc.x -= x.x;
-                acc.y -= x.y;
-              }
-              tv[v] = acc;
+              const float2 y = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
+              qv += y.x * y.x + y.y * y.y;
             }
-            wave_lds_sync();
-            float2 *T = scr + wave * 256;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) T[(4 * lq + v) * 16 + l16] = tv[v];
-            wave_lds_sync();
-            f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
-            float2 a4[4], b4[4];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-              const int k = 4 * ks + lq;
-              if (pass == 0) {
-                a4[ks] = Wd[R * 256 + k * 16 + l16];            // W_RR[l16][k]
-              } else {
-                const float2 w = Wd[R * 256 + l16 * 16 + k];    // W_RR[k][l16]; A = conj of it
-                a4[ks] = make_float2(w.x, -w.y);
-              }
-              b4[ks] = T[k * 16 + l16];
-            }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Yt[(16 * R + 4 * lq + v) * PT + 16 * wave + l16] = make_float2(yr[v], yi[v]);
+            qv += __shfl_xor(qv, 16);
+            qv += __shfl_xor(qv, 32);
+            if (lq == 0) red_q[I * NT + 16 * cb + l16] = qv;
           }
-          __syncthreads();
-        }
-        if (pass == 0) {   // q per row block and column
-          for (int e = tid; e < Lb * NT; e += THREADS) {
-            const int I = e / NT, c = e - I * NT;
-            float acc = 0.0f;
-            for (int i = 16 * I; i < 16 * I + 16; ++i) {
-              const float2 y = Yt[i * PT + c];
-              acc += y.x * y.x + y.y * y.y;
-            }
-            red_q[I * NT + c] = acc;
-          }
-          __syncthreads();
         }
       }
     }
+    __syncthreads();
+    PSCA_MARK(it, 6);   // both solves: the wavefronts do not meet between them
+    PSCA_MARK(it, 7);
     PSCA_MARK(it, 8);
     // q - r = b^H (Sigma - SigmaHat) b, Sigma - SigmaHat from phase B.  The
     // difference is Hermitian, so b^H D b = sum_I b_I^H D_II b_I
