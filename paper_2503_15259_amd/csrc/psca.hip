@@ -1438,6 +1438,33 @@ __device__ __forceinline__ void warm_l2(const float2 *p, int n, int t, int nthre
   asm volatile("" ::"v"(x));
 }
 
+// FP32 complex 16x16x4 product with three real MFMAs (Gauss): t1 += ar br,
+// t2 += ai bi, t3 += (ar + ai)(br + bi); re = t1 - t2, im = t3 - t1 - t2.
+__device__ __forceinline__ void cmfma3(float2 a, float2 b, f4 &t1, f4 &t2, f4 &t3) {
+  t1 = mfma4(a.x, b.x, t1);
+  t2 = mfma4(a.y, b.y, t2);
+  t3 = mfma4(a.x + a.y, b.x + b.y, t3);
+}
+
+// Gauss accumulators (t1, t2, t3) += the 16x16 block products get(q) returns
+// for q in [q0, q1), four blocks at a time so that their loads are in flight
+// together.
+template <class Get>
+__device__ __forceinline__ void block_sum_gauss(int q0, int q1, f4 &t1, f4 &t2, f4 &t3, Get get) {
+  for (int q = q0; q < q1; q += 4) {
+    float2 a4[4][4], b4[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u < q1) get(q + u, a4[u], b4[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q + u < q1) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma3(a4[u][ks], b4[u][ks], t1, t2, t3);
+      }
+  }
+}
+
 // acc += A B over a run of 16x16 blocks, operands fetched four blocks at a
 // time so that their loads are in flight together.  get(q, a4, b4) fills
 // the operands of term q.
@@ -1689,9 +1716,9 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       for (int pass = 0; pass < 2; ++pass) {
         for (int r = 0; r < Lb; ++r) {
           const int R = pass == 0 ? r : Lb - 1 - r;
-          f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+          f4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
           if (pass == 0) {   // sum_{K<R} L_RK Y_K
-            block_sum(0, R, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+            block_sum_gauss(0, R, t1, t2, t3, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
               const float2 *lrk = pblk(Lg.lbuf, R, K);
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) {
@@ -1701,7 +1728,7 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
               }
             });
           } else {           // sum_{K>R} L_KR^H B_K
-            block_sum(R + 1, Lb, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
+            block_sum_gauss(R + 1, Lb, t1, t2, t3, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
               const float2 *lkr = pblk(Lg.lbuf, K, R);
 #pragma unroll
               for (int ks = 0; ks < 4; ++ks) {
@@ -1715,10 +1742,12 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {   // T = rhs_R - sum
             const float2 y = Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16];
-            T[(4 * lq + v) * 16 + l16] = make_float2(y.x - cr[v], y.y - ci[v]);
+            T[(4 * lq + v) * 16 + l16] = make_float2(y.x - (t1[v] - t2[v]), y.y - (t3[v] - t1[v] - t2[v]));
           }
           wave_lds_sync();
-          f4 yr = {0.f, 0.f, 0.f, 0.f}, yi = {0.f, 0.f, 0.f, 0.f};
+          t1 = f4{0.f, 0.f, 0.f, 0.f};
+          t2 = t1;
+          t3 = t1;
           float2 a4[4], b4[4];
 #pragma unroll
           for (int ks = 0; ks < 4; ++ks) {
@@ -1732,9 +1761,10 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
             b4[ks] = T[k * 16 + l16];
           }
 #pragma unroll
-          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], yr, yi);
+          for (int ks = 0; ks < 4; ++ks) cmfma3(a4[ks], b4[ks], t1, t2, t3);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(yr[v], yi[v]);
+          for (int v = 0; v < 4; ++v)
+            Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(t1[v] - t2[v], t3[v] - t1[v] - t2[v]);
           wave_lds_sync();
         }
         if (pass == 0) {   // q of this column block, per row block
