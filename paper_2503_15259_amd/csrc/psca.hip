@@ -1338,6 +1338,18 @@ __global__ void __launch_bounds__(512) k_psca_back(BackArgs Bk) {
   psca_back_body<LP, 512>(Bk, blockIdx.x);
 }
 
+// Logical workgroup index under which consecutive indices share an XCD.
+// Workgroup b of a launch goes to XCD b mod 8, so the first 8 floor(n/8)
+// workgroups are renumbered XCD-major and the rest keep their index: a team
+// of consecutive logical indices then spans as few XCDs (and L2 caches) as
+// its size allows, and its barrier's cache write-backs and invalidations
+// meet fewer other teams' data.
+__device__ __forceinline__ int xcd_major(int b, int n) {
+  constexpr int kXcds = 8;
+  const int q = n / kXcds;
+  return b >= q * kXcds ? b : (b % kXcds) * q + b / kXcds;
+}
+
 // Batched layer backward: teams of T workgroups work through their lists of
 // instances as k_psca_teams does (every member takes part in every instance
 // of its team; tiles past N are empty).
@@ -1349,7 +1361,8 @@ __device__ __noinline__ void back_member(const BackArgs *__restrict__ desc, int 
 __global__ void __launch_bounds__(512) k_psca_back_teams(const BackArgs *__restrict__ descs,
                                                          const int *__restrict__ lists,
                                                          const int *__restrict__ offsets, int T) {
-  const int t = blockIdx.x / T, g = blockIdx.x - t * T;
+  const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);
+  const int t = b / T, g = b - t * T;
   const int i1 = offsets[t + 1];
   for (int idx = offsets[t]; idx < i1; ++idx) {
     const BackArgs *desc = descs + lists[idx];
@@ -1879,7 +1892,8 @@ __device__ __noinline__ void team_member(const CoopArgs *__restrict__ desc, int 
 __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__restrict__ descs,
                                                               const int *__restrict__ lists,
                                                               const int *__restrict__ offsets, int T) {
-  const int t = blockIdx.x / T, g = blockIdx.x - t * T;
+  const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);
+  const int t = b / T, g = b - t * T;
   const int i1 = offsets[t + 1];
   for (int idx = offsets[t]; idx < i1; ++idx) {
     const CoopArgs *desc = descs + lists[idx];
