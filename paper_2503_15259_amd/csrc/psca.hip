@@ -1911,26 +1911,55 @@ __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__
   }
 }
 
-// SigmaHat = Y Y^H / M; one thread per lower-triangle entry, mirrored so the
+// SigmaHat = Y Y^H / M.  Each workgroup stages Y through 64 KiB of LDS,
+// cov_chunk(L, M) columns at a time (all of Y when it fits) with coalesced
+// loads; one thread forms one lower-triangle entry and mirrors it, so the
 // result is exactly Hermitian.
+__host__ __device__ inline int cov_chunk(int L, int M) { return min(M, 8192 / L); }
+inline size_t cov_lds_bytes(int L, int M) { return (size_t)cov_chunk(L, M) * L * sizeof(float2); }
+
 __global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restrict__ Y, int L, int M,
                                                          float2 *__restrict__ Sh) {
+  extern __shared__ float4 smem_raw[];
+  float2 *ys = (float2 *)smem_raw;   // [cov_chunk(L, M)][L]: columns m0.. of Y
+  const int chunk = cov_chunk(L, M);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= L * (L + 1) / 2) return;
-  int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-  while (i * (i + 1) / 2 > e) --i;
-  while ((i + 1) * (i + 2) / 2 <= e) ++i;
-  const int j = e - i * (i + 1) / 2;
-  // Accumulated in double and rounded once: Sigma - SigmaHat is formed from
-  // this matrix every iteration, so its FP32 entries should carry no more
-  // than their own rounding.
-  double ax = 0.0, ay = 0.0;
-  for (int m = 0; m < M; ++m) {
-    const float2 a = Y[i + (size_t)m * L], b = Y[j + (size_t)m * L];
-    ax += (double)a.x * b.x + (double)a.y * b.y;
-    ay += (double)a.y * b.x - (double)a.x * b.y;
+  const bool active = e < L * (L + 1) / 2;
+  int i = 0, j = 0;
+  if (active) {
+    i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while (i * (i + 1) / 2 > e) --i;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    j = e - i * (i + 1) / 2;
   }
-  float2 acc = make_float2((float)(ax / M), (float)(ay / M));
+  // Accumulated in double (two interleaved sums) and rounded once: Sigma -
+  // SigmaHat is formed from this matrix every iteration, so its FP32 entries
+  // should carry no more than their own rounding.
+  double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
+  for (int m0 = 0; m0 < M; m0 += chunk) {
+    const int mc = min(chunk, M - m0);
+    __syncthreads();   // the previous chunk has been read
+    for (int t = threadIdx.x; t < mc * L; t += blockDim.x) ys[t] = Y[(size_t)m0 * L + t];
+    __syncthreads();
+    if (active) {
+      int m = 0;
+      for (; m + 1 < mc; m += 2) {
+        const float2 a0 = ys[m * L + i], b0 = ys[m * L + j];
+        const float2 a1 = ys[(m + 1) * L + i], b1 = ys[(m + 1) * L + j];
+        ax0 += (double)a0.x * b0.x + (double)a0.y * b0.y;
+        ay0 += (double)a0.y * b0.x - (double)a0.x * b0.y;
+        ax1 += (double)a1.x * b1.x + (double)a1.y * b1.y;
+        ay1 += (double)a1.y * b1.x - (double)a1.x * b1.y;
+      }
+      if (m < mc) {
+        const float2 a0 = ys[m * L + i], b0 = ys[m * L + j];
+        ax0 += (double)a0.x * b0.x + (double)a0.y * b0.y;
+        ay0 += (double)a0.y * b0.x - (double)a0.x * b0.y;
+      }
+    }
+  }
+  if (!active) return;
+  float2 acc = make_float2((float)((ax0 + ax1) / M), (float)((ay0 + ay1) / M));
   if (i == j) acc.y = 0.0f;
   Sh[i + (size_t)j * L] = acc;
   Sh[j + (size_t)i * L] = make_float2(acc.x, -acc.y);
@@ -2815,8 +2844,8 @@ int psca_sample_cov(psca_ctx *ctx, const psca_c32 *Y, int L, int M, psca_c32 *Si
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
   const int T = L * (L + 1) / 2;
-  hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), 0, as_stream(stream),
-                     (const float2 *)Y, L, M, (float2 *)Sigma_hat);
+  hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), cov_lds_bytes(L, M),
+                     as_stream(stream), (const float2 *)Y, L, M, (float2 *)Sigma_hat);
   return launch_ok();
 }
 
@@ -2843,8 +2872,8 @@ int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, in
   if (rc != PSCA_OK) return rc;
   float2 *Sh = (float2 *)ctx->sh;
   const int T = L * (L + 1) / 2;
-  hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), 0, as_stream(stream),
-                     (const float2 *)Y, L, prm->M, Sh);
+  hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), cov_lds_bytes(L, prm->M),
+                     as_stream(stream), (const float2 *)Y, L, prm->M, Sh);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
   return run_detect(ctx, Sh, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr, x_out, nullptr, nullptr,
                     nullptr, status, as_stream(stream));

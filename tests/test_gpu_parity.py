@@ -59,7 +59,8 @@ def label(inst, variant, iters):
 
 
 def test_sample_covariance(P):
-    for (N, L, M) in [(10, 1, 1), (30, 13, 7), (100, 64, 128), (50, 96, 256)]:
+    # M = 33 and 65: a ragged last chunk of Y's columns; L = 256 the largest pilot length
+    for (N, L, M) in [(10, 1, 1), (30, 13, 7), (100, 64, 128), (50, 96, 256), (20, 200, 33), (40, 256, 65)]:
         inst = I.make_instance(7, L, N, L, M, 0.2).fp32_inputs()
         print(f"sample_cov L={L} M={M}", flush=True)
         got = P.sample_cov(c64(inst.Y))
