@@ -17,6 +17,7 @@ import math
 from dataclasses import replace
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import psca as P
@@ -59,10 +60,10 @@ class _Unrolled(torch.autograd.Function):
 
 
 class _UnrolledBatch(torch.autograd.Function):
-    """x^(K) of every instance of a minibatch as functions of the shared step
-    sizes: the forward is one persistent batch launch with every iterate
-    recorded (psca_detect_batch), the backward one batched launch per layer
-    (psca_layer_backward_batch)."""
+    """x^(K) of every instance of a minibatch, concatenated, as a function of
+    the shared step sizes: the forward is one persistent batch launch with
+    every iterate recorded (psca_detect_batch), the backward one batched
+    launch per layer (psca_layer_backward_batch)."""
 
     @staticmethod
     def forward(fctx, rhos, items, pctx):
@@ -75,17 +76,19 @@ class _UnrolledBatch(torch.autograd.Function):
             probs.append(P.Problem(Sigma_hat=Sh, S=S, params=replace(params, iters=K, rho=rho_dev), hist=hist))
         P.detect_batch(probs, ctx=pctx)
         fctx.hists = [pb.hist for pb in probs]
-        fctx.rhos = rho_dev.clone()
+        fctx.sizes = [pb.hist.shape[1] for pb in probs]
+        fctx.host_rhos = rhos.detach().float().cpu().tolist()   # the FP32 values the kernels use
         fctx.rho_device = rhos.device
         fctx.items = items
         fctx.pctx = pctx
-        return tuple(pb.hist[-1].clone() for pb in probs)
+        return torch.cat([pb.hist[-1] for pb in probs])
 
     @staticmethod
-    def backward(fctx, *grad_outs):
-        host_rhos = fctx.rhos.cpu().tolist()
-        vs = [torch.zeros_like(h[-1]) if g is None else g.contiguous().float()
-              for g, h in zip(grad_outs, fctx.hists)]
+    def backward(fctx, grad):
+        host_rhos = fctx.host_rhos   # taken in the forward: no device round trip here
+        if grad is None:
+            grad = torch.zeros(sum(fctx.sizes), dtype=torch.float32, device=fctx.hists[0].device)
+        vs = list(grad.contiguous().float().split(fctx.sizes))   # contiguous pieces
         grads = []
         bb = P.BackBatch(fctx.items, ctx=fctx.pctx)
         for k in range(len(host_rhos) - 1, -1, -1):
@@ -95,15 +98,34 @@ class _UnrolledBatch(torch.autograd.Function):
         return d_rho, None, None
 
 
-def bce(x: torch.Tensor, alpha: torch.Tensor, g: Optional[torch.Tensor], known: bool, clamp: float = 1e-7):
-    """Eq. Loss_alpha (known pathloss: z = alpha~) or eq. Loss_gamma
-    (z = gamma~ / g), mean over devices; z clamped to [clamp, 1 - clamp].
+def bce_terms(x: torch.Tensor, alpha: torch.Tensor, g: Optional[torch.Tensor], known: bool,
+              clamp: float = 1e-7) -> torch.Tensor:
+    """Per-device terms of eq. Loss_alpha (known pathloss: z = alpha~) or
+    eq. Loss_gamma (z = gamma~ / g); z clamped to [clamp, 1 - clamp].
     Evaluated in float64: in float32, 1 - 1e-7 rounds to 1 - 1.19e-7."""
     x = x.double()
     z = x if known else x / g.double()
     z = z.clamp(clamp, 1.0 - clamp)
     a = alpha.double()
-    return -(a * torch.log(z) + (1.0 - a) * torch.log(1.0 - z)).mean()
+    return -(a * torch.log(z) + (1.0 - a) * torch.log(1.0 - z))
+
+
+def bce(x: torch.Tensor, alpha: torch.Tensor, g: Optional[torch.Tensor], known: bool, clamp: float = 1e-7):
+    """The loss of one instance: the mean of its per-device terms."""
+    return bce_terms(x, alpha, g, known, clamp).mean()
+
+
+def batch_loss(net: "PscaNet", batch) -> torch.Tensor:
+    """Mean over a minibatch of (Sigma_hat, S, params, alpha, g) of each
+    instance's loss, from one concatenated forward: the device terms of
+    instance b are weighted 1 / (B N_b), so instances of different N count
+    equally, as in the mean of per-instance losses."""
+    x = net.forward_batch_cat([(Sh, S, prm) for Sh, S, prm, _, _ in batch])
+    alpha = torch.cat([a for _, _, _, a, _ in batch])
+    g = None if net.known else torch.cat([gg for _, _, _, _, gg in batch])
+    sizes = np.array([S.shape[1] for _, S, _, _, _ in batch])
+    w = np.repeat(1.0 / (len(batch) * sizes), sizes)
+    return (bce_terms(x, alpha, g, net.known) * torch.from_numpy(w).to(x.device)).sum()
 
 
 class PscaNet(torch.nn.Module):
@@ -124,11 +146,17 @@ class PscaNet(torch.nn.Module):
         prm = params or self.params
         return _Unrolled.apply(self.rho, Sigma_hat, S, prm, self.ctx or P.default_context(S.device))
 
+    def forward_batch_cat(self, items) -> torch.Tensor:
+        """x^(K) of every (Sigma_hat, S, params) of a minibatch, concatenated
+        in order, in batched launches."""
+        return _UnrolledBatch.apply(self.rho, list(items), self.ctx or P.default_context(items[0][1].device))
+
     def forward_batch(self, items):
-        """x^(K) of every (Sigma_hat, S, params) of a minibatch, in batched launches."""
+        """x^(K) of every (Sigma_hat, S, params) of a minibatch, one tensor per
+        instance (views of the concatenation)."""
         if not items:
             return ()
-        return _UnrolledBatch.apply(self.rho, list(items), self.ctx or P.default_context(items[0][1].device))
+        return tuple(self.forward_batch_cat(items).split([S.shape[1] for _, S, _ in items]))
 
     def project(self):
         """Keep every step size in [0, 1] after an optimiser step."""
@@ -142,8 +170,7 @@ def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch, batched: bool = 
     minibatch in batched launches (L <= 64), else instance by instance."""
     opt.zero_grad()
     if batched:
-        xs = net.forward_batch([(Sh, S, prm) for Sh, S, prm, _, _ in batch])
-        loss = sum(bce(x, alpha, g, net.known) for x, (_, _, _, alpha, g) in zip(xs, batch)) / len(batch)
+        loss = batch_loss(net, batch)
         loss.backward()
         total = loss.detach()
     else:

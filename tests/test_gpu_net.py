@@ -206,3 +206,13 @@ def test_batched_network_gradient_matches_oracle(P, variant):
     assert loss.item() == pytest.approx(loss_ref, rel=1e-3)
     got = model.rho.grad.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(got, g_ref, rtol=5e-3, atol=5e-3 * np.max(np.abs(g_ref)))
+    # the training step's form: one weighted sum over the concatenated devices
+    model.rho.grad = None
+    loss2 = NET.batch_loss(model, batch)
+    loss2.backward()
+    torch.cuda.synchronize()
+    assert loss2.item() == pytest.approx(loss_ref, rel=1e-3)
+    assert loss2.item() == pytest.approx(loss.item(), rel=1e-12)
+    got2 = model.rho.grad.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got2, g_ref, rtol=5e-3, atol=5e-3 * np.max(np.abs(g_ref)))
+    np.testing.assert_allclose(got2, got, rtol=1e-5, atol=1e-6 * np.max(np.abs(got)))
