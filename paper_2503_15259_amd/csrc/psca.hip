@@ -1561,9 +1561,22 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
     // where it stays until the solves of C4 overwrite it
     PSCA_MARK(it, 0);
     for (int c = tid; c < NT; c += THREADS) red_q[c] = known ? gs[c] * xs[c] : xs[c];
-    for (int e = tid; e < Lp * NT; e += THREADS) {
-      const int c = e / Lp, i = e - c * Lp;   // down a column: coalesced
-      Yt[i * PT + c] = s_at(i, c);
+    {
+      constexpr int kU = 8;   // loads in flight per thread
+      const int tot = Lp * NT;
+      for (int e0 = tid; e0 < tot; e0 += kU * THREADS) {
+        float2 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;   // down a column: coalesced
+          v[u] = e < tot ? s_at(i, c) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;
+          if (e < tot) Yt[i * PT + c] = v[u];
+        }
+      }
     }
     __syncthreads();
     for (int b = wave; b < NB; b += kWaves) {
@@ -1603,12 +1616,26 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       for (int e0 = 0; e0 < cnt; e0 += THREADS / Pp) {
         const int e_loc = e0 + tid % (THREADS / Pp), part = tid / (THREADS / Pp);
         double2 acc = make_double2(0.0, 0.0);
-        if (part < Pp && e_loc < cnt)
-          for (int h = part; h < A.G; h += Pp) {
-            const float2 v = A.partials[(size_t)h * A.pstride + start + e_loc];
+        if (part < Pp && e_loc < cnt) {
+          constexpr int kU = 8;   // loads in flight per thread
+          const float2 *src = A.partials + start + e_loc;
+          int h = part;
+          for (; h + (kU - 1) * Pp < A.G; h += kU * Pp) {
+            float2 v[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) v[u] = src[(size_t)(h + u * Pp) * A.pstride];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+              acc.x += v[u].x;
+              acc.y += v[u].y;
+            }
+          }
+          for (; h < A.G; h += Pp) {
+            const float2 v = src[(size_t)h * A.pstride];
             acc.x += v.x;
             acc.y += v.y;
           }
+        }
         dscr[tid] = acc;
         __syncthreads();
         const int e = start + e0 + tid;
