@@ -114,13 +114,6 @@ __device__ __forceinline__ void cmfma_d3(double2 a, double2 b, d4 &t1, d4 &t2, d
 // speculate it into unconditional code plus selects.
 #define PSCA_KEEP_BRANCH() asm volatile("" ::: "memory")
 
-__device__ __forceinline__ float2 cmul_conj(float2 a, float2 b) {  // a * conj(b)
-  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
-}
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
 // packed lower-block index of block (I, J), I >= J, and its inverse
 __device__ __forceinline__ int blk_index(int I, int J) { return I * (I + 1) / 2 + J; }
 __device__ __forceinline__ void blk_coords(int b, int &I, int &J) {
@@ -128,11 +121,6 @@ __device__ __forceinline__ void blk_coords(int b, int &I, int &J) {
   while ((r + 1) * (r + 2) / 2 <= b) ++r;
   I = r;
   J = b - r * (r + 1) / 2;
-}
-// offset of element (i, j), i >= j, in the block-packed lower triangle
-// (blocks column-major inside: element (ii, jj) at jj * 16 + ii)
-__device__ __forceinline__ int bp_offset(int i, int j) {
-  return blk_index(i >> 4, j >> 4) * 256 + (j & 15) * 16 + (i & 15);
 }
 
 // ---------------------------------------------------------------------------
@@ -840,7 +828,7 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
 template <int LPMAX, int THREADS>
 __device__ __forceinline__ void psca_body(const CoopArgs &A, const int g) {
   constexpr int kWaves = THREADS / 64;
-  constexpr int Lp = LPMAX, Lb = LPMAX / kBlk, NB = Lb * (Lb + 1) / 2;   // padded pilot length
+  constexpr int Lp = LPMAX, Lb = LPMAX / kBlk;                          // padded pilot length
   constexpr int P = Lp + 1;                                             // pitch of the L x L LDS matrix
   constexpr bool kShLds = LPMAX <= 64;                                  // SigmaHat resident in LDS
   extern __shared__ float4 smem_raw[];
@@ -1425,12 +1413,10 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
 // diagonal block J redundantly in registers and keeps W_JJ = L_JJ^-1 in LDS;
 // the trailing updates A_IK -= L_IJ L_KJ^H are spread over all wavefronts
 // of the instance, each forming the panel blocks L_IJ = A_IJ W_JJ^H it
-// needs, with one device-wide barrier per block step.  Each workgroup then solves its own tile,
-// Y = L^-1 S_t (q = |y|^2) and B = L^-H Y, one block row per round with the
-// row's block products split over its wavefronts, and forms
-// q - r = b^H (Sigma - SigmaHat) b, the difference taken in phase B from the
-// FP64 sum.
-constexpr int kLargeMaxLp = 256;
+// needs, with one device-wide barrier per block step.  Each workgroup then
+// solves its own tile, Y = L^-1 S_t (q = |y|^2) and B = L^-H Y, one
+// wavefront per 16-column block, and forms q - r = b^H (Sigma - SigmaHat) b,
+// the difference taken in phase B from the FP64 sum.
 
 struct LargeArgs {
   CoopArgs c;             // sigma: packed Sigma, updated in place by the trailing steps
