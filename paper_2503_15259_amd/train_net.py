@@ -8,8 +8,10 @@ validation uses seeds from 10^6 on, disjoint from training.  The step sizes
 kept are those of the best validation loss seen (checked 20 times during
 training), and the detection threshold is the one minimising the validation
 error rate.
-Every forward and backward pass runs in the HIP kernels (psca_net_forward,
-psca_layer_backward); Adam on the K step sizes, projected to [0, 1].
+Every forward and backward pass runs in the HIP kernels: a minibatch goes
+through one psca_detect_batch launch with every iterate recorded and one
+psca_layer_backward_batch launch per layer, validation through
+psca_net_forward; Adam on the K step sizes, projected to [0, 1].
 """
 from __future__ import annotations
 
