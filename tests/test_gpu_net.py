@@ -166,6 +166,45 @@ def test_layer_backward_batch_matches_oracle_and_single_calls(P):
         assert float(gr[k].item()) == pytest.approx(float(singles[k][1].item()), rel=2e-3, abs=tol), k
 
 
+def test_layer_backward_batch_full_minibatch_sampled(P):
+    """One layer's batched backward over a full training minibatch (512 MAP-UR
+    instances at N=1000, L=64, M=128), at seeded iterates: every status is 0,
+    three sampled instances agree with the single-instance backward, and two
+    of them meet the oracle's vector-Jacobian product."""
+    B, N, L, M, rho = 512, 1000, 64, 128, 0.3
+    wid = I.WORKLOAD_IDS["net"]
+    items, xs, vs, insts = [], [], [], []
+    rng = np.random.default_rng(2024)
+    for k in range(B):
+        inst = I.make_instance(wid, k, N, L, M, 0.1).fp32_inputs()
+        x = (inst.g * rng.uniform(0.0, 0.3, N)).astype(np.float32).astype(np.float64)
+        v = rng.standard_normal(N).astype(np.float32).astype(np.float64)
+        items.append((P.sample_cov(c64(inst.Y)), c64(inst.S), params_for(P, inst, O.MAP_UR), f32(x), f32(v)))
+        xs.append(x)
+        vs.append(v)
+        insts.append(inst)
+    status = torch.full((B,), 7, dtype=torch.int32, device=dev())
+    print(f"[layer backward batch of {B}, MAP-UR N={N} L={L} M={M}]", flush=True)
+    gxs, gr = P.layer_backward_batch(items, rho, status=status)
+    torch.cuda.synchronize()
+    assert int((status != 0).sum().item()) == 0
+    for k in (0, 255, 511):
+        Sh, S, prm, x_t, v_t = items[k]
+        gx1, gr1 = P.layer_backward(Sh, S, prm, rho, x_t, v_t)
+        torch.cuda.synchronize()
+        gx = gxs[k].cpu().numpy().astype(np.float64)
+        scale = np.max(np.abs(gx1.cpu().numpy()))
+        assert np.max(np.abs(gx - gx1.cpu().numpy())) / scale < 2e-3, k
+        tol = 1e-6 * np.sum(np.abs(vs[k])) * np.max(np.abs(xs[k]))
+        assert float(gr[k].item()) == pytest.approx(float(gr1.item()), rel=2e-3, abs=tol), k
+    for k in (0, 511):
+        dx_ref, drho_ref = O.layer_vjp(O.problem_from_instance(insts[k], O.MAP_UR, eps=EPS), xs[k], rho, vs[k])
+        gx = gxs[k].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(gx - dx_ref)) / np.max(np.abs(dx_ref)) < 2e-3, k
+        tol = 1e-6 * np.sum(np.abs(vs[k])) * np.max(np.abs(xs[k]))
+        assert float(gr[k].item()) == pytest.approx(drho_ref, rel=2e-3, abs=tol), k
+
+
 def test_layer_backward_batch_validation(P):
     inst = I.make_instance(3, 5, 30, 80, 16, 0.2).fp32_inputs()
     Sh = P.sample_cov(c64(inst.Y))

@@ -305,6 +305,39 @@ def test_uneven_batch_matches_oracle_for_every_team_size(P):
             assert_parity(x, ref, O.ML_UD, f"team={key} " + label(inst, O.ML_UD, 20))
 
 
+def test_uneven_full_batch_sampled_against_oracle(P):
+    """The uneven configuration at full size, launched as the benchmark does:
+    4096 ML-UD detections (100 iterations) cycling 64 distinct instances, team
+    size from the autotuner.  Every device status is 0; every copy of an
+    instance returns the same vector bit for bit (same tiles and reduction
+    order wherever it runs); four sampled instances meet the oracle bar."""
+    pool, iters, B = 64, 100, 4096
+    wid = I.WORKLOAD_IDS["uneven"]
+    insts = [I.make_uneven_instance(wid, k).fp32_inputs() for k in range(pool)]
+    Ss = [c64(x.S) for x in insts]
+    Shs = [P.sample_cov(c64(x.Y)) for x in insts]
+    status = torch.full((B,), 7, dtype=torch.int32, device=dev())
+    probs = [P.Problem(Sigma_hat=Shs[b % pool], S=Ss[b % pool],
+                       params=P.Params(variant=O.ML_UD, iters=iters, sigma2=insts[b % pool].sigma2,
+                                       M=insts[b % pool].M),
+                       status=status[b:b + 1]) for b in range(B)]
+    print(f"[uneven full batch: {B} instances, ML-UD, {iters} iterations]", flush=True)
+    T = P.autotune_batch(probs, tune_iters=4)
+    plan = P.Plan(probs, team_size=T)
+    outs = plan.launch()
+    torch.cuda.synchronize()
+    assert int((status != 0).sum().item()) == 0
+    got = torch.cat(outs)
+    first = torch.cat([outs[b % pool] for b in range(B)])
+    assert torch.equal(got, first)
+    assert bool(torch.isfinite(got).all()) and bool((got >= 0).all())
+    for k in (0, 17, 40, 63):
+        ref = O.psca(O.problem_from_instance(insts[k], O.ML_UD, eps=EPS), iters)
+        assert_parity(outs[k].cpu().numpy().astype(np.float64), ref, O.ML_UD,
+                      f"full batch, team={T} " + label(insts[k], O.ML_UD, iters))
+    plan.close()
+
+
 def test_plan_replays_inside_a_captured_graph(P):
     """A planned batch captured into a graph and replayed three times, with
     eager work and synchronisation between replays: every replay reproduces
