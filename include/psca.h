@@ -229,11 +229,12 @@ typedef struct {
 int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream);
 
 /* Autotuner for psca_detect_batch: times the batch with every candidate team
- * size (each instance capped at tune_iters >= 1 iterations; candidates from
- * the smallest feasible team to the whole GPU) and remembers the fastest in
+ * specification (each instance capped at tune_iters >= 1 iterations;
+ * uniform team sizes from the smallest feasible team to the whole GPU, and
+ * mixed teams for 32-, 48- and 64-column tiles) and remembers the fastest in
  * the context for batches with the same (L, N) list.  Synchronous; writes
  * scratch results into the instances' x_out.  *team_size (optional)
- * receives the choice. */
+ * receives the choice, in the encoding of psca_plan_create. */
 int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int tune_iters, int *team_size,
                         void *stream);
 
@@ -242,7 +243,19 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
  * team lists, descriptors; synchronous); psca_plan_launch only enqueues two
  * kernels (barrier reset, persistent batch), so it may be captured.  The
  * problems' device buffers must stay valid while the plan is used; their
- * contents are read at each launch.  team_size 0 = tuned or default.
+ * contents are read at each launch.  team_size:
+ *   > 0  uniform teams of team_size workgroups (at least the smallest
+ *        feasible team, at most the co-resident capacity);
+ *   < 0  mixed teams: instance b runs on a team of
+ *        max(ceil(N_b / largest tile), ceil(N_b / -team_size)) workgroups
+ *        (rounded up to a power of two); instances of one team size
+ *        share that size's teams, and each size gets teams in proportion to
+ *        its work.  -team_size is 16, 32, 48 or 64;
+ *   0    the value psca_autotune_batch chose for this (L, N) list, else the
+ *        default of psca_detect_batch.
+ * Other values return PSCA_EINVAL.  psca_plan_team_size returns the plan's
+ * team_size in this encoding (mixed specifications are multiples of 16, so
+ * they never equal an error code).
  * Inside a capture the batch kernel is recorded as an ordinary kernel node,
  * which relies on its grid (at most the device's co-resident capacity) being
  * resident at once; the bounded device-wide waits report PSCA_ESYNC if not. */

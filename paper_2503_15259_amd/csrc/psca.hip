@@ -37,6 +37,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
+#include <map>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -1904,9 +1906,16 @@ __device__ __noinline__ void team_member(const CoopArgs *__restrict__ desc, int 
 
 __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__restrict__ descs,
                                                               const int *__restrict__ lists,
-                                                              const int *__restrict__ offsets, int T) {
+                                                              const int *__restrict__ offsets,
+                                                              const int *__restrict__ team_start, int n_teams) {
   const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);
-  const int t = b / T, g = b - t * T;
+  int t = 0, hi = n_teams - 1;   // the team with team_start[t] <= b < team_start[t + 1]
+  while (t < hi) {
+    const int mid = (t + hi + 1) >> 1;
+    if (team_start[mid] <= b) t = mid;
+    else hi = mid - 1;
+  }
+  const int g = b - team_start[t];
   const int i1 = offsets[t + 1];
   for (int idx = offsets[t]; idx < i1; ++idx) {
     const CoopArgs *desc = descs + lists[idx];
@@ -2422,15 +2431,17 @@ int run_layer_backward(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, 
 constexpr size_t kMaxLds = 159 * 1024;   // dynamic LDS per workgroup (160 KB on gfx950, less the static part)
 
 struct BatchPlan {
-  int B = 0, T = 0, n_teams = 0;
+  int B = 0, T = 0, n_teams = 0;   // T: the team specification (team_spec_ok)
   size_t lds = 0;
   std::vector<psca_problem> probs;
   std::vector<InstPlan> ip;
   std::vector<int> iters;        // per instance (capped while tuning)
   std::vector<int> team_of;
   std::vector<int> lists, offsets;
+  std::vector<int> team_start;   // [n_teams + 1]: first logical workgroup of each team; the grid
   std::vector<size_t> ws_off;    // per instance: Sigma, barrier words, status
-  size_t part_off = 0, part_stride = 0;   // per team partials: T ranks of E_max entries
+  std::vector<size_t> part_team_off;   // per team partials (its ranks x E_max entries), from part_off
+  size_t part_off = 0;
   size_t E_max = 0;
   size_t ws_bytes = 0;
 };
@@ -2473,27 +2484,87 @@ int default_team(int B, const psca_problem *pr, int cap) {
   return T0;
 }
 
-// Plans a batch on teams of T workgroups: tiles, longest-first assignment of
-// instances to teams (the estimated cost of an iteration grows with the
-// pivot blocks and with the tile's MFMA work) and the workspace layout.
+// Team specification of a batch plan: spec > 0, teams of spec workgroups;
+// spec < 0, mixed teams: each instance gets a team sized for tiles of about
+// -spec columns (a multiple of 16, at most 16 kMaxNcb).
+bool team_spec_ok(int spec, int cap) {
+  if (spec > 0) return spec <= cap;
+  return spec < 0 && (-spec) % 16 == 0 && -spec <= 16 * kMaxNcb;
+}
+
+// Longest-first assignment of `items` (indices into cost) to the teams
+// [t0, t0 + n): each goes to the least loaded team so far.
+void assign_longest_first(std::vector<int> items, const std::vector<double> &cost, int t0, int n,
+                          std::vector<std::vector<int>> &team, std::vector<int> &team_of) {
+  std::stable_sort(items.begin(), items.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<double> load(n, 0.0);
+  for (int b : items) {
+    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    team[t0 + t].push_back(b);
+    team_of[b] = t0 + t;
+    load[t] += cost[b];
+  }
+}
+
+// Plans a batch: team sizes, tiles, longest-first assignment of instances to
+// teams (the estimated cost of an iteration grows with the pivot blocks and
+// with the tile's MFMA work) and the workspace layout.
+//  * spec > 0: n = min(cap / spec, B) teams of spec workgroups, every
+//    instance on any of them;
+//  * spec < 0: instance b needs a team of T_b = max(ceil(N_b / max tile),
+//    ceil(N_b / -spec)) workgroups, rounded up to a power of two.
+//    Instances with the same T_b form a class with its own teams; while one
+//    team per class would not fit the grid, the smallest class joins the
+//    next larger one.  Every class starts with one team, then teams are
+//    added to the class with the most work per team while the grid fits.
+//    Small instances then run on small teams, several at a time, instead of
+//    idling most of a team sized for the largest one.
 // iters_cap >= 0 caps every instance's iteration count (tuning runs).
-int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &plan, int iters_cap) {
-  if (T < 1 || T > cap) return PSCA_EINVAL;
+int make_batch_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan &plan, int iters_cap) {
+  if (!team_spec_ok(spec, cap)) return PSCA_EINVAL;
   plan = BatchPlan();
   plan.B = B;
-  plan.T = T;
-  plan.n_teams = std::max(1, std::min(cap / T, B));
+  plan.T = spec;
   plan.probs.assign(pr, pr + B);
   plan.ip.resize(B);
   plan.iters.resize(B);
+  std::vector<int> tsize(B, spec);   // team size of each instance
+  for (int b = 0; b < B; ++b) {
+    const int mt = max_tile((pr[b].L + 15) & ~15);
+    if (mt == 0) return PSCA_ENOTSUP;
+    if (spec < 0) {
+      const int need = std::max((pr[b].N + mt - 1) / mt, (pr[b].N - spec - 1) / (-spec));
+      int T = 1;
+      while (T < need) T *= 2;
+      tsize[b] = T;
+    }
+    if (tsize[b] > cap) return PSCA_ENOTSUP;
+  }
+  if (spec < 0) {   // merge the smallest class into the next larger one while one team each overflows
+    std::vector<int> sizes(tsize);
+    std::sort(sizes.begin(), sizes.end());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    long long used = 0;
+    for (int v : sizes) used += v;
+    size_t first = 0;
+    while (used > cap && first + 1 < sizes.size()) {
+      used -= sizes[first];
+      for (int &t : tsize)
+        if (t == sizes[first]) t = sizes[first + 1];
+      ++first;
+    }
+    if (used > cap) return PSCA_ENOTSUP;
+  }
   std::vector<double> cost(B);
   size_t E_max = 0;
   for (int b = 0; b < B; ++b) {
     InstPlan &q = plan.ip[b];
     q.Lp = (pr[b].L + 15) & ~15;
+    const int mt = max_tile(q.Lp);
+    const int T = tsize[b];
     const int per = (pr[b].N + T - 1) / T;
     q.NT = std::max(16, (per + 15) & ~15);
-    if (q.NT > max_tile(q.Lp)) return PSCA_ENOTSUP;
+    if (q.NT > mt) return PSCA_ENOTSUP;
     q.ncb = q.NT / 16;
     // every member of the team takes part (tiles past N are empty), so a
     // team moves through its list in step and no member waits at an
@@ -2507,18 +2578,57 @@ int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
     cost[b] = (double)plan.iters[b] * (3.0 * Lb + 0.05 * q.ncb * Lb * Lb + 8.0);
     E_max = std::max(E_max, packed_entries(q.Lp));
   }
-  std::vector<int> order(B);
-  for (int b = 0; b < B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  std::vector<double> load(plan.n_teams, 0.0);
-  std::vector<std::vector<int>> team(plan.n_teams);
+  std::vector<int> team_size;   // per team
+  std::vector<std::vector<int>> team;
   plan.team_of.resize(B);
-  for (int b : order) {
-    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    team[t].push_back(b);
-    plan.team_of[b] = t;
-    load[t] += cost[b];
+  if (spec > 0) {
+    const int n = std::max(1, std::min(cap / spec, B));
+    team_size.assign(n, spec);
+    team.resize(n);
+    std::vector<int> all(B);
+    for (int b = 0; b < B; ++b) all[b] = b;
+    assign_longest_first(all, cost, 0, n, team, plan.team_of);
+  } else {
+    std::map<int, std::vector<int>, std::greater<int>> cls;   // team size -> instances, largest first
+    for (int b = 0; b < B; ++b) cls[plan.ip[b].G].push_back(b);
+    std::vector<int> size_of, count;
+    std::vector<double> work;
+    int used = 0;
+    for (const auto &kv : cls) {
+      size_of.push_back(kv.first);
+      double w = 0.0;
+      for (int b : kv.second) w += cost[b];
+      work.push_back(w);
+      count.push_back(1);
+      used += kv.first;
+    }
+    if (used > cap) return PSCA_ENOTSUP;
+    for (;;) {   // one more team for the class with the most work per team that still fits
+      int best = -1, c = 0;
+      double best_w = 0.0;
+      for (const auto &kv : cls) {
+        if (count[c] < (int)kv.second.size() && size_of[c] <= cap - used && work[c] / count[c] > best_w) {
+          best = c;
+          best_w = work[c] / count[c];
+        }
+        ++c;
+      }
+      if (best < 0) break;
+      ++count[best];
+      used += size_of[best];
+    }
+    int c = 0;
+    for (const auto &kv : cls) {
+      const int t0 = (int)team_size.size();
+      for (int k = 0; k < count[c]; ++k) team_size.push_back(size_of[c]);
+      team.resize(team_size.size());
+      assign_longest_first(kv.second, cost, t0, count[c], team, plan.team_of);
+      ++c;
+    }
   }
+  plan.n_teams = (int)team_size.size();
+  plan.team_start.assign(1, 0);
+  for (int t = 0; t < plan.n_teams; ++t) plan.team_start.push_back(plan.team_start.back() + team_size[t]);
   plan.offsets.push_back(0);
   for (int t = 0; t < plan.n_teams; ++t) {
     for (int b : team[t]) plan.lists.push_back(b);
@@ -2532,8 +2642,12 @@ int make_batch_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
   }
   plan.part_off = off;
   plan.E_max = E_max;
-  plan.part_stride = align_up((size_t)T * E_max * sizeof(float2));
-  plan.ws_bytes = off + plan.part_stride * plan.n_teams;
+  size_t part = 0;
+  for (int t = 0; t < plan.n_teams; ++t) {
+    plan.part_team_off.push_back(part);
+    part += align_up((size_t)team_size[t] * E_max * sizeof(float2));
+  }
+  plan.ws_bytes = off + part;
   return PSCA_OK;
 }
 
@@ -2556,16 +2670,16 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
     a.x_hist = q.x_hist;
     // every rank of a team owns the same slot for all of the team's instances:
     // a rank that sits out an instance may start the next one early
-    a.partials = (float2 *)(base + plan.part_off + (size_t)plan.team_of[b] * plan.part_stride);
+    a.partials = (float2 *)(base + plan.part_off + plan.part_team_off[plan.team_of[b]]);
     a.pstride = plan.E_max;
     out[b] = a;
   }
 }
 
-// Host image of a plan's device arrays: descriptors, lists, offsets.
+// Host image of a plan's device arrays: descriptors, lists, offsets, team starts.
 size_t batch_image_bytes(const BatchPlan &plan) {
   return align_up(plan.B * sizeof(CoopArgs)) + align_up(plan.lists.size() * sizeof(int)) +
-         align_up(plan.offsets.size() * sizeof(int));
+         align_up(plan.offsets.size() * sizeof(int)) + align_up(plan.team_start.size() * sizeof(int));
 }
 
 void write_batch_image(const BatchPlan &plan, char *ws_base, char *img) {
@@ -2574,6 +2688,8 @@ void write_batch_image(const BatchPlan &plan, char *ws_base, char *img) {
   memcpy(p, plan.lists.data(), plan.lists.size() * sizeof(int));
   p += align_up(plan.lists.size() * sizeof(int));
   memcpy(p, plan.offsets.data(), plan.offsets.size() * sizeof(int));
+  p += align_up(plan.offsets.size() * sizeof(int));
+  memcpy(p, plan.team_start.data(), plan.team_start.size() * sizeof(int));
 }
 
 // Launches a planned batch whose device image is at `dimg`.
@@ -2581,19 +2697,20 @@ int launch_batch(const BatchPlan &plan, const char *dimg, hipStream_t st) {
   const CoopArgs *descs = (const CoopArgs *)dimg;
   const int *lists = (const int *)(dimg + align_up(plan.B * sizeof(CoopArgs)));
   const int *offsets = (const int *)((const char *)lists + align_up(plan.lists.size() * sizeof(int)));
-  int T = plan.T;
+  const int *team_start = (const int *)((const char *)offsets + align_up(plan.offsets.size() * sizeof(int)));
+  int n_teams = plan.n_teams;
   hipLaunchKernelGGL(k_prepare_batch, dim3(plan.B), dim3(256), 0, st, descs);
   int rc = launch_ok();
   if (rc != PSCA_OK) return rc;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess) return PSCA_EHIP;
-  const dim3 grid(plan.n_teams * plan.T), block(kBatchThreads);
+  const dim3 grid(plan.team_start.back()), block(kBatchThreads);
   if (cs == hipStreamCaptureStatusActive) {
     // graph capture: a plain kernel node; the grid fits the device at once
-    hipLaunchKernelGGL(k_psca_teams, grid, block, plan.lds, st, descs, lists, offsets, T);
+    hipLaunchKernelGGL(k_psca_teams, grid, block, plan.lds, st, descs, lists, offsets, team_start, n_teams);
     return launch_ok();
   }
-  void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&T};
+  void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&team_start, (void *)&n_teams};
   if (hipLaunchCooperativeKernel((const void *)k_psca_teams, grid, block, args, (unsigned)plan.lds, st) !=
       hipSuccess) {
     (void)hipGetLastError();
@@ -2916,7 +3033,7 @@ int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *
   if (cap <= 0) return PSCA_ENOTSUP;
   const auto hit = ctx->tuned.find(batch_signature(B, problems));
   const int T = (hit != ctx->tuned.end()) ? hit->second : default_team(B, problems, cap);
-  if (T < 0) return PSCA_ENOTSUP;
+  if (hit == ctx->tuned.end() && T < 0) return PSCA_ENOTSUP;
   BatchPlan plan;
   if ((rc = make_batch_plan(B, problems, T, cap, plan, -1)) != PSCA_OK) return rc;
   if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) return rc;
@@ -2945,7 +3062,7 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   const int cap = batch_capacity(ctx);
   const int T0 = min_team(B, problems);
   if (cap <= 0 || T0 < 0 || T0 > cap) return PSCA_ENOTSUP;
-  std::vector<int> cand = {T0, default_team(B, problems, cap)};
+  std::vector<int> cand = {T0, default_team(B, problems, cap), -32, -48, -64};   // < 0: mixed teams
   for (int t : {8, 16, 24, 32, 48, 64, 96, 128, 192, 256})
     if (t >= T0 && t <= cap) cand.push_back(t);
   if ((long long)B * T0 <= cap) cand.push_back(cap / B);
@@ -2960,7 +3077,7 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   int best = -1;
   float best_ms = 0.0f;
   for (int T : cand) {
-    if (T < T0) continue;
+    if (T > 0 && T < T0) continue;
     BatchPlan plan;
     if (make_batch_plan(B, problems, T, cap, plan, tune_iters) != PSCA_OK) continue;
     if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) break;
@@ -2997,7 +3114,7 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
 }
 
 int psca_plan_create(psca_ctx *ctx, int B, const psca_problem *problems, int team_size, psca_plan **out) {
-  if (!ctx || !out || team_size < 0) return PSCA_EINVAL;
+  if (!ctx || !out) return PSCA_EINVAL;
   *out = nullptr;
   int rc = validate_batch(B, problems);
   if (rc != PSCA_OK) return rc;
@@ -3010,9 +3127,9 @@ int psca_plan_create(psca_ctx *ctx, int B, const psca_problem *problems, int tea
   if (T == 0) {
     const auto hit = ctx->tuned.find(batch_signature(B, problems));
     T = (hit != ctx->tuned.end()) ? hit->second : default_team(B, problems, cap);
+    if (T == -1) return PSCA_ENOTSUP;   // no feasible default
   }
-  if (T < 0) return PSCA_ENOTSUP;
-  if (T < min_team(B, problems) || T > cap) return PSCA_EINVAL;
+  if (!team_spec_ok(T, cap) || (T > 0 && T < min_team(B, problems))) return PSCA_EINVAL;
   psca_plan *p = new (std::nothrow) psca_plan;
   if (!p) return PSCA_ENOMEM;
   p->device = ctx->device;

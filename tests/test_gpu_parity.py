@@ -264,6 +264,11 @@ def test_batch_validation_and_empty(P):
         P.detect_batch([P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, O.ML_UD, 5)),
                         P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=bad)])
     assert e.value.code == -1
+    good = [P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, O.ML_UD, 5))]
+    for spec in (-7, -80, -1, 100000):   # mixed specs are multiples of 16 up to 64 columns
+        with pytest.raises(P.PscaError) as e:
+            P.Plan(good, team_size=spec)
+        assert e.value.code == -1, spec
 
 
 def _uneven_batch(P, count, iters, variant=O.ML_UD):
@@ -281,8 +286,9 @@ def _uneven_batch(P, count, iters, variant=O.ML_UD):
 
 def test_uneven_batch_matches_oracle_for_every_team_size(P):
     """Uneven batch (N ~ U{200..2000}, L in {32,48,64,96}, M in {64,128,256},
-    p ~ U[0.05, 0.2]) in one persistent launch, with the default team size and
-    with forced smallest and larger teams: every instance meets the oracle bar."""
+    p ~ U[0.05, 0.2]) in one persistent launch, with the default team size,
+    with forced uniform teams and with mixed teams (sized per instance for
+    32- and 64-column tiles): every instance meets the oracle bar."""
     probs, refs, insts = _uneven_batch(P, 12, 20)
     print("[uneven batch 12 instances, ML-UD, 20 iterations]", flush=True)
     outs = P.detect_batch(probs)
@@ -290,7 +296,7 @@ def test_uneven_batch_matches_oracle_for_every_team_size(P):
     results = {"default": [x.cpu().numpy().astype(np.float64) for x in outs]}
     for pb in probs:
         assert int(pb.status.item()) == 0
-    for T in (32, 80):
+    for T in (32, 80, -32, -64):
         for pb in probs:
             pb.out = None
         plan = P.Plan(probs, team_size=T)
@@ -375,7 +381,7 @@ def test_plan_replays_inside_a_captured_graph(P):
 def test_autotuner_choice_is_used_and_exact(P):
     probs, refs, insts = _uneven_batch(P, 5, 12)
     T = P.autotune_batch(probs, tune_iters=2)
-    assert 1 <= T <= 256
+    assert 1 <= T <= 256 or T in (-32, -48, -64)
     for pb in probs:
         pb.out = None
     outs = P.detect_batch(probs)
