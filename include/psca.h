@@ -229,12 +229,14 @@ typedef struct {
 int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream);
 
 /* Autotuner for psca_detect_batch: times the batch with every candidate team
- * specification (each instance capped at tune_iters >= 1 iterations;
- * uniform team sizes from the smallest feasible team to the whole GPU, and
- * mixed teams for 32-, 48- and 64-column tiles) and remembers the fastest in
- * the context for batches with the same (L, N) list.  Synchronous; writes
- * scratch results into the instances' x_out.  *team_size (optional)
- * receives the choice, in the encoding of psca_plan_create. */
+ * specification (uniform team sizes from the smallest feasible team to the
+ * whole GPU, and mixed teams for 32-, 48- and 64-column tiles), each
+ * instance capped at tune_iters >= 1 and at 2 tune_iters iterations, and
+ * keeps the one whose time extrapolated from those two runs to the batch's
+ * largest iteration count is least, in the context, for batches with the
+ * same (L, N) list.  Synchronous; writes scratch results into the
+ * instances' x_out.  *team_size (optional) receives the choice, in the
+ * encoding of psca_plan_create. */
 int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int tune_iters, int *team_size,
                         void *stream);
 

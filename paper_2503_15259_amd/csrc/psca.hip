@@ -3074,40 +3074,54 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
     (void)hipEventDestroy(e0);
     return PSCA_EHIP;
   }
-  int best = -1;
+  // Each candidate is timed at k1 = tune_iters and k2 = 2 tune_iters capped
+  // iterations; the launch at the batch's own iteration count is estimated
+  // from the two points (per-instance set-up and the tail of the team
+  // lists weigh more at few iterations than at many).
+  int K = 1;
+  for (int b = 0; b < B; ++b) K = std::max(K, (int)problems[b].prm.iters);
+  auto time_plan = [&](int T, int k, bool warm, float *ms) -> int {
+    BatchPlan plan;
+    int r = make_batch_plan(B, problems, T, cap, plan, k);
+    if (r != PSCA_OK) return r;
+    if ((r = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) return r;
+    const size_t bytes = batch_image_bytes(plan);
+    char *host = nullptr;
+    if ((r = stage_desc(ctx, bytes, &host)) != PSCA_OK) return r;
+    write_batch_image(plan, (char *)ctx->ws, host);
+    if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(ctx->desc_done, st) != hipSuccess)
+      return PSCA_EHIP;
+    ctx->desc_pending = true;
+    if (warm && (r = launch_batch(plan, (const char *)ctx->ddesc, st)) != PSCA_OK) return r;
+    if (hipEventRecord(e0, st) != hipSuccess) return PSCA_EHIP;
+    if ((r = launch_batch(plan, (const char *)ctx->ddesc, st)) != PSCA_OK) return r;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return PSCA_EHIP;
+    return PSCA_OK;
+  };
+  bool found = false;   // team specifications may be negative (mixed teams)
+  int best = 0;
   float best_ms = 0.0f;
   for (int T : cand) {
     if (T > 0 && T < T0) continue;
-    BatchPlan plan;
-    if (make_batch_plan(B, problems, T, cap, plan, tune_iters) != PSCA_OK) continue;
-    if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) break;
-    const size_t bytes = batch_image_bytes(plan);
-    char *host = nullptr;
-    if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) break;
-    write_batch_image(plan, (char *)ctx->ws, host);
-    if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipEventRecord(ctx->desc_done, st) != hipSuccess) {
-      rc = PSCA_EHIP;
-      break;
-    }
-    ctx->desc_pending = true;
-    float ms = 0.0f;
-    if ((rc = launch_batch(plan, (const char *)ctx->ddesc, st)) != PSCA_OK ||   // warm-up
-        hipEventRecord(e0, st) != hipSuccess || (rc = launch_batch(plan, (const char *)ctx->ddesc, st)) != PSCA_OK ||
-        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      if (rc == PSCA_OK) rc = PSCA_EHIP;
-      break;
-    }
-    if (best < 0 || ms < best_ms) {
+    BatchPlan probe;
+    if (make_batch_plan(B, problems, T, cap, probe, tune_iters) != PSCA_OK) continue;   // infeasible
+    const int k1 = tune_iters, k2 = 2 * tune_iters;
+    float t1 = 0.0f, t2 = 0.0f;
+    if ((rc = time_plan(T, k1, true, &t1)) != PSCA_OK || (rc = time_plan(T, k2, false, &t2)) != PSCA_OK) break;
+    const float est = K <= k1 ? t1 : t1 + (t2 - t1) * (float)(K - k1) / (float)(k2 - k1);
+    if (!found || est < best_ms) {
+      found = true;
       best = T;
-      best_ms = ms;
+      best_ms = est;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != PSCA_OK) return rc;
-  if (best < 0) return PSCA_ENOTSUP;
+  if (!found) return PSCA_ENOTSUP;
   ctx->tuned[batch_signature(B, problems)] = best;
   if (team_size) *team_size = best;
   return PSCA_OK;
