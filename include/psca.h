@@ -257,7 +257,8 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
  *        default of psca_detect_batch.
  * Other values return PSCA_EINVAL.  psca_plan_team_size returns the plan's
  * team_size in this encoding (mixed specifications are multiples of 16, so
- * they never equal an error code).
+ * they never equal an error code); a mixed specification under which every
+ * instance gets the same team size T is the uniform plan of T and reports T.
  * Inside a capture the batch kernel is recorded as an ordinary kernel node,
  * which relies on its grid (at most the device's co-resident capacity) being
  * resident at once; the bounded device-wide waits report PSCA_ESYNC if not. */

@@ -2519,6 +2519,8 @@ void assign_longest_first(std::vector<int> items, const std::vector<double> &cos
 //    added to the class with the most work per team while the grid fits.
 //    Small instances then run on small teams, several at a time, instead of
 //    idling most of a team sized for the largest one.
+// A mixed specification that yields a single class is the uniform plan of
+// that team size and is recorded as such (plan.T).
 // iters_cap >= 0 caps every instance's iteration count (tuning runs).
 int make_batch_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan &plan, int iters_cap) {
   if (!team_spec_ok(spec, cap)) return PSCA_EINVAL;
@@ -2603,6 +2605,15 @@ int make_batch_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan 
       used += kv.first;
     }
     if (used > cap) return PSCA_ENOTSUP;
+    if (cls.size() == 1) {   // one team size for all: exactly the uniform plan of that size
+      const int T = cls.begin()->first;
+      plan.T = T;
+      const int n = std::max(1, std::min(cap / T, B));
+      team_size.assign(n, T);
+      team.resize(n);
+      assign_longest_first(cls.begin()->second, cost, 0, n, team, plan.team_of);
+      cls.clear();
+    }
     for (;;) {   // one more team for the class with the most work per team that still fits
       int best = -1, c = 0;
       double best_w = 0.0;
@@ -3104,10 +3115,14 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   bool found = false;   // team specifications may be negative (mixed teams)
   int best = 0;
   float best_ms = 0.0f;
+  std::vector<int> seen;
   for (int T : cand) {
     if (T > 0 && T < T0) continue;
     BatchPlan probe;
     if (make_batch_plan(B, problems, T, cap, probe, tune_iters) != PSCA_OK) continue;   // infeasible
+    T = probe.T;   // a single-class mixed plan is a uniform one
+    if (std::find(seen.begin(), seen.end(), T) != seen.end()) continue;
+    seen.push_back(T);
     const int k1 = tune_iters, k2 = 2 * tune_iters;
     float t1 = 0.0f, t2 = 0.0f;
     if ((rc = time_plan(T, k1, true, &t1)) != PSCA_OK || (rc = time_plan(T, k2, false, &t2)) != PSCA_OK) break;
