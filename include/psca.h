@@ -250,7 +250,8 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
  *        feasible team, at most the co-resident capacity);
  *   < 0  mixed teams: instance b runs on a team of
  *        max(ceil(N_b / largest tile), ceil(N_b / -team_size)) workgroups
- *        (rounded up to a power of two); instances of one team size
+ *        (rounded up to the next of 1, 2, 4, 6, 8, 12, 16, 24, 32, 48, ...:
+ *        powers of two and their 1.5 multiples); instances of one team size
  *        share that size's teams, and each size gets teams in proportion to
  *        its work.  -team_size is 16, 32, 48 or 64;
  *   0    the value psca_autotune_batch chose for this (L, N) list, else the

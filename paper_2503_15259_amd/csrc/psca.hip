@@ -2512,7 +2512,8 @@ void assign_longest_first(std::vector<int> items, const std::vector<double> &cos
 //  * spec > 0: n = min(cap / spec, B) teams of spec workgroups, every
 //    instance on any of them;
 //  * spec < 0: instance b needs a team of T_b = max(ceil(N_b / max tile),
-//    ceil(N_b / -spec)) workgroups, rounded up to a power of two.
+//    ceil(N_b / -spec)) workgroups, rounded up to the next of 1, 2, 4, 6,
+//    8, 12, 16, 24, 32, 48, ... (powers of two and their 1.5 multiples).
 //    Instances with the same T_b form a class with its own teams; while one
 //    team per class would not fit the grid, the smallest class joins the
 //    next larger one.  Every class starts with one team, then teams are
@@ -2536,8 +2537,8 @@ int make_batch_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan 
     if (mt == 0) return PSCA_ENOTSUP;
     if (spec < 0) {
       const int need = std::max((pr[b].N + mt - 1) / mt, (pr[b].N - spec - 1) / (-spec));
-      int T = 1;
-      while (T < need) T *= 2;
+      int T = 1;   // the ladder 1, 2, 4, 6, 8, 12, 16, 24, 32, 48, ...
+      while (T < need) T = T < 4 ? 2 * T : ((T & (T - 1)) == 0 ? T + T / 2 : T / 3 * 4);
       tsize[b] = T;
     }
     if (tsize[b] > cap) return PSCA_ENOTSUP;
