@@ -37,9 +37,9 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per k_psca_teams launch of the default workload (four detections,
 # teams of 32 workgroups) from the FETCH_SIZE and WRITE_SIZE counter passes,
 # each scaled by the copy-kernel calibration (profile
-# k_psca_teams_single_N1000_L64_x4_traffic.md): 176.5 MB fetched + 297.1 MB
+# k_psca_teams_single_N1000_L64_x4_traffic.md): 176.6 MB fetched + 297.1 MB
 # written.  Keyed by team size; other team sizes report null.
-TRAFFIC_BYTES_PER_LAUNCH = {32: 473667858}
+TRAFFIC_BYTES_PER_LAUNCH = {32: 473766760}
 
 
 def iteration_flops(N, L):
