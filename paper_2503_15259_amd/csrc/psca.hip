@@ -1090,10 +1090,12 @@ struct BackArgs {
   float2 *gram_a, *gram_b;   // packed G_a, G_b
 };
 
-// LDS footprint of the backward body (Lp <= 64, SigmaHat resident)
+// LDS footprint of the backward body (Lp <= 64, SigmaHat resident).  At
+// Lp = 64 the per-wavefront scratch shares the B and C tiles (see the body).
 __host__ __device__ inline size_t lds_back_bytes(int Lp, int NT, int waves) {
   const size_t pt = (size_t)NT + 1, P = (size_t)Lp + 1, Lb = (size_t)Lp / 16;
-  const size_t f2 = 3 * (size_t)Lp * pt + (size_t)Lp * 17 + 2 * (size_t)Lp * P + (size_t)waves * 256;
+  const size_t scr = Lp == 64 ? 0 : (size_t)waves * 256;
+  const size_t f2 = 3 * (size_t)Lp * pt + (size_t)Lp * 17 + 2 * (size_t)Lp * P + scr;
   const size_t fl = 7 * (size_t)NT + 2 * Lb * NT + (size_t)waves;
   return f2 * sizeof(float2) + fl * 4;
 }
@@ -1128,8 +1130,17 @@ __device__ __forceinline__ void psca_back_body(const BackArgs &Bk, const int g) 
   float2 *Dt = Cf + Lp * PT;           // [Lp][kPB] SigmaHat B of one 16-column block
   float2 *WS = Dt + Lp * kPB;          // [Lp][P] Sigma^-1, then G_a
   float2 *ShL = WS + Lp * P;           // [Lp][P] SigmaHat, then G_b
-  float2 *scr = ShL + Lp * P;          // [kWaves][256]
-  float *xs = (float *)(scr + kWaves * 256);
+  // [kWaves][256] scratch of the first reduction and the factorisation.  At
+  // Lp = 64 it lives in the B and C tiles, which are first written after the
+  // factorisation (2 Lp PT >= kWaves 256 for PT >= 17), and the two Gram
+  // reductions, while B and C are live, use Dt (Lp kPB float2 >= THREADS
+  // double2), which is dead after the tile products: this frees the 16 KiB
+  // that let the tile grow to 48 columns.
+  constexpr bool kShareScr = LP == 64;
+  static_assert(!kShareScr || (2 * LP * 17 >= kWaves * 256 && LP * kPB * 8 >= THREADS * 16), "scratch fits");
+  float2 *scr = kShareScr ? Bf : ShL + Lp * P;
+  double2 *gscr = (double2 *)(kShareScr ? Dt : scr);
+  float *xs = (float *)(ShL + Lp * P + (kShareScr ? 0 : kWaves * 256));
   float *gs = xs + NT, *ls = gs + NT, *vs = ls + NT, *aw = vs + NT, *bw = aw + NT, *dxo = bw + NT;
   float *red_q = dxo + NT;             // [Lb][NT]
   float *red_r = red_q + Lb * NT;      // [Lb][NT]
@@ -1267,9 +1278,9 @@ __device__ __forceinline__ void psca_back_body(const BackArgs &Bk, const int g) 
     tile_gram<Lp, THREADS>(St, PT, A.ncb, aw, A.partials + (size_t)g * A.pstride);
     tile_gram<Lp, THREADS>(St, PT, A.ncb, bw, Bk.partials_b + (size_t)g * A.pstride);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
-    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, Bk.gram_a, (double2 *)scr, false, A.L, 0.0f);
+    reduce_slice<Lp, THREADS>(A.partials, A.pstride, A.G, g, Bk.gram_a, gscr, false, A.L, 0.0f);
     __syncthreads();
-    reduce_slice<Lp, THREADS>(Bk.partials_b, A.pstride, A.G, g, Bk.gram_b, (double2 *)scr, false, A.L, 0.0f);
+    reduce_slice<Lp, THREADS>(Bk.partials_b, A.pstride, A.G, g, Bk.gram_b, gscr, false, A.L, 0.0f);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
     unpack_hermitian<Lp, THREADS>(Bk.gram_a, WS);
     unpack_hermitian<Lp, THREADS>(Bk.gram_b, ShL);
