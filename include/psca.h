@@ -60,7 +60,7 @@ typedef enum {
   PSCA_ENOTPD = -2,   /* Sigma not numerically positive definite (device) */
   PSCA_EHIP = -3,     /* a HIP runtime call failed */
   PSCA_ENOMEM = -4,   /* device allocation failed */
-  PSCA_ENOTSUP = -5,  /* size outside what this build supports (e.g. L > PSCA_MAX_L) */
+  PSCA_ENOTSUP = -5,  /* size outside what the library supports (e.g. L > PSCA_MAX_L) */
   PSCA_ESYNC = -6     /* a device-wide barrier timed out (device status word only) */
 } psca_status;
 

@@ -2936,7 +2936,7 @@ const char *psca_strerror(int code) {
     case PSCA_ENOTPD: return "covariance matrix not positive definite (Cholesky pivot <= 0 or not finite)";
     case PSCA_EHIP: return "HIP runtime error";
     case PSCA_ENOMEM: return "device memory allocation failed";
-    case PSCA_ENOTSUP: return "size not supported by this build";
+    case PSCA_ENOTSUP: return "size or configuration not supported by the library";
     case PSCA_ESYNC: return "device-wide barrier timed out (workgroups not co-resident)";
     default: return "unknown error";
   }
