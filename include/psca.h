@@ -230,7 +230,7 @@ int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *
 
 /* Autotuner for psca_detect_batch: times the batch with every candidate team
  * specification (uniform team sizes from the smallest feasible team to the
- * whole GPU, and mixed teams for 32-, 48- and 64-column tiles), each
+ * whole GPU, and mixed teams for tiles of 32, 48, ..., 128 columns), each
  * instance capped at tune_iters >= 1 and at 2 tune_iters iterations, and
  * keeps the one whose time extrapolated from those two runs to the batch's
  * largest iteration count is least, in the context, for batches with the
@@ -253,7 +253,7 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
  *        (rounded up to the next of 1, 2, 4, 6, 8, 12, 16, 24, 32, 48, ...:
  *        powers of two and their 1.5 multiples); instances of one team size
  *        share that size's teams, and each size gets teams in proportion to
- *        its work.  -team_size is 16, 32, 48 or 64;
+ *        its work.  -team_size is a multiple of 16 up to 128;
  *   0    the value psca_autotune_batch chose for this (L, N) list, else the
  *        default of psca_detect_batch.
  * Other values return PSCA_EINVAL.  psca_plan_team_size returns the plan's

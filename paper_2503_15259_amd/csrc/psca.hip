@@ -52,7 +52,7 @@ constexpr int kThreads = 256;                              // helper kernels
 constexpr int kBlk = 16;
 constexpr int kMaxL = PSCA_MAX_L;                          // 256 (above 96: the cooperative large-L kernel)
 constexpr int kMaxLdsL = 96;                               // largest L whose L x L matrix lives in LDS
-constexpr int kMaxNcb = 4;                                 // column blocks per workgroup
+constexpr int kMaxNcb = 8;                                 // column blocks per workgroup (LDS permitting)
 constexpr unsigned kSpinLimit = 1u << 20;                  // grid-barrier wait bound
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -2464,7 +2464,7 @@ size_t inst_ws_bytes(int Lp, int G, int N) {
          3 * align_up(sizeof(unsigned)) + align_up(2 * (size_t)N * sizeof(float));
 }
 
-// Largest column tile (multiple of 16, at most 64) whose LDS fits a workgroup.
+// Largest column tile (multiple of 16, at most 16 kMaxNcb) whose LDS fits a workgroup.
 int max_tile(int Lp) {
   for (int ncb = kMaxNcb; ncb >= 1; --ncb)
     if (lds_bytes(Lp, 16 * ncb, kBatchThreads / 64) <= kMaxLds) return 16 * ncb;
@@ -3085,7 +3085,8 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   const int cap = batch_capacity(ctx);
   const int T0 = min_team(B, problems);
   if (cap <= 0 || T0 < 0 || T0 > cap) return PSCA_ENOTSUP;
-  std::vector<int> cand = {T0, default_team(B, problems, cap), -32, -48, -64};   // < 0: mixed teams
+  std::vector<int> cand = {T0, default_team(B, problems, cap)};
+  for (int c = 32; c <= 16 * kMaxNcb; c += 16) cand.push_back(-c);   // mixed teams
   for (int t : {8, 16, 24, 32, 48, 64, 96, 128, 192, 256})
     if (t >= T0 && t <= cap) cand.push_back(t);
   if ((long long)B * T0 <= cap) cand.push_back(cap / B);

@@ -285,8 +285,8 @@ class Plan:
     """psca_plan: a batch planned once and launched many times (launches may be
     captured into a CUDA/HIP graph).  Keep the problems' tensors alive.
     team_size: > 0 uniform teams of that many workgroups; < 0 mixed teams,
-    each instance's team sized for tiles of -team_size columns (-32, -48,
-    -64); 0 the autotuned choice, else the default."""
+    each instance's team sized for tiles of -team_size columns (a multiple
+    of 16 up to 128); 0 the autotuned choice, else the default."""
 
     def __init__(self, problems, team_size: int = 0, ctx: Optional[Context] = None):
         self.ctx = ctx or default_context(problems[0].S.device)

@@ -265,7 +265,7 @@ def test_batch_validation_and_empty(P):
                         P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=bad)])
     assert e.value.code == -1
     good = [P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, O.ML_UD, 5))]
-    for spec in (-7, -80, -1, 100000):   # mixed specs are multiples of 16 up to 64 columns
+    for spec in (-7, -144, -1, 100000):   # mixed specs are multiples of 16 up to 128 columns
         with pytest.raises(P.PscaError) as e:
             P.Plan(good, team_size=spec)
         assert e.value.code == -1, spec
