@@ -246,6 +246,7 @@ def run_uneven(args):
     }
     print(json.dumps(line), flush=True)
     plan.close()
+    ctx.close()
 
 
 # ---------------------------------------------------------------------------
@@ -352,6 +353,7 @@ def run_large(args):
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+    ctx.close()
 
 
 # ---------------------------------------------------------------------------
@@ -462,6 +464,7 @@ def run_net(args):
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+    ctx.close()
 
 
 # ---------------------------------------------------------------------------
@@ -528,6 +531,7 @@ def run_train(args):
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+    ctx.close()
 
 
 # ---------------------------------------------------------------------------
@@ -765,7 +769,15 @@ def main():
     print(json.dumps(line), flush=True)
     for pl in plans:
         pl.close()
+    ctx.close()
 
 
 if __name__ == "__main__":
     main()
+    try:   # release torch's cached blocks while the runtime is up
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+    except ImportError:
+        pass

@@ -86,11 +86,12 @@ typedef enum {
  *   g          DEVICE [N] known pathloss, > 0; required by ML-K and MAP-K.
  *   p          DEVICE [N] activity probabilities in (0, 1); required by MAP-K.
  *   d_lo, d_hi, pl_c0, pl_beta, eps   MAP-UR prior (Sec. II eqs. dispdf, gn,
- *              pg, pgamma, peps): devices area-uniform on the annulus
- *              [d_lo, d_hi] (0 < d_lo < d_hi), pathloss map phi(d) = pl_c0 *
- *              d^-pl_beta (pl_c0 > 0, pl_beta > 0), Hermite width eps with
- *              0 < eps and 2 eps < g_l = phi(d_hi).  The gradient's prior term
- *              p^eps'/p^eps does not depend on the activity probability.
+ *              pg, pgamma, peps): device distances on [d_lo, d_hi]
+ *              (0 < d_lo < d_hi) with the law `dist_law`, pathloss map
+ *              phi(d) = pl_c0 * d^-pl_beta (pl_c0 > 0, pl_beta > 0), Hermite
+ *              width eps with 0 < eps and 2 eps < g_l = phi(d_hi).  The
+ *              gradient's prior term p^eps'/p^eps does not depend on the
+ *              activity probability.
  *   c1, c2_ptr, c2_col, c2_val, c2_nnz   MAP-K2 prior (eq. second): DEVICE
  *              [N] first-order coefficients c_n, and the symmetric pairwise
  *              coefficients c_{n,n'} (zero diagonal) as CSR: row pointers
@@ -100,6 +101,11 @@ typedef enum {
  *              outside [0, c2_nnz) and columns outside [0, N) are skipped on
  *              the device.  Required by MAP-K2 (with g); ignored otherwise, but
  *              must then be zero-initialised by callers that build the struct.
+ *   dist_law   MAP-UR distance law behind the pathloss density p_G (eq. pg):
+ *              PSCA_DIST_AREA (0): area-uniform on the annulus, p_D(d) =
+ *              2d / (d_hi^2 - d_lo^2) (eq. dispdf, the paper's model);
+ *              PSCA_DIST_LINEAR (1): uniform in d, p_D(d) = 1 / (d_hi - d_lo).
+ *              Other values return PSCA_EINVAL for MAP-UR; ignored otherwise.
  */
 typedef struct {
   int32_t variant;
@@ -117,7 +123,11 @@ typedef struct {
   const int32_t *c2_col;
   const float *c2_val;
   int32_t c2_nnz;
+  int32_t dist_law;
 } psca_params;
+
+/* Values of psca_params.dist_law. */
+enum { PSCA_DIST_AREA = 0, PSCA_DIST_LINEAR = 1 };
 
 typedef struct psca_ctx psca_ctx;
 

@@ -24,8 +24,11 @@ Readings where the paper is silent, ambiguous or garbled:
       junction slope at g_l.
   R3  Where p^eps = 0 (the gap [eps, g_l - eps], including its closed left
       end of the H2 piece), the prior term p^eps'/p^eps is taken as 0.
-  R4  Pathloss map phi(d) = c0 d^-beta (power law), distance law area-uniform
-      on the annulus [d_l, d_u] (eq. dispdf); one common annulus for all n.
+  R4  Pathloss map phi(d) = c0 d^-beta (power law); one common annulus
+      [d_l, d_u] for all n.  The distance law is area-uniform (eq. dispdf,
+      law 0) by default; law 1 is uniform in d, the law the synthetic
+      instances are drawn from.  The pathloss density is eq. pg's change of
+      variables p_G(x) = p_D(psi(x)) |psi'(x)| for either law.
   R5  Step sizes: rho_0 = 0.5, rho_{k+1} = rho_k (1 - 0.5 rho_k); the update
       at iteration k uses rho_k.  Fixed iteration count (no stopping rule).
   R6  Clip bounds are inclusive; K variants [0, 1], ML-UD [0, inf),
@@ -103,17 +106,22 @@ def quadratic_forms(S: np.ndarray, Sigma_inv: np.ndarray, Sigma_hat: np.ndarray)
 # eq. pepsd; Theorem 1)
 # ---------------------------------------------------------------------------
 
+AREA_UNIFORM, UNIFORM_IN_D = 0, 1   # distance laws (reading R4)
+
+
 @dataclass
 class PowerLawPrior:
     """Effective-pathloss prior for one device with phi(d) = c0 d^-beta,
-    distance area-uniform on [d_l, d_u], activity probability p and Hermite
-    smoothing width eps."""
+    distance on [d_l, d_u] with law `law` (AREA_UNIFORM: p_D(d) = 2d/D as
+    eq. dispdf; UNIFORM_IN_D: p_D(d) = 1/(d_u - d_l)), activity probability p
+    and Hermite smoothing width eps."""
     p: float
     d_l: float
     d_u: float
     c0: float
     beta: float
     eps: float
+    law: int = AREA_UNIFORM
 
     # psi = phi^-1 and its derivatives
     def psi(self, x):
@@ -137,8 +145,15 @@ class PowerLawPrior:
     def D(self):
         return self.d_u ** 2 - self.d_l ** 2
 
+    def dddpsi(self, x):
+        b = 1.0 / self.beta
+        return -b * (b + 1.0) * (b + 2.0) * self.psi(x) / x ** 3
+
     def p_G(self, x):
-        """Pathloss density on [g_l, g_u] (eq. pg)."""
+        """Pathloss density on [g_l, g_u] (eq. pg): p_D(psi(x)) |psi'(x)|,
+        psi decreasing."""
+        if self.law == UNIFORM_IN_D:
+            return -self.dpsi(x) / (self.d_u - self.d_l)
         return -2.0 * self.psi(x) * self.dpsi(x) / self.D
 
     def p_upsilon_cont(self, x):
@@ -147,15 +162,16 @@ class PowerLawPrior:
 
     def dp_upsilon_cont(self, x):
         """Derivative of the continuous part (fourth case of eq. pepsd)."""
+        if self.law == UNIFORM_IN_D:
+            return -self.p * self.ddpsi(x) / (self.d_u - self.d_l)
         return -2.0 * self.p / self.D * (self.dpsi(x) ** 2 + self.psi(x) * self.ddpsi(x))
 
     def ddp_upsilon_cont(self, x):
         """Second derivative of the continuous part (needs the third
         derivative of psi for the power law)."""
-        b = 1.0 / self.beta
-        psi = self.psi(x)
-        d3 = -b * (b + 1.0) * (b + 2.0) * psi / x ** 3
-        return -2.0 * self.p / self.D * (3.0 * self.dpsi(x) * self.ddpsi(x) + psi * d3)
+        if self.law == UNIFORM_IN_D:
+            return -self.p * self.dddpsi(x) / (self.d_u - self.d_l)
+        return -2.0 * self.p / self.D * (3.0 * self.dpsi(x) * self.ddpsi(x) + self.psi(x) * self.dddpsi(x))
 
     def H1(self, x):
         e = self.eps
@@ -170,7 +186,15 @@ class PowerLawPrior:
         return 6.0 * (1.0 - self.p) / e ** 3 * (2.0 * x - e)
 
     def _AB(self):
+        """The coefficients of eq. H2, written out at g_l = phi(d_u) (so
+        psi(g_l) = d_u).  Area-uniform law: as eq. H2 defines them.  Uniform
+        in d: the same construction with p_D = 1/(d_u - d_l).  Theorem 1
+        makes them p_Upsilon(g_l) and p_Upsilon'(g_l); the junction pins
+        check that against the density functions above."""
         gl = self.g_l
+        if self.law == UNIFORM_IN_D:
+            w = self.d_u - self.d_l
+            return -self.p / w * self.dpsi(gl), -self.p / w * self.ddpsi(gl)
         A = -2.0 * self.p * self.d_u / self.D * self.dpsi(gl)
         B = -2.0 * self.p / self.D * (self.dpsi(gl) ** 2 + self.ddpsi(gl) * self.d_u)
         return A, B
@@ -254,9 +278,9 @@ class PowerLawPrior:
         return self.dp_eps(x) / pe
 
 
-def make_prior(p, d_l, d_u, c0, beta, eps) -> PowerLawPrior:
+def make_prior(p, d_l, d_u, c0, beta, eps, law: int = AREA_UNIFORM) -> PowerLawPrior:
     return PowerLawPrior(p=float(p), d_l=float(d_l), d_u=float(d_u), c0=float(c0),
-                         beta=float(beta), eps=float(eps))
+                         beta=float(beta), eps=float(eps), law=int(law))
 
 
 # ---------------------------------------------------------------------------
@@ -405,9 +429,40 @@ def psca(prob: Problem, iters: int, rho=None, record: bool = False):
     return (x, hist) if record else x
 
 
-def problem_from_instance(inst, variant: int, eps: float = 0.01) -> Problem:
+def bcd(prob: Problem, sweeps: int) -> np.ndarray:
+    """Block coordinate descent from x = 0 (the sequential counterpart of
+    PSCA: the BCD-ML-K listing of Sec. III-A, Algorithm 2, which Sec. IV-A
+    carries over to gamma as BCD-ML-UD).  Each sweep visits n = 0..N-1 in
+    order; device n takes the clipped coordinate step of eq. Solution_ML
+    (Solution_ML_U) computed from the current inverse, x_n <- clip(x_n -
+    grad_n / curv_n), and the inverse follows the change by the
+    Sherman-Morrison (Woodbury) rank-one update.  ML-K and ML-UD only: there
+    the step is the exact coordinate minimiser (the remark after Lemma 1)."""
+    if prob.variant not in (ML_K, ML_UD):
+        raise ValueError("bcd covers ML-K and ML-UD")
+    N, L = prob.N, prob.S.shape[0]
+    kappa = prob.g if prob.variant == ML_K else np.ones(N)
+    lo, hi = prob.bounds()
+    x = np.zeros(N)
+    Si = np.eye(L) / prob.sigma2
+    for _ in range(sweeps):
+        for n in range(N):
+            s = prob.S[:, n]
+            b = Si @ s
+            q = float(np.real(s.conj() @ b))
+            r = float(np.real(b.conj() @ prob.Sigma_hat @ b))
+            x_new = min(max(x[n] - kappa[n] * (q - r) / (kappa[n] * q) ** 2, lo), hi)
+            d = (x_new - x[n]) * kappa[n]
+            if d != 0.0:
+                Si = Si - d * np.outer(b, b.conj()) / (1.0 + d * q)
+            x[n] = x_new
+    return x
+
+
+def problem_from_instance(inst, variant: int, eps: float = 0.01, law: int = AREA_UNIFORM) -> Problem:
     """Wrap a generated instance (fields S, Y, g, p, sigma2, d_lo, d_hi,
-    pl_c0, pl_beta) as an oracle Problem; SigmaHat is formed here."""
+    pl_c0, pl_beta) as an oracle Problem; SigmaHat is formed here.  `law` is
+    the MAP-UR prior's distance law (reading R4)."""
     Sh = sample_covariance(inst.Y)
     N = inst.S.shape[1]
     kw = dict(Sigma_hat=Sh, S=np.asarray(inst.S, np.complex128), sigma2=float(inst.sigma2),
@@ -417,7 +472,7 @@ def problem_from_instance(inst, variant: int, eps: float = 0.01) -> Problem:
     if variant == MAP_K:
         kw["p"] = np.full(N, float(inst.p))
     if variant == MAP_UR:
-        kw["prior"] = make_prior(inst.p, inst.d_lo, inst.d_hi, inst.pl_c0, inst.pl_beta, eps)
+        kw["prior"] = make_prior(inst.p, inst.d_lo, inst.d_hi, inst.pl_c0, inst.pl_beta, eps, law)
     if variant == MAP_K2:
         kw["c1"], kw["C2"] = pairwise_prior(N, inst.c_single, *inst.pair_csr())
     return Problem(**kw)

@@ -18,6 +18,7 @@ PSCA_ENOTSUP = -5
 PSCA_ESYNC = -6
 
 ML_K, MAP_K, ML_UD, MAP_UR, MAP_K2 = 0, 1, 2, 3, 4
+DIST_AREA, DIST_LINEAR = 0, 1   # psca_params.dist_law
 MAX_L = 256
 
 # every symbol include/psca.h declares
@@ -50,6 +51,7 @@ class PscaParams(ctypes.Structure):
         ("c2_col", ctypes.c_void_p),
         ("c2_val", ctypes.c_void_p),
         ("c2_nnz", ctypes.c_int32),
+        ("dist_law", ctypes.c_int32),
     ]
 
 

@@ -2114,6 +2114,7 @@ int validate_params(const psca_params *prm, int L, int N, bool need_iters) {
       return PSCA_EINVAL;
     const double gl = (double)prm->pl_c0 * pow((double)prm->d_hi, -(double)prm->pl_beta);
     if (!(2.0 * (double)prm->eps < gl)) return PSCA_EINVAL;
+    if (prm->dist_law != PSCA_DIST_AREA && prm->dist_law != PSCA_DIST_LINEAR) return PSCA_EINVAL;
   }
   return PSCA_OK;
 }
@@ -2139,8 +2140,15 @@ StepArgs make_step_args(const psca_params *prm) {
     a.eps = prm->eps;
     a.g_l = (float)gl;
     a.g_u = (float)gu;
-    a.dens_c = (float)(2.0 / beta + 1.0);
-    a.h2_b = (float)(-(2.0 / beta + 1.0) / gl);
+    // On the density piece p_G is p_D(psi) |psi'| with psi = phi^-1 =
+    // (c0 / x)^(1/beta), so p'/p = psi''/psi' + (p_D'/p_D)(psi) psi':
+    //   area-uniform (p_D ~ d):  -(1/beta + 1)/x - 1/(beta x) = -(2/beta + 1)/x;
+    //   uniform in d (p_D const): -(1/beta + 1)/x.
+    // H2's coefficient ratio B/A = p_Upsilon'(g_l)/p_Upsilon(g_l) is that same
+    // log-derivative at g_l.
+    const double c = (prm->dist_law == PSCA_DIST_LINEAR ? 1.0 : 2.0) / beta + 1.0;
+    a.dens_c = (float)c;
+    a.h2_b = (float)(-c / gl);
   }
   return a;
 }

@@ -32,31 +32,59 @@ def schedule(K: int, rho0: float = 0.5, decay: float = 0.5) -> list:
     return out
 
 
+class StatusLog:
+    """Device status words of the launches behind one training step (forward
+    and backward).  Every launch writes its own words; check() reads them
+    all back at once and raises on any non-zero code (PSCA_ENOTPD: a
+    factorisation failed and that instance's iterates stopped advancing;
+    PSCA_ESYNC: a device-wide wait gave up), so no optimiser step is taken
+    on results the device has flagged."""
+
+    def __init__(self):
+        self.words = []
+
+    def new(self, n: int, device) -> torch.Tensor:
+        w = torch.zeros(n, dtype=torch.int32, device=device)
+        self.words.append(w)
+        return w
+
+    def check(self):
+        if not self.words:
+            return
+        bad = torch.cat(self.words)
+        self.words = []
+        codes = sorted({int(c) for c in bad[bad != 0].tolist()})
+        if codes:
+            raise P.PscaError(codes[0], "unrolled network: device status " + ", ".join(map(str, codes)))
+
+
 class _Unrolled(torch.autograd.Function):
     """x^(K) of the unrolled network as a function of the step sizes."""
 
     @staticmethod
-    def forward(fctx, rhos, Sigma_hat, S, params, pctx):
+    def forward(fctx, rhos, Sigma_hat, S, params, pctx, log):
         rho_dev = rhos.detach().to(S.device, torch.float32).contiguous()
         prm = replace(params, iters=rhos.numel(), rho=rho_dev)
-        hist = P.net_forward(Sigma_hat, S, prm, ctx=pctx)
+        hist = P.net_forward(Sigma_hat, S, prm, ctx=pctx, status=log.new(1, S.device))
         fctx.save_for_backward(rho_dev.clone(), hist)
         fctx.rho_device = rhos.device
-        fctx.inputs = (Sigma_hat, S, params, pctx)
+        fctx.inputs = (Sigma_hat, S, params, pctx, log)
         return hist[-1].clone()
 
     @staticmethod
     def backward(fctx, grad_out):
         rhos, hist = fctx.saved_tensors
-        Sigma_hat, S, params, pctx = fctx.inputs
+        Sigma_hat, S, params, pctx, log = fctx.inputs
         host_rhos = rhos.cpu().tolist()
         v = grad_out.contiguous().float()
         grads = []
+        status = log.new(len(host_rhos), S.device)   # one word per layer launch
         for k in range(len(host_rhos) - 1, -1, -1):
-            v, g = P.layer_backward(Sigma_hat, S, params, float(host_rhos[k]), hist[k].contiguous(), v, ctx=pctx)
+            v, g = P.layer_backward(Sigma_hat, S, params, float(host_rhos[k]), hist[k].contiguous(), v, ctx=pctx,
+                                    status=status[k:k + 1])
             grads.append(g)
         d_rho = torch.cat(grads[::-1]).to(fctx.rho_device)
-        return d_rho, None, None, None, None
+        return d_rho, None, None, None, None, None
 
 
 class _UnrolledBatch(torch.autograd.Function):
@@ -66,15 +94,18 @@ class _UnrolledBatch(torch.autograd.Function):
     launch per layer (psca_layer_backward_batch)."""
 
     @staticmethod
-    def forward(fctx, rhos, items, pctx):
+    def forward(fctx, rhos, items, pctx, log):
         K = rhos.numel()
         dev = items[0][1].device
         rho_dev = rhos.detach().to(dev, torch.float32).contiguous()
+        status = log.new(len(items), dev)
         probs = []
-        for Sh, S, params in items:
+        for b, (Sh, S, params) in enumerate(items):
             hist = torch.empty((K + 1, S.shape[1]), dtype=torch.float32, device=dev)
-            probs.append(P.Problem(Sigma_hat=Sh, S=S, params=replace(params, iters=K, rho=rho_dev), hist=hist))
+            probs.append(P.Problem(Sigma_hat=Sh, S=S, params=replace(params, iters=K, rho=rho_dev), hist=hist,
+                                   status=status[b:b + 1]))
         P.detect_batch(probs, ctx=pctx)
+        fctx.log = log
         fctx.hists = [pb.hist for pb in probs]
         fctx.sizes = [pb.hist.shape[1] for pb in probs]
         fctx.host_rhos = rhos.detach().float().cpu().tolist()   # the FP32 values the kernels use
@@ -90,12 +121,17 @@ class _UnrolledBatch(torch.autograd.Function):
             grad = torch.zeros(sum(fctx.sizes), dtype=torch.float32, device=fctx.hists[0].device)
         vs = list(grad.contiguous().float().split(fctx.sizes))   # contiguous pieces
         grads = []
+        K = len(host_rhos)
+        # one status word per instance and layer: a layer's launch writes
+        # every instance's word, so each layer gets its own
+        status = fctx.log.new(K * len(fctx.items), fctx.hists[0].device).view(K, -1)
         bb = P.BackBatch(fctx.items, ctx=fctx.pctx)
-        for k in range(len(host_rhos) - 1, -1, -1):
+        for k in range(K - 1, -1, -1):
+            bb.set_status(status[k])
             vs, gr = bb.run([h[k] for h in fctx.hists], vs, float(host_rhos[k]))
             grads.append(gr.sum().reshape(1))
         d_rho = torch.cat(grads[::-1]).to(fctx.rho_device)
-        return d_rho, None, None
+        return d_rho, None, None, None
 
 
 def bce_terms(x: torch.Tensor, alpha: torch.Tensor, g: Optional[torch.Tensor], known: bool,
@@ -137,6 +173,7 @@ class PscaNet(torch.nn.Module):
         self.ctx = ctx
         self.rho = torch.nn.Parameter(torch.tensor(schedule(K), dtype=torch.float32))
         self.theta = 0.5
+        self.status = StatusLog()
 
     @property
     def known(self) -> bool:
@@ -144,12 +181,13 @@ class PscaNet(torch.nn.Module):
 
     def forward(self, Sigma_hat: torch.Tensor, S: torch.Tensor, params: Optional[P.Params] = None):
         prm = params or self.params
-        return _Unrolled.apply(self.rho, Sigma_hat, S, prm, self.ctx or P.default_context(S.device))
+        return _Unrolled.apply(self.rho, Sigma_hat, S, prm, self.ctx or P.default_context(S.device), self.status)
 
     def forward_batch_cat(self, items) -> torch.Tensor:
         """x^(K) of every (Sigma_hat, S, params) of a minibatch, concatenated
         in order, in batched launches."""
-        return _UnrolledBatch.apply(self.rho, list(items), self.ctx or P.default_context(items[0][1].device))
+        return _UnrolledBatch.apply(self.rho, list(items), self.ctx or P.default_context(items[0][1].device),
+                                    self.status)
 
     def forward_batch(self, items):
         """x^(K) of every (Sigma_hat, S, params) of a minibatch, one tensor per
@@ -180,6 +218,7 @@ def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch, batched: bool = 
             loss = bce(x, alpha, g, net.known) / len(batch)
             loss.backward()
             total = loss.detach() if total is None else total + loss.detach()
+    net.status.check()   # raises before the optimiser step if any launch flagged an instance
     opt.step()
     net.project()
     return float(total) if total is not None else 0.0

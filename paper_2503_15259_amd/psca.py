@@ -8,14 +8,16 @@ produces that layout (a no-op for a tensor that already has it).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
 from dataclasses import dataclass
 from typing import Optional
 
 import torch
 
 from . import _native as N
-from ._native import ML_K, MAP_K, ML_UD, MAP_UR, MAP_K2, MAX_L, PscaError  # noqa: F401
+from ._native import ML_K, MAP_K, ML_UD, MAP_UR, MAP_K2, MAX_L, DIST_AREA, DIST_LINEAR, PscaError  # noqa: F401
 
 VARIANTS = {"ML-K": ML_K, "MAP-K": MAP_K, "ML-UD": ML_UD, "MAP-UR": MAP_UR, "MAP-K2": MAP_K2}
 
@@ -36,6 +38,20 @@ def _ptr(t: Optional[torch.Tensor]):
 def _stream(device: torch.device, stream=None) -> ctypes.c_void_p:
     s = torch.cuda.current_stream(device) if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _on_stream(device: torch.device, stream, temporaries) -> None:
+    """Before a launch on a caller-given `stream`: order it after the work
+    torch queued on the current stream (the column-major copies the call may
+    have made there), and tell the caching allocator that those copies are
+    in use on `stream` until its work is done."""
+    if stream is None:
+        return
+    cur = torch.cuda.current_stream(device)
+    if stream != cur:
+        stream.wait_stream(cur)
+    for t in temporaries:
+        t.record_stream(stream)
 
 
 def _need(t: torch.Tensor, dtype, device, name):
@@ -60,6 +76,10 @@ class Context:
             self.handle = None
 
     def __del__(self):
+        # no HIP calls while the interpreter shuts down: the runtime (or a
+        # profiler attached to it) may already be finalising
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -67,6 +87,17 @@ class Context:
 
 
 _default_ctx = {}
+
+
+@atexit.register
+def _close_default_contexts():
+    """Free the default contexts while the HIP runtime is still up."""
+    for c in list(_default_ctx.values()):
+        try:
+            c.close()
+        except Exception:
+            pass
+    _default_ctx.clear()
 
 
 def default_context(device=None) -> Context:
@@ -94,6 +125,7 @@ class Params:
     pl_c0: float = 10.0 ** 0.89
     pl_beta: float = 3.76
     eps: float = 0.01
+    dist_law: int = 0   # MAP-UR distance law: 0 area-uniform (eq. dispdf), 1 uniform in d
     # MAP-K2: first-order coefficients [N] and the pairwise coefficients as
     # CSR (row pointers [N+1] int32, columns [nnz] int32, values [nnz] float32)
     c1: Optional[torch.Tensor] = None
@@ -119,6 +151,7 @@ class Params:
         c.c2_col = None if self.c2_col is None else self.c2_col.data_ptr()
         c.c2_val = None if self.c2_val is None else self.c2_val.data_ptr()
         c.c2_nnz = 0 if self.c2_col is None else int(self.c2_col.numel())
+        c.dist_law = int(self.dist_law)
         return c
 
     def check_tensors(self, device, n):
@@ -186,6 +219,7 @@ def detect(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: Option
     params.check_tensors(ctx.device, n)
     x = torch.empty(n, dtype=torch.float32, device=ctx.device) if out is None else out
     c = params.to_c()
+    _on_stream(ctx.device, stream, (Sigma_hat, S))
     N.check(ctx._lib.psca_detect(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c), _ptr(x),
                                  _ptr(status), _stream(ctx.device, stream)), "psca_detect")
     return x
@@ -205,6 +239,7 @@ def detect_y(Y: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Con
     params.check_tensors(ctx.device, n)
     x = torch.empty(n, dtype=torch.float32, device=ctx.device) if out is None else out
     c = params.to_c()
+    _on_stream(ctx.device, stream, (Y, S))
     N.check(ctx._lib.psca_detect_y(ctx.handle, _ptr(Y), _ptr(S), L, n, ctypes.byref(c), _ptr(x),
                                    _ptr(status), _stream(ctx.device, stream)), "psca_detect_y")
     return x
@@ -264,7 +299,8 @@ def detect_batch(problems, ctx: Optional[Context] = None, stream=None):
     if not problems:
         return []
     ctx = ctx or default_context(problems[0].S.device)
-    arr, outs, _keep = _problem_array(problems, ctx)
+    arr, outs, keep = _problem_array(problems, ctx)
+    _on_stream(ctx.device, stream, keep)
     N.check(ctx._lib.psca_detect_batch(ctx.handle, len(problems), arr, _stream(ctx.device, stream)),
             "psca_detect_batch")
     return outs
@@ -274,7 +310,8 @@ def autotune_batch(problems, tune_iters: int = 4, ctx: Optional[Context] = None,
     """psca_autotune_batch: times the candidate team sizes for this batch and
     remembers the fastest in the context.  Returns the chosen team size."""
     ctx = ctx or default_context(problems[0].S.device)
-    arr, _outs, _keep = _problem_array(problems, ctx)
+    arr, _outs, keep = _problem_array(problems, ctx)
+    _on_stream(ctx.device, stream, keep)
     t = ctypes.c_int(0)
     N.check(ctx._lib.psca_autotune_batch(ctx.handle, len(problems), arr, int(tune_iters), ctypes.byref(t),
                                          _stream(ctx.device, stream)), "psca_autotune_batch")
@@ -332,6 +369,7 @@ def iterate(Sigma_hat: torch.Tensor, S: torch.Tensor, x: torch.Tensor, rho: floa
     params.check_tensors(ctx.device, n)
     x_next, q, r, xt = (torch.empty(n, dtype=torch.float32, device=ctx.device) for _ in range(4))
     c = params.to_c()
+    _on_stream(ctx.device, stream, (Sigma_hat, S))
     N.check(ctx._lib.psca_iterate(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c),
                                   ctypes.c_float(rho), _ptr(x), _ptr(x_next), _ptr(q), _ptr(r), _ptr(xt),
                                   _ptr(status), _stream(ctx.device, stream)), "psca_iterate")
@@ -351,6 +389,7 @@ def net_forward(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: O
     params.check_tensors(ctx.device, n)
     hist = torch.empty((params.iters + 1, n), dtype=torch.float32, device=ctx.device)
     c = params.to_c()
+    _on_stream(ctx.device, stream, (Sigma_hat, S))
     N.check(ctx._lib.psca_net_forward(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c), _ptr(hist),
                                       _ptr(status), _stream(ctx.device, stream)), "psca_net_forward")
     return hist
@@ -375,6 +414,7 @@ def layer_backward(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, rho
     gx = torch.empty(n, dtype=torch.float32, device=ctx.device)
     gr = torch.empty(1, dtype=torch.float32, device=ctx.device)
     c = params.to_c()
+    _on_stream(ctx.device, stream, (Sigma_hat, S))
     N.check(ctx._lib.psca_layer_backward(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c),
                                          ctypes.c_float(rho), _ptr(x_in), _ptr(v), _ptr(gx), _ptr(gr),
                                          _ptr(status), _stream(ctx.device, stream)), "psca_layer_backward")
@@ -411,6 +451,15 @@ class BackBatch:
             e.grad_rho = self.gr.data_ptr() + 4 * k
             e.status = None if status is None else status[k].data_ptr()
 
+    def set_status(self, status):
+        """Point every instance's status word at status[k] (a device int32
+        tensor of B words), or at nothing when status is None."""
+        if status is not None and (status.dtype != torch.int32 or status.numel() < self.B):
+            raise ValueError("status must hold B int32 words")
+        for k in range(self.B):
+            self.arr[k].status = None if status is None else status[k].data_ptr()
+        self.status_words = status
+
     def run(self, x_ins, vs, rho: float, stream=None):
         """Returns ([dL/dx per instance], dL/drho per instance as a tensor [B])."""
         gxs, hold = [], []
@@ -425,6 +474,7 @@ class BackBatch:
             hold += [x_in, v]
             e = self.arr[k]
             e.x_in, e.v, e.grad_x = x_in.data_ptr(), v.data_ptr(), gx.data_ptr()
+        _on_stream(self.ctx.device, stream, self.keep)
         N.check(self.ctx._lib.psca_layer_backward_batch(self.ctx.handle, self.B, self.arr, ctypes.c_float(rho),
                                                         _stream(self.ctx.device, stream)),
                 "psca_layer_backward_batch")

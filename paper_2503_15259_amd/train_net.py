@@ -73,6 +73,7 @@ def main():
             tot = 0.0
             for Sh, S, prm, alpha, g in val:
                 tot += float(NET.bce(model(Sh, S, prm), alpha, g, model.known))
+            model.status.check()
             return tot / len(val)
 
     history = [{"step": 0, "val_loss": val_loss()}]
@@ -97,6 +98,7 @@ def main():
             x = model(Sh, S, prm)
             scores.append(x if model.known else x / g)
             truths.append(alpha)
+        model.status.check()
         theta = NET.choose_threshold(scores, truths)
     out = {"variant": args.variant, "K": args.K, "rho": [float(r) for r in model.rho.detach().cpu()],
            "best_step": best_step, "best_val_loss": best_val, "theta": theta, "threshold_on": "alpha~" if model.known else "gamma~/g",

@@ -53,3 +53,44 @@ def assert_same_support(x_gpu, x_ref, truth, variant, what=""):
         flips = (x_gpu >= th) != (x_ref >= th)
         n_flip = int(np.sum(flips & ~near))
         assert n_flip == 0, f"{what} {O.VARIANT_NAMES[variant]}: {n_flip} support flips at theta={th}"
+
+
+# MAP-UR devices whose iterates pass within this relative distance of a
+# branch point of p^eps (eps, g_l - eps, g_l) are not held to the element-wise
+# bar: the prior term has poles at the first two and a jump at the third, so
+# there an FP32 trajectory cannot follow the FP64 one (see branch_margin).
+BRANCH_DELTA = 1e-4
+
+
+def map_ur_device_parity(x_gpu, x_ref, margin, delta=BRANCH_DELTA):
+    """Element-wise MAP-UR parity on the devices whose oracle trajectory keeps
+    a relative distance >= delta from every branch point.  Returns the
+    report of the kept devices and the number excluded."""
+    keep = np.asarray(margin) >= delta
+    rep = parity_report(np.asarray(x_gpu)[keep], np.asarray(x_ref)[keep], O.MAP_UR)
+    rep["excluded"] = int((~keep).sum())
+    return rep
+
+
+def stepwise_parity(prob, hist_gpu, rhos, delta=BRANCH_DELTA):
+    """One oracle iteration from each GPU iterate x^(k) (rounded values taken
+    as exact) against the GPU's x^(k+1), element by element at the parity
+    bar.  MAP-UR devices whose x^(k) lies within delta (relative) of a branch
+    point of p^eps are skipped at that step.  Returns (worst report, total
+    skipped device-steps)."""
+    hist = np.asarray(hist_gpu, dtype=np.float64)
+    worst, skipped = None, 0
+    for k, rho in enumerate(rhos):
+        rec = O.psca_iteration(prob, hist[k], float(rho))
+        keep = np.ones(prob.N, dtype=bool)
+        if prob.variant == O.MAP_UR:
+            pr = prob.prior
+            pts = np.array([pr.eps, pr.g_l - pr.eps, pr.g_l])
+            d = np.min(np.abs(hist[k][:, None] - pts[None, :]) / pts[None, :], axis=1)
+            keep = d >= delta
+        skipped += int((~keep).sum())
+        rep = parity_report(hist[k + 1][keep], rec.x_next[keep], prob.variant)
+        rep["step"] = k
+        if worst is None or rep["n_bad"] > worst["n_bad"]:
+            worst = rep
+    return worst, skipped

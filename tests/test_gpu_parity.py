@@ -6,7 +6,8 @@ import pytest
 
 import oracle as O
 from paper_2503_15259_amd import instances as I
-from parity import assert_parity, assert_same_support
+from parity import (assert_parity, assert_same_support, map_ur_device_parity, parity_report,
+                    stepwise_parity)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -96,9 +97,15 @@ def test_iteration_from_a_mid_trajectory_point(P, variant):
     Sh = P.sample_cov(c64(inst.Y))
     xn, q, r, xt = P.iterate(Sh, c64(inst.S), f32(x15), rho, params_for(P, inst, variant, 1))
     torch.cuda.synchronize()
-    for name, got, ref in [("q", q, rec.q), ("r", r, rec.r)]:
-        got = got.cpu().numpy().astype(np.float64)
-        assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-3, name
+    q_gpu = q.cpu().numpy().astype(np.float64)
+    qmr_gpu = q_gpu - r.cpu().numpy().astype(np.float64)
+    qmr_ref = rec.q - rec.r
+    q_err = float(np.max(np.abs(q_gpu - rec.q) / np.abs(rec.q)))
+    # q - r nearly cancels near a stationary point, so its error is measured
+    # against q, the scale of the two terms it is the difference of
+    qmr_err = float(np.max(np.abs(qmr_gpu - qmr_ref) / np.abs(rec.q)))
+    print(f"{label(inst, variant, 1)} iterate 15: max rel err q {q_err:.2e}, (q - r) / q {qmr_err:.2e}", flush=True)
+    assert q_err < 1e-5 and qmr_err < 1e-5, (q_err, qmr_err)
     assert_parity(xn.cpu().numpy(), rec.x_next, variant, label(inst, variant, 1))
 
 
@@ -122,6 +129,72 @@ def test_detect_single_instance_workload(P, variant):
     got = run_gpu(P, inst, variant, iters)
     assert_parity(got, ref, variant, label(inst, variant, iters))
     assert_same_support(got, ref, inst.alpha, variant, label(inst, variant, iters))
+
+
+@pytest.mark.parametrize("workload,index", [("small", 0), ("single", 0)])
+def test_map_ur_with_the_uniform_in_distance_law(P, workload, index):
+    """MAP-UR with the prior built on the generator's own distance law
+    (uniform in d, dist_law = 1) against the oracle with the same law."""
+    inst = I.workload_instance(workload, index).fp32_inputs()
+    iters = 100
+    prob = O.problem_from_instance(inst, O.MAP_UR, eps=EPS, law=O.UNIFORM_IN_D)
+    ref, hist = O.psca(prob, iters, record=True)
+    prm = params_for(P, inst, O.MAP_UR, iters)
+    prm.dist_law = P.DIST_LINEAR
+    status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+    x = P.detect_y(c64(inst.Y), c64(inst.S), prm, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    rep = map_ur_device_parity(x.cpu().numpy(), ref, O.branch_margin(prob, hist))
+    print(f"MAP-UR uniform-in-d law {label(inst, O.MAP_UR, iters)}: {rep}", flush=True)
+    assert rep["n_bad"] == 0, rep
+    # the law changes the result (the prior's density piece differs)
+    ref_area = O.psca(O.problem_from_instance(inst, O.MAP_UR, eps=EPS), iters)
+    assert np.max(np.abs(ref_area - ref)) > 1e-3 * np.max(np.abs(ref))
+    bad = params_for(P, inst, O.MAP_UR, 5)
+    bad.dist_law = 2
+    with pytest.raises(P.PscaError) as e:
+        P.detect_y(c64(inst.Y), c64(inst.S), bad)
+    assert e.value.code == -1
+
+
+def test_map_ur_single_workload_every_device_outside_the_prior_poles(P):
+    """MAP-UR on instances 0-3 of the N=1000, L=64 workload (100 iterations).
+    Devices whose oracle trajectory passes within BRANCH_DELTA of a branch
+    point of p^eps are excluded (and counted); every other device meets the
+    element-wise bar.  Where the oracle itself is input-sensitive (its
+    result moves beyond the bar when only its inputs are rounded to FP32:
+    a pole crossing there perturbs every other device through Sigma), the
+    whole trajectory is held step by step instead: one oracle iteration
+    from each recorded GPU iterate against the GPU's next iterate, on every
+    device not within BRANCH_DELTA of a branch point at that step."""
+    iters = 100
+    rhos = O.step_sizes(iters)
+    for idx in range(4):
+        inst64 = I.workload_instance("single", idx)
+        inst = inst64.fp32_inputs()
+        prob = O.problem_from_instance(inst, O.MAP_UR, eps=EPS)
+        ref, hist = O.psca(prob, iters, record=True)
+        margin = O.branch_margin(prob, hist)
+        ref64 = O.psca(O.problem_from_instance(inst64, O.MAP_UR, eps=EPS), iters)
+        shift = parity_report(ref64, ref, O.MAP_UR)
+        Sh = P.sample_cov(c64(inst.Y))
+        status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+        hist_gpu = P.net_forward(Sh, c64(inst.S), params_for(P, inst, O.MAP_UR, iters), status=status)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        hist_gpu = hist_gpu.cpu().numpy()
+        got = hist_gpu[-1].astype(np.float64)
+        rep = map_ur_device_parity(got, ref, margin)
+        sensitive = shift["n_bad"] > 0
+        print(f"MAP-UR single instance {idx}: {rep['excluded']} devices near a branch point; "
+              f"input-sensitive {sensitive}; {rep}", flush=True)
+        if not sensitive:
+            assert rep["n_bad"] == 0, (idx, rep)
+            assert_same_support(got, ref, inst.alpha, O.MAP_UR, f"MAP-UR instance {idx}")
+        worst, skipped = stepwise_parity(prob, hist_gpu, rhos)
+        print(f"  step by step: {skipped} device-steps skipped near a branch point; worst {worst}", flush=True)
+        assert worst["n_bad"] == 0, (idx, worst)
 
 
 @pytest.mark.parametrize("N,L,M", [(1, 1, 4), (1, 8, 16), (65, 13, 9), (129, 3, 40), (200, 96, 64),
@@ -296,7 +369,7 @@ def test_uneven_batch_matches_oracle_for_every_team_size(P):
     results = {"default": [x.cpu().numpy().astype(np.float64) for x in outs]}
     for pb in probs:
         assert int(pb.status.item()) == 0
-    for T in (32, 80, -32, -64):
+    for T in (32, 80, -32, -64, -96, -112, -128):
         for pb in probs:
             pb.out = None
         plan = P.Plan(probs, team_size=T)
@@ -309,6 +382,33 @@ def test_uneven_batch_matches_oracle_for_every_team_size(P):
     for key, xs in results.items():
         for inst, x, ref in zip(insts, xs, refs):
             assert_parity(x, ref, O.ML_UD, f"team={key} " + label(inst, O.ML_UD, 20))
+
+
+def test_forward_batch_on_112_column_tiles(P):
+    """The training forward's launch shape: N = 1000, L = 64 on a team of 9
+    workgroups, i.e. 112-column tiles (seven 16-column blocks per
+    workgroup), every recorded iterate of ML-K and MAP-UR against the
+    oracle's trajectory."""
+    inst = I.workload_instance("single", 1).fp32_inputs()
+    iters = 20
+    Sh = P.sample_cov(c64(inst.Y))
+    for variant in (O.ML_K, O.MAP_UR):
+        hist = torch.empty((iters + 1, inst.N), dtype=torch.float32, device=dev())
+        status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+        pb = P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, variant, iters), hist=hist,
+                       status=status)
+        plan = P.Plan([pb], team_size=9)
+        assert plan.team_size == 9
+        print(f"[112-column tiles: {label(inst, variant, iters)}]", flush=True)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        _, recs = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters, record=True)
+        h = hist.cpu().numpy().astype(np.float64)
+        for k, rec in enumerate(recs):
+            assert_parity(h[k + 1], rec.x_next, variant, f"112-column tiles, iterate {k + 1} " +
+                          label(inst, variant, iters))
+        plan.close()
 
 
 def test_uneven_full_batch_sampled_against_oracle(P):
@@ -381,7 +481,7 @@ def test_plan_replays_inside_a_captured_graph(P):
 def test_autotuner_choice_is_used_and_exact(P):
     probs, refs, insts = _uneven_batch(P, 5, 12)
     T = P.autotune_batch(probs, tune_iters=2)
-    assert 1 <= T <= 256 or T in (-32, -48, -64)
+    assert 1 <= T <= 256 or (T < 0 and -T % 16 == 0 and -T <= 128), T
     for pb in probs:
         pb.out = None
     outs = P.detect_batch(probs)

@@ -316,23 +316,33 @@ def test_brute_force_support_on_tiny_instances(variant):
 # ---------------------------------------------------------------------------
 
 PRIOR = O.make_prior(0.1, I.D_LO_KM, I.D_HI_KM, I.PL_C0, I.PL_BETA, 0.5)
+PRIORS = {law: O.make_prior(0.1, I.D_LO_KM, I.D_HI_KM, I.PL_C0, I.PL_BETA, 0.5, law)
+          for law in (O.AREA_UNIFORM, O.UNIFORM_IN_D)}
+LAWS = sorted(PRIORS)
 
 
-def test_pathloss_density_integrates_to_one_and_matches_cdf():
-    pr = PRIOR
+@pytest.mark.parametrize("law", LAWS)
+def test_pathloss_density_integrates_to_one_and_matches_cdf(law):
+    pr = PRIORS[law]
     tot, _ = integrate.quad(pr.p_G, pr.g_l, pr.g_u, limit=400, points=[2 * pr.g_l, 10 * pr.g_l])
     assert abs(tot - 1) < 1e-8
-    # P[G <= g] = P[D >= psi(g)] = (d_u^2 - psi(g)^2) / (d_u^2 - d_l^2) for area-uniform D
+    # P[G <= g] = P[D >= psi(g)]: (d_u^2 - psi(g)^2) / (d_u^2 - d_l^2) for
+    # area-uniform D, (d_u - psi(g)) / (d_u - d_l) for D uniform in d
     for gg in [1.5 * pr.g_l, 7 * pr.g_l, 0.3 * pr.g_u]:
         cdf, _ = integrate.quad(pr.p_G, pr.g_l, gg, limit=400)
         d = (pr.c0 / gg) ** (1 / pr.beta)
-        assert abs(cdf - (pr.d_u ** 2 - d ** 2) / pr.D) < 1e-8
+        want = (pr.d_u ** 2 - d ** 2) / pr.D if law == O.AREA_UNIFORM else (pr.d_u - d) / (pr.d_u - pr.d_l)
+        assert abs(cdf - want) < 1e-8
 
 
-def test_pathloss_density_matches_monte_carlo():
-    pr = PRIOR
+@pytest.mark.parametrize("law", LAWS)
+def test_pathloss_density_matches_monte_carlo(law):
+    pr = PRIORS[law]
     rng = np.random.default_rng(11)
-    d = np.sqrt(rng.uniform(pr.d_l ** 2, pr.d_u ** 2, 400000))   # area-uniform
+    if law == O.AREA_UNIFORM:
+        d = np.sqrt(rng.uniform(pr.d_l ** 2, pr.d_u ** 2, 400000))
+    else:   # the synthetic instances' law
+        d = rng.uniform(pr.d_l, pr.d_u, 400000)
     gs = pr.c0 * d ** (-pr.beta)
     edges = np.array([pr.g_l, 2 * pr.g_l, 5 * pr.g_l, 30 * pr.g_l, pr.g_u])
     hist = np.histogram(gs, edges)[0] / len(gs)
@@ -340,8 +350,18 @@ def test_pathloss_density_matches_monte_carlo():
     assert np.allclose(hist, mass, atol=3e-3)
 
 
-def test_theorem1_junction_values_and_slopes():
-    pr = PRIOR
+def test_distance_laws_differ():
+    """The two laws put different mass near g_l (far devices): the prior and
+    the generator disagree unless the uniform-in-d law is selected."""
+    a, b = PRIORS[O.AREA_UNIFORM], PRIORS[O.UNIFORM_IN_D]
+    ma = integrate.quad(a.p_G, a.g_l, 2 * a.g_l)[0]
+    mb = integrate.quad(b.p_G, b.g_l, 2 * b.g_l)[0]
+    assert ma > mb + 0.05
+
+
+@pytest.mark.parametrize("law", LAWS)
+def test_theorem1_junction_values_and_slopes(law):
+    pr = PRIORS[law]
     e, gl = pr.eps, pr.g_l
     assert abs(pr.H1(e)) < 1e-15 and abs(pr.H2(gl - e)) < 1e-12 * pr.p_upsilon_cont(gl)
     assert abs(pr.H1(0.0) - (1 - pr.p)) < 1e-15              # point mass value at 0
@@ -351,9 +371,10 @@ def test_theorem1_junction_values_and_slopes():
     assert abs(pr.dH2(gl) - pr.dp_upsilon_cont(gl)) < 1e-10 * abs(pr.dp_upsilon_cont(gl))
 
 
+@pytest.mark.parametrize("law", LAWS)
 @pytest.mark.parametrize("where", ["H1", "H2", "density"])
-def test_prior_derivative_matches_finite_differences(where):
-    pr = PRIOR
+def test_prior_derivative_matches_finite_differences(where, law):
+    pr = PRIORS[law]
     e, gl, gu = pr.eps, pr.g_l, pr.g_u
     pts = {"H1": np.linspace(0.05 * e, 0.95 * e, 7),
            "H2": np.linspace(gl - 0.95 * e, gl - 0.05 * e, 7),
@@ -366,11 +387,14 @@ def test_prior_derivative_matches_finite_differences(where):
         assert abs(fdl - pr.log_ratio(x)) <= 1e-5 * max(1.0, abs(fdl))
 
 
-def test_prior_density_piece_log_ratio_power_law_closed_form():
-    """For phi(d) = c0 d^-beta, p'/p on [g_l, g_u] is -(2/beta + 1)/gamma."""
-    pr = PRIOR
+@pytest.mark.parametrize("law", LAWS)
+def test_prior_density_piece_log_ratio_power_law_closed_form(law):
+    """For phi(d) = c0 d^-beta, p'/p on [g_l, g_u] is -(2/beta + 1)/gamma
+    for the area-uniform law and -(1/beta + 1)/gamma for uniform in d."""
+    pr = PRIORS[law]
+    c = (2.0 if law == O.AREA_UNIFORM else 1.0) / pr.beta + 1.0
     for x in np.geomspace(pr.g_l, pr.g_u, 9):
-        assert abs(pr.log_ratio(x) + (2 / pr.beta + 1) / x) < 1e-12 / x
+        assert abs(pr.log_ratio(x) + c / x) < 1e-12 / x
 
 
 def test_prior_gap_reading():
@@ -473,3 +497,46 @@ def test_map_ur_trajectories_can_pass_through_a_pole_of_the_prior():
     assert rel[n] > 0.5 and m[n] < 1e-4
     rel0, _ = rel_change(I.workload_instance("single", 0))
     assert rel0.max() < 1e-5
+
+
+def test_ml_k_with_unit_pathloss_is_ml_ud_below_the_upper_bound():
+    """With every g_n = 1, ML-K's objective, gradient and curvature are
+    ML-UD's (eqs. likelihood_Y / likelihood_Y_U with Sigma built from
+    w = g alpha = alpha); the two differ only in the upper clip at 1 of
+    Lemma 1.  On an instance whose iterates stay below 1 the trajectories
+    are identical."""
+    rng = np.random.default_rng(21)
+    N, L, M = 40, 10, 64
+    S = crandn(rng, L, N) / np.sqrt(L)
+    gam = 0.3 * (rng.uniform(size=N) < 0.2)
+    H = crandn(rng, N, M)
+    W = crandn(rng, L, M)
+    Y = S @ (np.sqrt(gam)[:, None] * H) + W
+    Sh = O.sample_covariance(Y)
+    ud = O.Problem(Sh, S, 1.0, M, O.ML_UD)
+    xk, hist = O.psca(O.Problem(Sh, S, 1.0, M, O.ML_K, g=np.ones(N)), 60, record=True)
+    xu = O.psca(ud, 60)
+    assert max(np.max(r.x_tilde) for r in hist) < 1.0   # the clip at 1 never binds
+    assert np.array_equal(xk, xu)
+
+
+@pytest.mark.parametrize("variant", [O.ML_UD, O.ML_K])
+def test_bcd_and_psca_reach_the_same_stationary_point(variant):
+    """Block coordinate descent (the sequential algorithm PSCA parallelises:
+    Algorithm 2, and its unknown-pathloss form BCD-ML-UD of Sec. IV-A) and
+    PSCA share the coordinate solution form (remark after Lemma 1), so on a
+    small instance both approach the same stationary point: the BCD limit
+    is a fixed point of PSCA's step (x~ = x), and PSCA's distance to it and
+    objective gap shrink as it iterates."""
+    inst = I.make_instance(0, 42, 30, 12, 256, 0.2)
+    prob = O.problem_from_instance(inst, variant)
+    xb = O.psca_oracle.bcd(prob, 1000)
+    rec = O.psca_iteration(prob, xb, 0.5)
+    scale = np.max(np.abs(xb))
+    assert np.max(np.abs(rec.x_tilde - xb)) <= 1e-9 * scale          # BCD limit: stationary
+    fb = O.objective(prob, xb)
+    x1, x4 = O.psca(prob, 1000), O.psca(prob, 4000)
+    gap1, gap4 = O.objective(prob, x1) - fb, O.objective(prob, x4) - fb
+    d1, d4 = np.max(np.abs(x1 - xb)) / scale, np.max(np.abs(x4 - xb)) / scale
+    assert 0.0 <= gap4 < gap1 / 3 and d4 < d1 / 3
+    assert d4 < (1e-3 if variant == O.ML_UD else 1e-2)
