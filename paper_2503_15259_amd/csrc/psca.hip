@@ -1508,6 +1508,200 @@ __device__ __forceinline__ const float2 *pblk(const float2 *packed, int I, int J
   return packed + (size_t)blk_index(I, J) * 256;
 }
 
+// Packed Gram partial S_t diag(w) S_t^H of a tile staged in LDS (Yt
+// [Lp][PT], ncb 16-column blocks, weights w[c]) into dst (NB lower 16x16
+// blocks of 256 entries, column-major within a block).  FP64 MFMA (the
+// FP32 operands' products are exact in FP64), three products per complex
+// step (Gauss); the blocks are spread over the waves.
+template <int THREADS>
+__device__ __forceinline__ void gram_tile_fp64(const float2 *Yt, int PT, int ncb, const float *w, int NB,
+                                               float2 *dst) {
+  constexpr int kWaves = THREADS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
+  for (int b = wave; b < NB; b += kWaves) {
+    int I, J;
+    blk_coords(b, I, J);
+    d4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;
+    for (int cb = 0; cb < ncb; ++cb) {
+      double2 av4[4], bv4[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int c = 16 * cb + 4 * ks + lq;
+        const float2 sv = Yt[(16 * J + l16) * PT + c];
+        const float2 av = Yt[(16 * I + l16) * PT + c];
+        const double wc = w[c];
+        av4[ks] = make_double2(av.x, av.y);
+        bv4[ks] = make_double2(wc * sv.x, -wc * sv.y);
+      }
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) cmfma_d3(av4[ks], bv4[ks], t1, t2, t3);
+    }
+    float2 *o = dst + (size_t)b * 256 + l16 * 16 + lq;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)(t1[v] - t2[v]), (float)(t3[v] - t1[v] - t2[v]));
+  }
+}
+
+// Phase B of a detection on T workgroups: workgroup g sums its 1/T slice of
+// packed Sigma over `parts` partial slots (FP64), adds sigma^2 on the
+// diagonal (unit pivots on padding rows) and writes Sigma and
+// Delta = Sigma - SigmaHat (from the FP64 sum) to memory.  dscr: THREADS
+// double2 of LDS.
+template <int THREADS>
+__device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *delta, int parts, int T, int g,
+                                                   double2 *dscr) {
+  const int tid = threadIdx.x;
+  const int Lp = (A.L + 15) & ~15, Lb = Lp / 16, E = Lb * (Lb + 1) / 2 * 256;
+  // Pp threads per element of the slice each sum every Pp-th partial
+  // (double), then one thread per element adds the Pp sums in LDS.
+  const int per = (E + T - 1) / T;
+  const int start = g * per, end = min(E, start + per), cnt = max(0, end - start);
+  const int Pp = cnt > 0 ? max(1, THREADS / cnt) : 1;
+  for (int e0 = 0; e0 < cnt; e0 += THREADS / Pp) {
+    const int e_loc = e0 + tid % (THREADS / Pp), part = tid / (THREADS / Pp);
+    double2 acc = make_double2(0.0, 0.0);
+    if (part < Pp && e_loc < cnt) {
+      constexpr int kU = 8;   // loads in flight per thread
+      const float2 *src = A.partials + start + e_loc;
+      int h = part;
+      for (; h + (kU - 1) * Pp < parts; h += kU * Pp) {
+        float2 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = src[(size_t)(h + u * Pp) * A.pstride];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          acc.x += v[u].x;
+          acc.y += v[u].y;
+        }
+      }
+      for (; h < parts; h += Pp) {
+        const float2 v = src[(size_t)h * A.pstride];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+    }
+    dscr[tid] = acc;
+    __syncthreads();
+    const int e = start + e0 + tid;
+    if (tid < THREADS / Pp && e0 + tid < cnt) {
+      double2 sm = make_double2(0.0, 0.0);   // summed in double, rounded once
+      for (int q = 0; q < Pp; ++q) {
+        const double2 v = dscr[q * (THREADS / Pp) + tid];
+        sm.x += v.x;
+        sm.y += v.y;
+      }
+      const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+      int I, J;
+      blk_coords(b, I, J);
+      if (I == J && ii == jj) {
+        sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
+        sm.y = 0.0;
+      }
+      A.sigma[e] = make_float2((float)sm.x, (float)sm.y);
+      const int i = 16 * I + ii, k = 16 * J + jj;   // Sigma - SigmaHat from the FP64 sum
+      const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+      delta[e] = make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y));
+    }
+    __syncthreads();
+  }
+}
+
+// Phase C1 of a detection on T workgroups: blocked Cholesky of packed Sigma
+// in memory, one team barrier per block step.  Every workgroup factors the
+// diagonal block in registers and keeps W_JJ = L_JJ^-1 in LDS (Wd); the
+// trailing updates are spread over the team's waves, each forming the panel
+// blocks it needs; the off-diagonal blocks of L go to lbuf.  Returns 0, 1
+// for a pivot that is not positive and finite (the same decision in every
+// workgroup), 2 when a barrier gave up.
+template <int THREADS>
+__device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 *delta, float2 *lbuf, float2 *Wd,
+                                                float2 *scr, int T, int g, unsigned &gen, int *s_ok, int *s_pd) {
+  constexpr int kWaves = THREADS / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lq = lane >> 4;
+  const int Lp = (A.L + 15) & ~15, Lb = Lp / 16, E = Lb * (Lb + 1) / 2 * 256;
+  const int gwave = g * kWaves + wave, nwaves = T * kWaves;
+  float2 *sig = A.sigma;
+  (void)scr;
+  int res = 0;
+  for (int J = 0; J < Lb; ++J) {
+    float2 *Wj = Wd + J * 256;
+    for (int e = tid; e < 256; e += THREADS) Wj[e] = pblk(sig, J, J)[e];
+    __syncthreads();
+    if (wave == 0) {
+      const bool ok = leaf_chol(Wj, 16, lane);
+      if (lane == 0) *s_pd = ok ? 1 : 0;
+    } else if (J == 0) {   // while the first leaf runs: Sigma - SigmaHat into L2 for C4
+      warm_l2(delta, E, tid - 64, THREADS - 64);
+    }
+    __syncthreads();
+    if (!*s_pd) {   // uniform: every workgroup factors the same block
+      res = 1;
+      break;
+    }
+    if (J + 1 == Lb) break;
+    {   // trailing A_IK -= L_IJ L_KJ^H (J < K <= I).  Each task forms the panel
+        // blocks it needs itself, L^T = conj(W_JJ) A^T, which leaves L[j][4q + v]
+        // in lane (j, q): the layout of an MFMA operand over the permuted index
+        // k = 4q + chunk.  So one barrier per block step; the task (I, J + 1)
+        // stores L_IJ for the solves.
+      const int m = Lb - 1 - J;
+      auto panel_t = [&](int I, f4 &dr, f4 &di) {
+        const float2 *blk = pblk(sig, I, J);
+        dr = (f4){0.f, 0.f, 0.f, 0.f};
+        di = (f4){0.f, 0.f, 0.f, 0.f};
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int k = 4 * ks + lq;
+          const float2 w = Wj[k * 16 + l16];   // W_JJ[l16][k]
+          a4[ks] = make_float2(w.x, -w.y);
+          b4[ks] = blk[k * 16 + l16];           // A_IJ[l16][k] = A^T[k][l16]
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], dr, di);
+      };
+      for (int t = gwave; t < m * (m + 1) / 2; t += nwaves) {
+        int ii = 0;
+        while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+        const int I = J + 1 + ii, K = J + 1 + (t - ii * (ii + 1) / 2);
+        f4 lir, lii, lkr, lki;
+        panel_t(I, lir, lii);
+        if (K == I) {
+          lkr = lir;
+          lki = lii;
+        } else {
+          panel_t(K, lkr, lki);
+        }
+        if (K == J + 1) {
+          float2 *lb = lbuf + (size_t)blk_index(I, J) * 256;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) lb[(4 * lq + v) * 16 + l16] = make_float2(lir[v], lii[v]);
+        }
+        float2 *dst = sig + (size_t)blk_index(I, K) * 256;
+        f4 cr, ci;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float2 c = dst[l16 * 16 + 4 * lq + v];
+          cr[v] = c.x;
+          ci[v] = c.y;
+        }
+        float2 a4[4], b4[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          a4[ks] = make_float2(-lir[ks], -lii[ks]);   // L_IJ[l16][4 lq + ks]
+          b4[ks] = make_float2(lkr[ks], -lki[ks]);    // conj(L_KJ[l16][4 lq + ks])
+        }
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[l16 * 16 + 4 * lq + v] = make_float2(cr[v], ci[v]);
+      }
+    }
+    if (!grid_sync(A.bar, T, g, gen, s_ok)) { res = 2; break; }
+  }
+  return res;
+}
+
 template <int THREADS>
 __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
   const CoopArgs &A = Lg.c;
@@ -1578,168 +1772,22 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
       }
     }
     __syncthreads();
-    for (int b = wave; b < NB; b += kWaves) {
-      int I, J;
-      blk_coords(b, I, J);
-      d4 t1 = {0.0, 0.0, 0.0, 0.0}, t2 = t1, t3 = t1;   // FP64, as tile_gram
-      for (int cb = 0; cb < ncb; ++cb) {
-        double2 av4[4], bv4[4];
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int c = 16 * cb + 4 * ks + lq;
-          const float2 sv = Yt[(16 * J + l16) * PT + c];
-          const float2 av = Yt[(16 * I + l16) * PT + c];
-          const double w = red_q[c];
-          av4[ks] = make_double2(av.x, av.y);
-          bv4[ks] = make_double2(w * sv.x, -w * sv.y);
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma_d3(av4[ks], bv4[ks], t1, t2, t3);
-      }
-      float2 *o = A.partials + (size_t)g * A.pstride + (size_t)b * 256 + l16 * 16 + lq;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)(t1[v] - t2[v]), (float)(t3[v] - t1[v] - t2[v]));
-    }
+    gram_tile_fp64<THREADS>(Yt, PT, ncb, red_q, NB, A.partials + (size_t)g * A.pstride);
     PSCA_MARK(it, 1);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ---- B. reduce a slice into Sigma and its copy
     PSCA_MARK(it, 2);
-    {
-      // Pp threads per element of the slice each sum every Pp-th partial
-      // (double), then one thread per element adds the Pp sums in LDS.
-      const int per = (E + A.G - 1) / A.G;
-      const int start = g * per, end = min(E, start + per), cnt = max(0, end - start);
-      const int Pp = cnt > 0 ? max(1, THREADS / cnt) : 1;
-      double2 *dscr = (double2 *)scr;   // [THREADS]
-      for (int e0 = 0; e0 < cnt; e0 += THREADS / Pp) {
-        const int e_loc = e0 + tid % (THREADS / Pp), part = tid / (THREADS / Pp);
-        double2 acc = make_double2(0.0, 0.0);
-        if (part < Pp && e_loc < cnt) {
-          constexpr int kU = 8;   // loads in flight per thread
-          const float2 *src = A.partials + start + e_loc;
-          int h = part;
-          for (; h + (kU - 1) * Pp < A.G; h += kU * Pp) {
-            float2 v[kU];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) v[u] = src[(size_t)(h + u * Pp) * A.pstride];
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-              acc.x += v[u].x;
-              acc.y += v[u].y;
-            }
-          }
-          for (; h < A.G; h += Pp) {
-            const float2 v = src[(size_t)h * A.pstride];
-            acc.x += v.x;
-            acc.y += v.y;
-          }
-        }
-        dscr[tid] = acc;
-        __syncthreads();
-        const int e = start + e0 + tid;
-        if (tid < THREADS / Pp && e0 + tid < cnt) {
-        double2 sm = make_double2(0.0, 0.0);   // summed in double, rounded once
-        for (int q = 0; q < Pp; ++q) {
-          const double2 v = dscr[q * (THREADS / Pp) + tid];
-          sm.x += v.x;
-          sm.y += v.y;
-        }
-        const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
-        int I, J;
-        blk_coords(b, I, J);
-        if (I == J && ii == jj) {
-          sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
-          sm.y = 0.0;
-        }
-        sig[e] = make_float2((float)sm.x, (float)sm.y);
-        const int i = 16 * I + ii, k = 16 * J + jj;   // Sigma - SigmaHat from the FP64 sum
-        const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
-        Lg.delta[e] = make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y));
-        }
-        __syncthreads();
-      }
-    }
+    reduce_sigma_slice<THREADS>(A, Lg.delta, A.G, A.G, g, (double2 *)scr);
     PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
 
     // ---- C1. cooperative blocked Cholesky in memory
     PSCA_MARK(it, 4);
-    for (int J = 0; J < Lb; ++J) {
-      float2 *Wj = Wd + J * 256;
-      for (int e = tid; e < 256; e += THREADS) Wj[e] = pblk(sig, J, J)[e];
-      __syncthreads();
-      if (wave == 0) {
-        const bool ok = leaf_chol(Wj, 16, lane);
-        if (lane == 0) s_pd = ok ? 1 : 0;
-      } else if (J == 0) {   // while the first leaf runs: Sigma - SigmaHat into L2 for C4
-        warm_l2(Lg.delta, E, tid - 64, THREADS - 64);
-      }
-      __syncthreads();
-      if (!s_pd) {   // uniform: every workgroup factors the same block
-        failed = true;
-        break;
-      }
-      if (J + 1 == Lb) break;
-      {   // trailing A_IK -= L_IJ L_KJ^H (J < K <= I).  Each task forms the panel
-          // blocks it needs itself, L^T = conj(W_JJ) A^T, which leaves L[j][4q + v]
-          // in lane (j, q): the layout of an MFMA operand over the permuted index
-          // k = 4q + chunk.  So one barrier per block step; the task (I, J + 1)
-          // stores L_IJ for the solves.
-        const int m = Lb - 1 - J;
-        auto panel_t = [&](int I, f4 &dr, f4 &di) {
-          const float2 *blk = pblk(sig, I, J);
-          dr = (f4){0.f, 0.f, 0.f, 0.f};
-          di = (f4){0.f, 0.f, 0.f, 0.f};
-          float2 a4[4], b4[4];
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lq;
-            const float2 w = Wj[k * 16 + l16];   // W_JJ[l16][k]
-            a4[ks] = make_float2(w.x, -w.y);
-            b4[ks] = blk[k * 16 + l16];           // A_IJ[l16][k] = A^T[k][l16]
-          }
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], dr, di);
-        };
-        for (int t = gwave; t < m * (m + 1) / 2; t += nwaves) {
-          int ii = 0;
-          while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-          const int I = J + 1 + ii, K = J + 1 + (t - ii * (ii + 1) / 2);
-          f4 lir, lii, lkr, lki;
-          panel_t(I, lir, lii);
-          if (K == I) {
-            lkr = lir;
-            lki = lii;
-          } else {
-            panel_t(K, lkr, lki);
-          }
-          if (K == J + 1) {
-            float2 *lb = Lg.lbuf + (size_t)blk_index(I, J) * 256;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) lb[(4 * lq + v) * 16 + l16] = make_float2(lir[v], lii[v]);
-          }
-          float2 *dst = sig + (size_t)blk_index(I, K) * 256;
-          f4 cr, ci;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const float2 c = dst[l16 * 16 + 4 * lq + v];
-            cr[v] = c.x;
-            ci[v] = c.y;
-          }
-          float2 a4[4], b4[4];
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            a4[ks] = make_float2(-lir[ks], -lii[ks]);   // L_IJ[l16][4 lq + ks]
-            b4[ks] = make_float2(lkr[ks], -lki[ks]);    // conj(L_KJ[l16][4 lq + ks])
-          }
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) dst[l16 * 16 + 4 * lq + v] = make_float2(cr[v], ci[v]);
-        }
-      }
-      if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
+    {
+      const int f = factor_in_memory<THREADS>(A, Lg.delta, Lg.lbuf, Wd, scr, A.G, g, gen, &s_ok, &s_pd);
+      failed = f == 1;
+      aborted = f == 2;
     }
     if (failed || aborted) break;
 
@@ -1894,6 +1942,384 @@ __device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
 }
 
 __global__ void __launch_bounds__(512) k_psca_large(LargeArgs Lg) { large_body<512>(Lg, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
+// Pilot lengths 97..256 on teams of workgroups: k_psca_large_teams
+//
+// One instance runs on a team of T workgroups.  Its devices are cut into Gv
+// Gram tiles of NT = 16 ncb columns; rank g of the team forms the packed
+// partials of tiles g, g + T, g + 2T, ... (each tile staged in LDS, FP64
+// Gram as in k_psca_large, one partial slot per tile).  Phase B sums the Gv
+// slots, 1/T of packed Sigma per rank; C1 factors Sigma in memory as
+// k_psca_large does.  The solves run per 16-column block with the block
+// held in registers: wave w of rank g takes the column blocks 8g + w,
+// 8g + w + 8T, ..., so every wave of the team has work whatever the tile
+// width, and a column block's substitutions, q, q - r and coordinate step
+// need neither LDS nor a barrier.  The iterate lives in memory (xw); a team
+// barrier closes every iteration but the last, before the next Gram pass
+// reads it.  Teams work through lists of instances as k_psca_teams does.
+// ---------------------------------------------------------------------------
+struct LargeTeamArgs {
+  CoopArgs c;        // c.G: the team size T; c.NT, c.ncb: the Gram tile; c.partials: [Gv][pstride]
+  float2 *delta;     // packed Sigma - SigmaHat
+  float2 *lbuf;      // packed off-diagonal blocks of the factor L
+  float *xw;         // [N] the iterate
+  int Gv;            // Gram tiles, ceil(N / NT)
+};
+
+__host__ __device__ inline size_t lds_large_team_bytes(int Lp, int NT, int threads) {
+  return ((size_t)Lp * (NT + 1) + (size_t)(Lp / 16) * 256) * sizeof(float2) + (size_t)threads * sizeof(double2) +
+         (size_t)NT * sizeof(float);
+}
+
+// Global loads through an explicitly global pointer: the descriptors' generic
+// pointers would otherwise give flat loads, whose waits also cover LDS.
+typedef float gvec2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) gvec2 gvec2_g;
+__device__ __forceinline__ float2 ldg2(const float2 *p, size_t i) {
+  const gvec2 v = ((gvec2_g *)p)[i];
+  return make_float2(v.x, v.y);
+}
+
+// Row of flat task t when row r holds r tasks (rows 1, 2, ...): the largest
+// r with r (r - 1) / 2 <= t.  Constant-folded where t is a constant.
+__device__ __forceinline__ constexpr int tri_row(int t) {
+  int r = 1;
+  while ((r + 1) * r / 2 <= t) ++r;
+  return r;
+}
+
+// Gauss accumulators, two independent sets (even and odd terms) so that
+// consecutive MFMAs do not wait on each other's results.
+struct Gauss2 {
+  f4 t[2][3];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t[s][k] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  // acc += A B for one 16x16 block: a[ks] = A[j][4h + ks], b[ks] = B[4h + ks][j]
+  __device__ __forceinline__ void add(int set, const float2 (&a)[4], const float2 (&b)[4]) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) cmfma3(a[ks], b[ks], t[set][0], t[set][1], t[set][2]);
+  }
+  __device__ __forceinline__ float2 get(int v) const {   // element v of this lane's output rows
+    const float p1 = t[0][0][v] + t[1][0][v], p2 = t[0][1][v] + t[1][1][v], p3 = t[0][2][v] + t[1][2][v];
+    return make_float2(p1 - p2, p3 - p1 - p2);
+  }
+};
+
+// One wave: Y = L^-1 S_c (q = sum |y|^2), B = L^-H Y (= Sigma^-1 S_c),
+// q - r = Re b^H (Sigma - SigmaHat) b and the coordinate step of the 16
+// devices c0 .. c0 + 15.  The column block lives in registers in the MFMA
+// output layout: lane (j, h) holds rows 4h .. 4h + 3 of every 16-row block,
+// column j.  Used as the B operand of a 16x16x4 step `ks`, that register
+// set supplies the inner index k = 4h + ks (a permutation of the 16 inner
+// indices over the four steps), so the A operands (blocks of L, W_RR and
+// Sigma - SigmaHat) are read in the same permuted order and no transposition
+// is needed between block rows.  Each pass walks its blocks in a fixed order
+// with the operands of the next two blocks already in flight.
+template <int LB>
+__device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, const float2 *Wd, int c0, int it,
+                                                   float rho, bool last) {
+  const CoopArgs &A = Tg.c;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+  const int n = c0 + l16;
+  const bool col_in = n < A.N;
+  // The factor and Sigma - SigmaHat are the same for every column block; an
+  // opaque copy of their addresses keeps the compiler from hoisting all of
+  // their loads out of the caller's loop over column blocks (thousands of
+  // registers, spilled).
+  const float2 *lbuf = Tg.lbuf, *dlt = Tg.delta;
+  asm volatile("" : "+v"(lbuf), "+v"(dlt));
+  const int lo_n = (4 * lq) * 16 + l16;   // A[j][4h + ks] at lo_n + 16 ks (column-major block)
+  const int lo_t = l16 * 16 + 4 * lq;     // A^T[j][4h + ks] at lo_t + ks
+  float2 y[LB][4];
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * R + 4 * lq + v;
+      y[R][v] = (col_in && row < A.L) ? ldg2(A.S, (size_t)n * A.L + row) : make_float2(0.f, 0.f);
+    }
+  float2 ring[3][4];   // operands of the current block and the next two
+  Gauss2 acc;
+
+  // forward substitution: Y_R = W_RR (S_R - sum_{K<R} L_RK Y_K); task t is
+  // block (R, K) with R = tri_row(t), K = t - R (R - 1) / 2
+  constexpr int nf = LB * (LB - 1) / 2;
+  auto load_f = [&](int t, float2 (&dst)[4]) {
+    const int R = tri_row(t), K = t - R * (R - 1) / 2;
+    const float2 *blk = pblk(lbuf, R, K);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) dst[ks] = ldg2(blk, lo_n + 16 * ks);
+  };
+  if (nf > 0) load_f(0, ring[0]);
+  if (nf > 1) load_f(1, ring[1]);
+#pragma unroll
+  for (int R = 0; R < LB; ++R) {
+    acc.zero();
+#pragma unroll
+    for (int K = 0; K < R; ++K) {
+      const int t = R * (R - 1) / 2 + K;
+      if (t + 2 < nf) load_f(t + 2, ring[(t + 2) % 3]);
+      acc.add(K & 1, ring[t % 3], y[K]);
+    }
+    float2 r4[4], w4[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float2 d = acc.get(v);
+      r4[v] = make_float2(y[R][v].x - d.x, y[R][v].y - d.y);
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) w4[ks] = Wd[R * 256 + lo_n + 16 * ks];   // W_RR[j][4h + ks]
+    acc.zero();
+    acc.add(0, w4, r4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[R][v] = acc.get(v);
+  }
+  float q = 0.0f;
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q += y[R][v].x * y[R][v].x + y[R][v].y * y[R][v].y;
+  q += __shfl_xor(q, 16);
+  q += __shfl_xor(q, 32);
+
+  // backward substitution: B_R = W_RR^H (Y_R - sum_{K>R} L_KR^H B_K), R from
+  // the last block row up; task t is block (K, R) with r = tri_row(t),
+  // R = LB - 1 - r, K = R + 1 + t - r (r - 1) / 2
+  auto load_b = [&](int t, float2 (&dst)[4]) {
+    const int r = tri_row(t), R = LB - 1 - r, K = R + 1 + t - r * (r - 1) / 2;
+    const float2 *blk = pblk(lbuf, K, R);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const float2 x = ldg2(blk, lo_t + ks);   // L_KR[4h + ks][j]
+      dst[ks] = make_float2(x.x, -x.y);
+    }
+  };
+  if (nf > 0) load_b(0, ring[0]);
+  if (nf > 1) load_b(1, ring[1]);
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    const int R = LB - 1 - r;
+    acc.zero();
+#pragma unroll
+    for (int j = 0; j < r; ++j) {
+      const int t = r * (r - 1) / 2 + j, K = R + 1 + j;
+      if (t + 2 < nf) load_b(t + 2, ring[(t + 2) % 3]);
+      acc.add(j & 1, ring[t % 3], y[K]);
+    }
+    float2 r4[4], w4[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float2 d = acc.get(v);
+      r4[v] = make_float2(y[R][v].x - d.x, y[R][v].y - d.y);
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const float2 w = Wd[R * 256 + lo_t + ks];   // W_RR[4h + ks][j]
+      w4[ks] = make_float2(w.x, -w.y);
+    }
+    acc.zero();
+    acc.add(0, w4, r4);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[R][v] = acc.get(v);
+  }
+
+  // q - r = b^H (Sigma - SigmaHat) b = sum_I b_I^H D_II b_I + 2 Re sum_{K<I} b_I^H D_IK b_K;
+  // task t is the packed block t = (I, K), K <= I
+  constexpr int nd = LB * (LB + 1) / 2;
+  auto load_d = [&](int t, float2 (&dst)[4]) {
+    const int I = tri_row(t) - 1, K = t - I * (I + 1) / 2;
+    const float f = K < I ? 2.0f : 1.0f;
+    const float2 *blk = dlt + (size_t)t * 256;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const float2 x = ldg2(blk, lo_n + 16 * ks);   // D_IK[j][4h + ks]
+      dst[ks] = make_float2(f * x.x, f * x.y);
+    }
+  };
+  load_d(0, ring[0]);
+  if (nd > 1) load_d(1, ring[1]);
+  float qmr = 0.0f;
+#pragma unroll
+  for (int I = 0; I < LB; ++I) {
+    acc.zero();
+#pragma unroll
+    for (int K = 0; K <= I; ++K) {
+      const int t = I * (I + 1) / 2 + K;
+      if (t + 2 < nd) load_d(t + 2, ring[(t + 2) % 3]);
+      acc.add(K & 1, ring[t % 3], y[K]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float2 d = acc.get(v);
+      qmr += y[I][v].x * d.x + y[I][v].y * d.y;
+    }
+  }
+  qmr += __shfl_xor(qmr, 16);
+  qmr += __shfl_xor(qmr, 32);
+  // coordinate step and convex update of device n
+  if (lq == 0 && col_in) {
+    const float x = Tg.xw[n];
+    const float gn = A.a.g ? A.a.g[n] : 0.0f;
+    float prior = 0.0f;
+    if (A.a.p) {
+      const float pn = A.a.p[n];
+      prior = logf(pn / (1.0f - pn));
+    }
+    const bool pairs = A.a.variant == PSCA_MAP_K2;
+    if (pairs) prior = A.a.c1[n] + pair_sum(A.a, n, A.N, A.a.xg + (size_t)(it & 1) * A.N);
+    const float xt = coordinate_step(x, q, qmr, gn, prior, A.a);
+    const float xn = (1.0f - rho) * x + rho * xt;
+    Tg.xw[n] = xn;
+    if (pairs) A.a.xg[(size_t)((it + 1) & 1) * A.N + n] = xn;
+    if (A.x_hist) A.x_hist[(size_t)(it + 1) * A.N + n] = xn;
+    if (last) {
+      A.x_out[n] = xn;
+      if (A.q_out) A.q_out[n] = q;
+      if (A.r_out) A.r_out[n] = q - qmr;
+      if (A.xt_out) A.xt_out[n] = xt;
+    }
+  }
+}
+
+template <int LB, int THREADS>
+__device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const int g) {
+  const CoopArgs &A = Tg.c;
+  constexpr int kWaves = THREADS / 64;
+  constexpr int Lp = 16 * LB, NB = LB * (LB + 1) / 2;
+  extern __shared__ float4 smem_raw[];
+  __shared__ int s_ok, s_pd;
+  const int NT = A.NT, PT = A.NT + 1, ncb = A.ncb, T = A.G, Gv = Tg.Gv;
+  float2 *Yt = (float2 *)smem_raw;          // [Lp][PT] Gram tile of S
+  float2 *Wd = Yt + Lp * PT;                // [LB][256] W_JJ, column-major blocks
+  double2 *dscr = (double2 *)(Wd + LB * 256);   // [THREADS] phase B
+  float *wv = (float *)(dscr + THREADS);    // [NT] weights of the tile
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K || A.a.variant == PSCA_MAP_K2);
+  const bool pairs = (A.a.variant == PSCA_MAP_K2);
+  const int ncol = (A.N + 15) / 16;
+  unsigned gen = 0;
+  bool failed = false, aborted = false;
+
+  for (int n = g * THREADS + tid; n < A.N; n += T * THREADS) {   // x^(0)
+    const float x = A.x_in ? A.x_in[n] : 0.0f;
+    Tg.xw[n] = x;
+    if (A.x_hist) A.x_hist[n] = x;
+    if (pairs) A.a.xg[n] = x;
+  }
+  if (!grid_sync(A.bar, T, g, gen, &s_ok)) aborted = true;
+
+  double rho_d = A.rho0;
+  for (int it = 0; it < A.iters && !aborted; ++it) {
+    // ---- A. packed Gram partials of this rank's tiles
+    for (int v = g; v < Gv; v += T) {
+      const int n0 = v * NT;
+      __syncthreads();   // the previous tile's Gram is done with Yt and wv
+      for (int c = tid; c < NT; c += THREADS) {
+        const int n = n0 + c;
+        const float x = n < A.N ? Tg.xw[n] : 0.0f;
+        wv[c] = n < A.N ? (known ? A.a.g[n] * x : x) : 0.0f;
+      }
+      {
+        constexpr int kU = 8;   // loads in flight per thread
+        const int tot = Lp * NT;
+        for (int e0 = tid; e0 < tot; e0 += kU * THREADS) {
+          float2 val[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;   // down a column: coalesced
+            const int n = n0 + c;
+            val[u] = (e < tot && i < A.L && n < A.N) ? A.S[(size_t)n * A.L + i] : make_float2(0.f, 0.f);
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;
+            if (e < tot) Yt[i * PT + c] = val[u];
+          }
+        }
+      }
+      __syncthreads();
+      gram_tile_fp64<THREADS>(Yt, PT, ncb, wv, NB, A.partials + (size_t)v * A.pstride);
+    }
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    // ---- B. Sigma and Sigma - SigmaHat, 1/T of the packed entries per rank
+    reduce_sigma_slice<THREADS>(A, Tg.delta, Gv, T, g, dscr);
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    // ---- C1. blocked Cholesky in memory
+    const int f = factor_in_memory<THREADS>(A, Tg.delta, Tg.lbuf, Wd, nullptr, T, g, gen, &s_ok, &s_pd);
+    if (f == 1) failed = true;
+    if (f == 2) aborted = true;
+    if (failed || aborted) break;
+    // ---- C4, C5. solves, quadratic forms and coordinate steps per column block
+    float rho;
+    if (A.rho_fixed >= 0.0f) rho = A.rho_fixed;
+    else if (A.rho_dev) rho = A.rho_dev[it];
+    else rho = (float)rho_d;
+    rho_d = rho_d * (1.0 - A.rho_decay * rho_d);
+    const bool last = (it == A.iters - 1);
+    for (int cb = g * kWaves + wave; cb < ncol; cb += T * kWaves)
+      solve_column_block<LB>(Tg, Wd, 16 * cb, it, rho, last);
+    if (!last && !grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+  }
+  if (A.iters == 0 || failed || aborted)   // x_out holds the last finite iterate
+    for (int n = g * THREADS + tid; n < A.N; n += T * THREADS) A.x_out[n] = Tg.xw[n];
+  if (g == 0 && tid == 0 && A.status) *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
+}
+
+template <int LB>
+__device__ __noinline__ void large_team_member(const LargeTeamArgs *__restrict__ desc, int g) {
+  const LargeTeamArgs A = *desc;
+  large_team_body<LB, 512>(A, g);
+}
+
+__global__ void __launch_bounds__(512) k_psca_large_teams(const LargeTeamArgs *__restrict__ descs,
+                                                          const int *__restrict__ lists,
+                                                          const int *__restrict__ offsets,
+                                                          const int *__restrict__ team_start, int n_teams) {
+  const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);
+  int t = 0, hi = n_teams - 1;   // the team with team_start[t] <= b < team_start[t + 1]
+  while (t < hi) {
+    const int mid = (t + hi + 1) >> 1;
+    if (team_start[mid] <= b) t = mid;
+    else hi = mid - 1;
+  }
+  const int g = b - team_start[t];
+  const int i1 = offsets[t + 1];
+  for (int idx = offsets[t]; idx < i1; ++idx) {
+    const LargeTeamArgs *desc = descs + lists[idx];
+    if (g < desc->c.G) {
+      switch ((desc->c.L + 15) >> 4) {
+        case 7: large_team_member<7>(desc, g); break;
+        case 8: large_team_member<8>(desc, g); break;
+        case 9: large_team_member<9>(desc, g); break;
+        case 10: large_team_member<10>(desc, g); break;
+        case 11: large_team_member<11>(desc, g); break;
+        case 12: large_team_member<12>(desc, g); break;
+        case 13: large_team_member<13>(desc, g); break;
+        case 14: large_team_member<14>(desc, g); break;
+        case 15: large_team_member<15>(desc, g); break;
+        default: large_team_member<16>(desc, g); break;
+      }
+    }
+    __syncthreads();   // the next instance reuses the LDS
+  }
+}
+
+// Barrier words, abort word and status of every instance of a large-L batch
+// launch: block b resets instance b.
+__global__ void k_prepare_large_batch(const LargeTeamArgs *__restrict__ descs) {
+  const CoopArgs &A = descs[blockIdx.x].c;
+  for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
+  if (threadIdx.x == 0) {
+    *A.bar.release = 0u;
+    *A.bar.abort_flag = 0;
+    *A.status = PSCA_OK;
+  }
+}
 
 template <int LPMAX, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
@@ -2303,13 +2729,18 @@ int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, co
   return PSCA_OK;
 }
 
+int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
+                   int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
+                   float *xt_out, int32_t *status, hipStream_t st, float *x_hist);
+
 // Runs k_psca for `iters` iterations from x_in (null: zeros).
 int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
                int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
                float *xt_out, int32_t *status, hipStream_t st, float *x_hist = nullptr) {
   const int Lp = (L + 15) & ~15;
   if (Lp > kMaxLdsL)
-    return run_large(ctx, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, st, x_hist);
+    return run_large_team(ctx, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, st,
+                          x_hist);
   const KernelChoice kc = pick_kernel(Lp);
   InstPlan p{};
   for (int ncb = 1;; ++ncb) {   // occupancy depends on the tile's LDS
@@ -2463,6 +2894,8 @@ struct BatchPlan {
   size_t part_off = 0;
   size_t E_max = 0;
   size_t ws_bytes = 0;
+  bool large = false;            // pilot lengths 97..256: k_psca_large_teams
+  std::vector<int> gv;           // large: Gram tiles per instance
 };
 
 size_t packed_entries(int Lp) { return (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256; }
@@ -2682,6 +3115,119 @@ int make_batch_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan 
   return PSCA_OK;
 }
 
+// ---- large pilot lengths (97..256): teams on k_psca_large_teams ------------
+constexpr int kLargeThreads = 512;
+
+// Widest Gram tile (16..64 columns) whose LDS fits a workgroup.
+int large_tile(int Lp) {
+  for (int nt = 64; nt >= 16; nt -= 16)
+    if (lds_large_team_bytes(Lp, nt, kLargeThreads) <= kMaxLds) return nt;
+  return 0;
+}
+
+// Per-instance workspace of a large-L launch: packed Sigma, Sigma - SigmaHat
+// and L, T barrier words, release/abort/status words, the iterate exchange
+// [2][N] (MAP-K2) and the iterate [N].
+size_t large_inst_ws_bytes(int Lp, int T, int N) {
+  const size_t E = packed_entries(Lp);
+  return 3 * align_up(E * sizeof(float2)) + align_up((size_t)T * 16 * sizeof(unsigned)) +
+         3 * align_up(sizeof(unsigned)) + align_up(2 * (size_t)N * sizeof(float)) + align_up((size_t)N * sizeof(float));
+}
+
+// Points a descriptor's work buffers into `w` (laid out as large_inst_ws_bytes).
+void bind_large_ws(LargeTeamArgs &a, char *w, int Lp, int T, int N) {
+  const size_t E = packed_entries(Lp);
+  a.c.sigma = (float2 *)w;          w += align_up(E * sizeof(float2));
+  a.delta = (float2 *)w;            w += align_up(E * sizeof(float2));
+  a.lbuf = (float2 *)w;             w += align_up(E * sizeof(float2));
+  a.c.bar.arrive = (unsigned *)w;   w += align_up((size_t)T * 16 * sizeof(unsigned));
+  a.c.bar.release = (unsigned *)w;  w += align_up(sizeof(unsigned));
+  a.c.bar.abort_flag = (int32_t *)w; w += align_up(sizeof(unsigned));
+  if (!a.c.status) a.c.status = (int32_t *)w;
+  w += align_up(sizeof(unsigned));
+  a.c.a.xg = (float *)w;            w += align_up(2 * (size_t)N * sizeof(float));
+  a.xw = (float *)w;
+}
+
+// Plans a batch of large-L instances on uniform teams of T workgroups:
+// n = min(cap / T, B) teams, instances assigned longest first (estimated
+// cost per iteration: the contraction, N L^2, plus the serial block steps
+// of the factorisation).  Each team owns one partial region sized for the
+// largest Gv E of its instances (they run one after the other).
+int make_large_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &plan, int iters_cap) {
+  if (T < 1 || T > cap) return PSCA_EINVAL;
+  plan = BatchPlan();
+  plan.large = true;
+  plan.B = B;
+  plan.T = T;
+  plan.probs.assign(pr, pr + B);
+  plan.ip.resize(B);
+  plan.iters.resize(B);
+  plan.gv.resize(B);
+  std::vector<double> cost(B);
+  for (int b = 0; b < B; ++b) {
+    InstPlan &q = plan.ip[b];
+    q.Lp = (pr[b].L + 15) & ~15;
+    q.NT = large_tile(q.Lp);
+    if (q.NT == 0) return PSCA_ENOTSUP;
+    q.ncb = q.NT / 16;
+    q.G = T;
+    q.lds = lds_large_team_bytes(q.Lp, q.NT, kLargeThreads);
+    q.ws = large_inst_ws_bytes(q.Lp, T, pr[b].N);
+    plan.gv[b] = (pr[b].N + q.NT - 1) / q.NT;
+    plan.lds = std::max(plan.lds, q.lds);
+    plan.iters[b] = iters_cap >= 0 ? std::min(pr[b].prm.iters, iters_cap) : pr[b].prm.iters;
+    const double Lb = q.Lp / 16;
+    cost[b] = (double)plan.iters[b] * ((double)pr[b].N * q.Lp * q.Lp / T + 2.0e5 * Lb);
+  }
+  const int n = std::max(1, std::min(cap / T, B));
+  std::vector<std::vector<int>> team(n);
+  plan.team_of.resize(B);
+  std::vector<int> all(B);
+  for (int b = 0; b < B; ++b) all[b] = b;
+  assign_longest_first(all, cost, 0, n, team, plan.team_of);
+  plan.n_teams = n;
+  plan.team_start.assign(1, 0);
+  for (int t = 0; t < n; ++t) plan.team_start.push_back(plan.team_start.back() + T);
+  plan.offsets.push_back(0);
+  for (int t = 0; t < n; ++t) {
+    for (int b : team[t]) plan.lists.push_back(b);
+    plan.offsets.push_back((int)plan.lists.size());
+  }
+  size_t off = 0;
+  plan.ws_off.resize(B);
+  for (int b = 0; b < B; ++b) {
+    plan.ws_off[b] = off;
+    off += plan.ip[b].ws;
+  }
+  plan.part_off = off;
+  size_t part = 0;
+  for (int t = 0; t < n; ++t) {
+    size_t need = 0;
+    for (int b : team[t]) need = std::max(need, (size_t)plan.gv[b] * packed_entries(plan.ip[b].Lp));
+    plan.part_team_off.push_back(part);
+    part += align_up(need * sizeof(float2));
+  }
+  plan.ws_bytes = off + part;
+  return PSCA_OK;
+}
+
+void bind_large_batch(const BatchPlan &plan, char *base, LargeTeamArgs *out) {
+  for (int b = 0; b < plan.B; ++b) {
+    const psca_problem &q = plan.probs[b];
+    const InstPlan &ip = plan.ip[b];
+    LargeTeamArgs a;
+    fill_args(a.c, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, plan.iters[b], -1.0f,
+              nullptr, q.x_out, nullptr, nullptr, nullptr, q.status, ip);
+    bind_large_ws(a, base + plan.ws_off[b], ip.Lp, ip.G, q.N);
+    a.c.x_hist = q.x_hist;
+    a.c.partials = (float2 *)(base + plan.part_off + plan.part_team_off[plan.team_of[b]]);
+    a.c.pstride = packed_entries(ip.Lp);
+    a.Gv = plan.gv[b];
+    out[b] = a;
+  }
+}
+
 // Descriptors of `plan` with its workspace at `base`.
 void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
   for (int b = 0; b < plan.B; ++b) {
@@ -2708,14 +3254,19 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
 }
 
 // Host image of a plan's device arrays: descriptors, lists, offsets, team starts.
+size_t desc_bytes(const BatchPlan &plan) {
+  return (size_t)plan.B * (plan.large ? sizeof(LargeTeamArgs) : sizeof(CoopArgs));
+}
+
 size_t batch_image_bytes(const BatchPlan &plan) {
-  return align_up(plan.B * sizeof(CoopArgs)) + align_up(plan.lists.size() * sizeof(int)) +
+  return align_up(desc_bytes(plan)) + align_up(plan.lists.size() * sizeof(int)) +
          align_up(plan.offsets.size() * sizeof(int)) + align_up(plan.team_start.size() * sizeof(int));
 }
 
 void write_batch_image(const BatchPlan &plan, char *ws_base, char *img) {
-  bind_batch(plan, ws_base, (CoopArgs *)img);
-  char *p = img + align_up(plan.B * sizeof(CoopArgs));
+  if (plan.large) bind_large_batch(plan, ws_base, (LargeTeamArgs *)img);
+  else bind_batch(plan, ws_base, (CoopArgs *)img);
+  char *p = img + align_up(desc_bytes(plan));
   memcpy(p, plan.lists.data(), plan.lists.size() * sizeof(int));
   p += align_up(plan.lists.size() * sizeof(int));
   memcpy(p, plan.offsets.data(), plan.offsets.size() * sizeof(int));
@@ -2725,25 +3276,33 @@ void write_batch_image(const BatchPlan &plan, char *ws_base, char *img) {
 
 // Launches a planned batch whose device image is at `dimg`.
 int launch_batch(const BatchPlan &plan, const char *dimg, hipStream_t st) {
-  const CoopArgs *descs = (const CoopArgs *)dimg;
-  const int *lists = (const int *)(dimg + align_up(plan.B * sizeof(CoopArgs)));
+  const void *descs = (const void *)dimg;
+  const int *lists = (const int *)(dimg + align_up(desc_bytes(plan)));
   const int *offsets = (const int *)((const char *)lists + align_up(plan.lists.size() * sizeof(int)));
   const int *team_start = (const int *)((const char *)offsets + align_up(plan.offsets.size() * sizeof(int)));
   int n_teams = plan.n_teams;
-  hipLaunchKernelGGL(k_prepare_batch, dim3(plan.B), dim3(256), 0, st, descs);
+  if (plan.large)
+    hipLaunchKernelGGL(k_prepare_large_batch, dim3(plan.B), dim3(256), 0, st, (const LargeTeamArgs *)descs);
+  else
+    hipLaunchKernelGGL(k_prepare_batch, dim3(plan.B), dim3(256), 0, st, (const CoopArgs *)descs);
   int rc = launch_ok();
   if (rc != PSCA_OK) return rc;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess) return PSCA_EHIP;
   const dim3 grid(plan.team_start.back()), block(kBatchThreads);
+  const void *fn = plan.large ? (const void *)k_psca_large_teams : (const void *)k_psca_teams;
   if (cs == hipStreamCaptureStatusActive) {
     // graph capture: a plain kernel node; the grid fits the device at once
-    hipLaunchKernelGGL(k_psca_teams, grid, block, plan.lds, st, descs, lists, offsets, team_start, n_teams);
+    if (plan.large)
+      hipLaunchKernelGGL(k_psca_large_teams, grid, block, plan.lds, st, (const LargeTeamArgs *)descs, lists,
+                         offsets, team_start, n_teams);
+    else
+      hipLaunchKernelGGL(k_psca_teams, grid, block, plan.lds, st, (const CoopArgs *)descs, lists, offsets,
+                         team_start, n_teams);
     return launch_ok();
   }
   void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&team_start, (void *)&n_teams};
-  if (hipLaunchCooperativeKernel((const void *)k_psca_teams, grid, block, args, (unsigned)plan.lds, st) !=
-      hipSuccess) {
+  if (hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)plan.lds, st) != hipSuccess) {
     (void)hipGetLastError();
     return PSCA_EHIP;
   }
@@ -2753,6 +3312,83 @@ int launch_batch(const BatchPlan &plan, const char *dimg, hipStream_t st) {
 int batch_capacity(psca_ctx *ctx) {
   const KernelChoice kc{(const void *)k_psca_teams, kBatchThreads, 96};
   return max_coresident(ctx, kc, kMaxLds);
+}
+
+int large_capacity(psca_ctx *ctx) {
+  const KernelChoice kc{(const void *)k_psca_large_teams, kLargeThreads, 256};
+  return max_coresident(ctx, kc, kMaxLds);
+}
+
+// One detection (or iteration, or network forward) with 97 <= L <= 256 on
+// one team of k_psca_large_teams: as many workgroups as Gram tiles, up to
+// the co-resident grid.
+int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
+                   int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
+                   float *xt_out, int32_t *status, hipStream_t st, float *x_hist) {
+  const int cap = large_capacity(ctx);
+  const int Lp = (L + 15) & ~15;
+  const int NT = large_tile(Lp);
+  if (cap <= 0 || NT == 0) return PSCA_ENOTSUP;
+  const int Gv = (N + NT - 1) / NT;
+  const int T = std::min(cap, Gv);
+  BatchPlan plan;
+  plan.large = true;
+  plan.B = 1;
+  plan.T = T;
+  plan.n_teams = 1;
+  plan.lds = lds_large_team_bytes(Lp, NT, kLargeThreads);
+  plan.lists = {0};
+  plan.offsets = {0, 1};
+  plan.team_start = {0, T};
+  const InstPlan ip{Lp, NT / 16, NT, T, plan.lds, large_inst_ws_bytes(Lp, T, N)};
+  const size_t E = packed_entries(Lp);
+  int rc = ensure_ws(ctx, ip.ws + align_up((size_t)Gv * E * sizeof(float2)));
+  if (rc != PSCA_OK) return rc;
+  char *base = (char *)ctx->ws;
+  LargeTeamArgs a;
+  fill_args(a.c, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, ip);
+  bind_large_ws(a, base, Lp, T, N);
+  a.c.x_hist = x_hist;
+  a.c.partials = (float2 *)(base + ip.ws);
+  a.c.pstride = E;
+  a.Gv = Gv;
+  const size_t bytes = batch_image_bytes(plan);
+  char *host = nullptr;
+  if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) return rc;
+  char *img = host;
+  memcpy(img, &a, sizeof(a));
+  img += align_up(desc_bytes(plan));
+  memcpy(img, plan.lists.data(), sizeof(int));
+  img += align_up(sizeof(int));
+  memcpy(img, plan.offsets.data(), 2 * sizeof(int));
+  img += align_up(2 * sizeof(int));
+  memcpy(img, plan.team_start.data(), 2 * sizeof(int));
+  if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  if (hipEventRecord(ctx->desc_done, st) != hipSuccess) return PSCA_EHIP;
+  ctx->desc_pending = true;
+  return launch_batch(plan, (const char *)ctx->ddesc, st);
+}
+
+// Whole-batch pilot-length class: 0 when every L <= 96 (k_psca_teams), 1
+// when every L is 97..256 (k_psca_large_teams), -1 for a batch mixing both.
+int batch_class(int B, const psca_problem *pr) {
+  int small = 0, large = 0;
+  for (int b = 0; b < B; ++b) (pr[b].L > kMaxLdsL ? large : small) = 1;
+  return (small && large) ? -1 : large;
+}
+
+// Default team size of a large-L batch: the co-resident grid shared evenly
+// by the instances, at least one workgroup each.
+int default_large_team(int B, int cap) { return std::max(1, cap / std::max(1, B)); }
+
+// Plan of either class; `spec` as psca_plan_create takes it (large-L
+// batches: uniform teams only).
+int make_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan &plan, int iters_cap) {
+  if (batch_class(B, pr) == 1) return make_large_plan(B, pr, spec, cap, plan, iters_cap);
+  return make_batch_plan(B, pr, spec, cap, plan, iters_cap);
 }
 
 uint64_t batch_signature(int B, const psca_problem *pr) {
@@ -2776,8 +3412,9 @@ int validate_batch(int B, const psca_problem *pr) {
     if (!q.Sigma_hat || !q.S || !q.x_out) return PSCA_EINVAL;
     const int rc = validate_params(&q.prm, q.L, q.N, true);
     if (rc != PSCA_OK) return rc;
-    if (q.L > kMaxLdsL) return PSCA_ENOTSUP;   // batches keep the L x L matrix in LDS
   }
+  // one launch runs one kernel: L x L in LDS (L <= 96) or in memory (97..256)
+  if (batch_class(B, pr) < 0) return PSCA_ENOTSUP;
   return PSCA_OK;
 }
 
@@ -3060,13 +3697,15 @@ int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return PSCA_EHIP;
   hipStream_t st = as_stream(stream);
-  const int cap = batch_capacity(ctx);
+  const bool large = batch_class(B, problems) == 1;
+  const int cap = large ? large_capacity(ctx) : batch_capacity(ctx);
   if (cap <= 0) return PSCA_ENOTSUP;
   const auto hit = ctx->tuned.find(batch_signature(B, problems));
-  const int T = (hit != ctx->tuned.end()) ? hit->second : default_team(B, problems, cap);
+  const int T = (hit != ctx->tuned.end()) ? hit->second
+                                          : (large ? default_large_team(B, cap) : default_team(B, problems, cap));
   if (hit == ctx->tuned.end() && T < 0) return PSCA_ENOTSUP;
   BatchPlan plan;
-  if ((rc = make_batch_plan(B, problems, T, cap, plan, -1)) != PSCA_OK) return rc;
+  if ((rc = make_plan(B, problems, T, cap, plan, -1)) != PSCA_OK) return rc;
   if ((rc = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) return rc;
   const size_t bytes = batch_image_bytes(plan);
   char *host = nullptr;
@@ -3090,14 +3729,22 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return PSCA_EHIP;
   hipStream_t st = as_stream(stream);
-  const int cap = batch_capacity(ctx);
-  const int T0 = min_team(B, problems);
+  const bool large = batch_class(B, problems) == 1;
+  const int cap = large ? large_capacity(ctx) : batch_capacity(ctx);
+  const int T0 = large ? 1 : min_team(B, problems);
   if (cap <= 0 || T0 < 0 || T0 > cap) return PSCA_ENOTSUP;
-  std::vector<int> cand = {T0, default_team(B, problems, cap)};
-  for (int c = 32; c <= 16 * kMaxNcb; c += 16) cand.push_back(-c);   // mixed teams
-  for (int t : {8, 16, 24, 32, 48, 64, 96, 128, 192, 256})
-    if (t >= T0 && t <= cap) cand.push_back(t);
-  if ((long long)B * T0 <= cap) cand.push_back(cap / B);
+  std::vector<int> cand;
+  if (large) {   // uniform teams
+    cand.push_back(default_large_team(B, cap));
+    for (int t : {1, 2, 4, 8, 16, 32, 64, 128, 256})
+      if (t <= cap) cand.push_back(t);
+  } else {
+    cand = {T0, default_team(B, problems, cap)};
+    for (int c = 32; c <= 16 * kMaxNcb; c += 16) cand.push_back(-c);   // mixed teams
+    for (int t : {8, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+      if (t >= T0 && t <= cap) cand.push_back(t);
+    if ((long long)B * T0 <= cap) cand.push_back(cap / B);
+  }
   std::sort(cand.begin(), cand.end());
   cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
   hipEvent_t e0, e1;
@@ -3114,7 +3761,7 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   for (int b = 0; b < B; ++b) K = std::max(K, (int)problems[b].prm.iters);
   auto time_plan = [&](int T, int k, bool warm, float *ms) -> int {
     BatchPlan plan;
-    int r = make_batch_plan(B, problems, T, cap, plan, k);
+    int r = make_plan(B, problems, T, cap, plan, k);
     if (r != PSCA_OK) return r;
     if ((r = ensure_ws(ctx, plan.ws_bytes)) != PSCA_OK) return r;
     const size_t bytes = batch_image_bytes(plan);
@@ -3140,7 +3787,7 @@ int psca_autotune_batch(psca_ctx *ctx, int B, const psca_problem *problems, int 
   for (int T : cand) {
     if (T > 0 && T < T0) continue;
     BatchPlan probe;
-    if (make_batch_plan(B, problems, T, cap, probe, tune_iters) != PSCA_OK) continue;   // infeasible
+    if (make_plan(B, problems, T, cap, probe, tune_iters) != PSCA_OK) continue;   // infeasible
     T = probe.T;   // a single-class mixed plan is a uniform one
     if (std::find(seen.begin(), seen.end(), T) != seen.end()) continue;
     seen.push_back(T);
@@ -3171,20 +3818,22 @@ int psca_plan_create(psca_ctx *ctx, int B, const psca_problem *problems, int tea
   if (B == 0) return PSCA_EINVAL;
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return PSCA_EHIP;
-  const int cap = batch_capacity(ctx);
+  const bool large = batch_class(B, problems) == 1;
+  const int cap = large ? large_capacity(ctx) : batch_capacity(ctx);
   if (cap <= 0) return PSCA_ENOTSUP;
   int T = team_size;
   if (T == 0) {
     const auto hit = ctx->tuned.find(batch_signature(B, problems));
-    T = (hit != ctx->tuned.end()) ? hit->second : default_team(B, problems, cap);
+    T = (hit != ctx->tuned.end()) ? hit->second : (large ? default_large_team(B, cap) : default_team(B, problems, cap));
     if (T == -1) return PSCA_ENOTSUP;   // no feasible default
   }
-  if (!team_spec_ok(T, cap) || (T > 0 && T < min_team(B, problems))) return PSCA_EINVAL;
+  if (large ? (T < 1 || T > cap) : (!team_spec_ok(T, cap) || (T > 0 && T < min_team(B, problems))))
+    return PSCA_EINVAL;
   psca_plan *p = new (std::nothrow) psca_plan;
   if (!p) return PSCA_ENOMEM;
   p->device = ctx->device;
   p->ws = p->dimg = nullptr;
-  if ((rc = make_batch_plan(B, problems, T, cap, p->plan, -1)) != PSCA_OK) {
+  if ((rc = make_plan(B, problems, T, cap, p->plan, -1)) != PSCA_OK) {
     delete p;
     return rc;
   }

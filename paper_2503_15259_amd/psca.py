@@ -75,10 +75,10 @@ class Context:
             self._lib.psca_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP calls while the interpreter shuts down: the runtime (or a
         # profiler attached to it) may already be finalising
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -347,7 +347,9 @@ class Plan:
             self.ctx._lib.psca_plan_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
         try:
             self.close()
         except Exception:

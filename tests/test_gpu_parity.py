@@ -528,3 +528,88 @@ def test_large_scale_workload_size(P):
         print(label(inst, variant, iters), flush=True)
         got = run_gpu(P, inst, variant, iters)
         assert_parity(got, ref, variant, label(inst, variant, iters))
+
+
+def _large_case(P, inst, variant, iters):
+    Sh = P.sample_cov(c64(inst.Y))
+    prm = params_for(P, inst, variant, iters)
+    status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+    return P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=prm, status=status)
+
+
+@pytest.mark.parametrize("team", [0, 1, 2, 5])
+def test_large_pilot_length_batch_matches_oracle_and_single_calls(P, team):
+    """Batches with 97 <= L <= 256 (Sigma factored in memory by each
+    instance's team): instances of different L, N, M, variant and iteration
+    count in one persistent launch, on default and forced team sizes (a team
+    of one workgroup holds every tile and column block of its instance).
+    Each result meets the oracle bar and agrees with the same instance run
+    alone to the same bar."""
+    cases = [(O.ML_K, I.make_instance(5, 31, 300, 97, 32, 0.2).fp32_inputs(), 12),
+             (O.ML_UD, I.make_instance(5, 32, 1000, 130, 64, 0.1).fp32_inputs(), 9),
+             (O.MAP_UR, I.make_instance(5, 33, 777, 200, 256, 0.1).fp32_inputs(), 8),
+             (O.MAP_K, I.make_instance(5, 34, 129, 256, 40, 0.2).fp32_inputs(), 7),
+             (O.ML_K, I.make_instance(5, 35, 33, 113, 16, 0.3).fp32_inputs(), 10)]
+    probs = [_large_case(P, inst, v, it) for v, inst, it in cases]
+    for pb, (v, inst, _) in zip(probs, cases):
+        if v == O.MAP_K:
+            pb.params.p = f32(np.full(inst.N, inst.p))
+    singles = [P.detect(pb.Sigma_hat, pb.S, pb.params) for pb in probs]
+    print(f"[large-L batch, team {team}]", flush=True)
+    if team == 0:
+        outs = P.detect_batch(probs)
+    else:
+        plan = P.Plan(probs, team_size=team)
+        assert plan.team_size == team
+        outs = plan.launch()
+    torch.cuda.synchronize()
+    for (variant, inst, iters), pb, x, xs in zip(cases, probs, outs, singles):
+        assert int(pb.status.item()) == 0
+        ref = O.psca(O.problem_from_instance(inst, variant, eps=EPS), iters)
+        got = x.cpu().numpy().astype(np.float64)
+        assert_parity(got, ref, variant, f"large batch team={team} " + label(inst, variant, iters))
+        assert_parity(got, xs.cpu().numpy().astype(np.float64), variant, "large batch vs single " +
+                      label(inst, variant, iters))
+    if team:
+        plan.close()
+
+
+def test_large_pilot_length_batch_validation(P):
+    small = I.make_instance(5, 36, 50, 64, 16, 0.2).fp32_inputs()
+    big = I.make_instance(5, 37, 50, 100, 16, 0.2).fp32_inputs()
+    probs = [_large_case(P, small, O.ML_UD, 3), _large_case(P, big, O.ML_UD, 3)]
+    with pytest.raises(P.PscaError) as e:   # one launch takes one of the two kernels
+        P.detect_batch(probs)
+    assert e.value.code == -5
+    with pytest.raises(P.PscaError) as e:   # large-L plans take uniform teams only
+        P.Plan(probs[1:], team_size=-64)
+    assert e.value.code == -1
+
+
+def test_large_pilot_length_iterate_and_network_forward(P):
+    """One iteration from a mid-trajectory point at L = 200 (q, q - r and
+    x~ against the oracle), and a network forward with explicit step sizes
+    whose recorded iterates follow the oracle's."""
+    inst = I.make_instance(5, 38, 2000, 200, 256, 0.05).fp32_inputs()
+    prob = O.problem_from_instance(inst, O.ML_K, eps=EPS)
+    x8 = O.psca(prob, 8)
+    rho = 0.37
+    rec = O.psca_iteration(prob, x8, rho)
+    Sh = P.sample_cov(c64(inst.Y))
+    xn, q, r, xt = P.iterate(Sh, c64(inst.S), f32(x8), rho, params_for(P, inst, O.ML_K, 1))
+    torch.cuda.synchronize()
+    qg = q.cpu().numpy().astype(np.float64)
+    qmr = qg - r.cpu().numpy().astype(np.float64)
+    q_err = float(np.max(np.abs(qg - rec.q) / np.abs(rec.q)))
+    qmr_err = float(np.max(np.abs(qmr - (rec.q - rec.r)) / np.abs(rec.q)))
+    print(f"L=200 iterate: q {q_err:.2e}, (q - r) / q {qmr_err:.2e}", flush=True)
+    assert q_err < 1e-5 and qmr_err < 1e-5
+    assert_parity(xt.cpu().numpy(), rec.x_tilde, O.ML_K, "L=200 x~")
+    assert_parity(xn.cpu().numpy(), rec.x_next, O.ML_K, "L=200 x+")
+    rhos = np.array([0.5, 0.7, 0.3, 0.45, 0.6, 0.2], dtype=np.float32)
+    prm = params_for(P, inst, O.ML_K, len(rhos))
+    prm.rho = f32(rhos)
+    hist = P.net_forward(Sh, c64(inst.S), prm).cpu().numpy().astype(np.float64)
+    _, recs = O.psca(prob, len(rhos), rho=rhos.astype(np.float64), record=True)
+    for k, rc in enumerate(recs):
+        assert_parity(hist[k + 1], rc.x_next, O.ML_K, f"L=200 network layer {k}")
