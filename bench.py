@@ -3,12 +3,19 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
-Workload: single-instance PSCA at N = 1000 devices, pilot length L = 64,
-M = 128 antennas, activity p = 0.1, 100 iterations, all four estimators
-(ML-K, MAP-K, ML-UD, MAP-UR).  One step detects four instances, one per
-estimator, each from its received pilots Y (the sample covariance is formed
-inside the timed region); the four detections run concurrently in one batched
-launch.  Inputs live in HBM before timing starts.
+Default workload (--workload large): the large-scale configuration, a batch
+of 64 instances with N = 10^4 devices, pilot length L = 200, M = 256
+antennas, activity p = 0.05.  One step detects all 64 with the unrolled ML-K
+network (20 layers, trained step sizes) from their received pilots Y: the
+sample covariances, then one persistent launch of the whole batch.  The line
+also reports plain ML-K PSCA at the iteration count k* where its pooled
+equal-error rate (P_MD = P_FA) first reaches the network's, and plain PSCA
+with 200 iterations for ML-K and MAP-UR, each batch in one launch.  Inputs
+live in HBM before timing starts.
+
+--workload single: the four estimators on N = 1000, L = 64, M = 128 (one
+instance each, one launch per step); uneven, net and train: the uneven
+batch, the network at N = 1000, and one training step.
 
 Prints one JSON line (see the keys at the end of main()).
 """
@@ -250,12 +257,97 @@ def run_uneven(args):
 
 
 # ---------------------------------------------------------------------------
-# Large scale: N = 10^4 devices, L = 200, M = 256, one detection per launch;
-# plain PSCA (ML-K and MAP-UR, 200 iterations) and the unrolled ML-K network
-# against ML-K PSCA at the same equal-error rate
+# Large scale (the default): a batch of 64 instances at N = 10^4 devices,
+# L = 200, M = 256, p = 0.05; the unrolled ML-K network (K = 20) against
+# plain PSCA at the same equal-error rate (P_MD = P_FA), and plain PSCA with
+# 200 iterations for ML-K and MAP-UR, each batch in one persistent launch
 # ---------------------------------------------------------------------------
-LARGE_POOL = 4      # instances cycled by the timed PSCA-200 launches
-LARGE_EVAL = 16     # instances of the equal-error comparison (seeds disjoint from training)
+LARGE_BATCH = 64      # instances per batch: seeds [4, i], i < 64
+LARGE_CPU_SAMPLE = 4  # instances 0..3: the oracle's sample
+# HBM bytes per k_psca_large_teams launch of the network over the batch
+# (64 instances x 20 layers, teams of 4 workgroups) from the FETCH_SIZE and
+# WRITE_SIZE counter passes, each scaled by the copy-kernel calibration
+# (profile k_psca_large_teams_net20_N10000_L200_x64_traffic.md).  Keyed by
+# team size; other team sizes report null.
+LARGE_TRAFFIC_BYTES_PER_LAUNCH = {4: 219800000000}
+
+
+def _large_net_oracle_task(args):
+    """The unrolled network's forward pass by the FP64 oracle on the inputs
+    the GPU receives (FP32 casts), one instance."""
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    index, rhos = args
+    import oracle as O
+    from paper_2503_15259_amd import instances as I
+    inst = I.workload_instance("large", index).fp32_inputs()
+    t0 = time.perf_counter()
+    prob = O.problem_from_instance(inst, O.ML_K, eps=EPS)   # includes SigmaHat
+    x = O.net_forward(prob, rhos)[-1]
+    return index, time.perf_counter() - t0, x
+
+
+def _large_net_steps_task(args):
+    """One oracle iteration from every recorded GPU iterate of the network
+    (layer k with its step size) against the GPU's next iterate: the worst
+    |alpha error| over the layers."""
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    index, rhos, hist = args
+    import numpy as np
+    import oracle as O
+    from paper_2503_15259_amd import instances as I
+    prob = O.problem_from_instance(I.workload_instance("large", index).fp32_inputs(), O.ML_K, eps=EPS)
+    worst = 0.0
+    for k, rho in enumerate(rhos):
+        rec = O.psca_iteration(prob, hist[k].astype(np.float64), float(rho))
+        worst = max(worst, float(np.max(np.abs(hist[k + 1].astype(np.float64) - rec.x_next))))
+    return index, worst
+
+
+def large_cpu_baseline(rhos):
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(LARGE_CPU_SAMPLE, cores))
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_large_net_oracle_task, [(i, list(rhos)) for i in range(LARGE_CPU_SAMPLE)])
+    wall = time.perf_counter() - t0
+    info = {"value": round(LARGE_CPU_SAMPLE / wall, 5), "unit": "instances/s", "cores": workers, "kind": "oracle",
+            "sample": (f"{LARGE_CPU_SAMPLE} instances of the batch (seeds [4, 0..{LARGE_CPU_SAMPLE - 1}]), the "
+                       f"network's {len(rhos)} layers with the trained step sizes, FP64 NumPy oracle (SigmaHat "
+                       f"included), one single-threaded process per instance"),
+            "s_per_instance_1core": round(sum(r[1] for r in res) / len(res), 3), "wall_s": round(wall, 3),
+            "cpu": _cpu_model()}
+    return info, {r[0]: r[2] for r in res}
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def copy_probe(dev, mib):
+    """One plain copy kernel of known size (reads and writes mib MiB), for
+    scaling the HBM byte counters of a profiler pass."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
 
 
 def run_large(args):
@@ -265,94 +357,183 @@ def run_large(args):
     from paper_2503_15259_amd import metrics
     from paper_2503_15259_amd import psca as P
 
+    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20.json")) as f:
+        trained = json.load(f)
+    K = trained["K"]
+    cpu_info, cpu_x = (None, {})
+    if not args.no_cpu_baseline:
+        cpu_info, cpu_x = large_cpu_baseline(trained["rho"])
+        progress(f"oracle sample done: {cpu_info['wall_s']} s")
+
     if not torch.cuda.is_available():
         sys.exit("bench.py needs a GPU")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     w = I.WORKLOADS["large"]
     N, L, M, iters = w["N"], w["L"], w["M"], w["iters"]
-    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20.json")) as f:
-        trained = json.load(f)
-    K = trained["K"]
+    B = LARGE_BATCH
     rho_net = torch.tensor(trained["rho"], dtype=torch.float32, device=dev)
     ctx = P.Context(0)
     stream = torch.cuda.current_stream(dev)
 
-    def upload(inst):
-        S = P.colmajor(torch.from_numpy(inst.S.astype(np.complex64)).to(dev))
-        Y = P.colmajor(torch.from_numpy(inst.Y.astype(np.complex64)).to(dev))
-        g = torch.from_numpy(inst.g.astype(np.float32)).to(dev)
-        return P.sample_cov(Y, ctx=ctx), S, g, inst
+    insts = [I.workload_instance("large", i) for i in range(B)]
+    progress(f"{B} instances drawn")
+    Ys = [P.colmajor(torch.from_numpy(x.Y.astype(np.complex64)).to(dev)) for x in insts]
+    Ss = [P.colmajor(torch.from_numpy(x.S.astype(np.complex64)).to(dev)) for x in insts]
+    gs = [torch.from_numpy(x.g.astype(np.float32)).to(dev) for x in insts]
+    shs = [torch.empty((L, L), dtype=torch.complex64, device=dev).mT for _ in range(B)]
+    for Y, sh in zip(Ys, shs):
+        P.sample_cov(Y, ctx=ctx, out=sh)
+    truth = np.concatenate([x.alpha for x in insts])
+    status = torch.zeros(B, dtype=torch.int32, device=dev)
 
-    def params(variant, inst, g, n_iter, rho=None):
+    def params(variant, inst, g, n_iter, rho=None, law=P.DIST_AREA):
         return P.Params(variant=variant, iters=n_iter, sigma2=inst.sigma2, M=M, d_lo=inst.d_lo, d_hi=inst.d_hi,
-                        pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS,
+                        pl_c0=inst.pl_c0, pl_beta=inst.pl_beta, eps=EPS, dist_law=law,
                         g=g if variant == P.ML_K else None, rho=rho)
 
-    def timed(fn, n):
-        for i in range(args.warmup):
-            fn(i)
+    def plan_of(variant, n_iter, rho=None, hist=False, law=P.DIST_AREA):
+        probs = [P.Problem(Sigma_hat=shs[b], S=Ss[b], params=params(variant, insts[b], gs[b], n_iter, rho, law),
+                           status=status[b:b + 1],
+                           hist=torch.empty((n_iter + 1, N), dtype=torch.float32, device=dev) if hist else None)
+                 for b in range(B)]
+        return P.Plan(probs, team_size=args.team_size, ctx=ctx), probs
+
+    def timed(plan, n, with_cov=False):
+        """Mean ms of n launches (HIP events on the launch stream) after the warm-ups."""
+        def once():
+            if with_cov:
+                for Y, sh in zip(Ys, shs):
+                    P.sample_cov(Y, ctx=ctx, out=sh)
+            plan.launch()
+        for _ in range(args.warmup):
+            once()
         torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
-        for i, (a, b) in enumerate(ev):
+        for a, b in ev:
             a.record(stream)
-            fn(i)
+            once()
             b.record(stream)
         torch.cuda.synchronize()
         return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
-    # equal-error rates of the network and of ML-K PSCA after every k <= 200
-    evals = [upload(I.workload_instance("large", 1000 + i)) for i in range(LARGE_EVAL)]
-    truth = np.concatenate([e[3].alpha for e in evals])
-    net_scores, hists = [], []
-    for Sh, S, g, inst in evals:
-        net_scores.append(P.net_forward(Sh, S, params(P.ML_K, inst, g, K, rho_net), ctx=ctx)[-1].cpu().numpy())
-        hists.append(P.net_forward(Sh, S, params(P.ML_K, inst, g, iters), ctx=ctx).cpu().numpy())
-    eer_net = metrics.equal_error_point(np.concatenate(net_scores), truth)[0]
-    eer_psca = [metrics.equal_error_point(np.concatenate([h[k] for h in hists]), truth)[0]
-                for k in range(1, iters + 1)]
+    def check_status(what):
+        bad = int((status != 0).sum().item())
+        if bad:
+            sys.exit(f"{what}: {bad} instances reported a device failure: {status.cpu().tolist()}")
+
+    # equal-error rates: the network, and ML-K PSCA after every k <= 200
+    net_plan, _ = plan_of(P.ML_K, K, rho_net)
+    net_out = torch.cat(net_plan.launch()).cpu().numpy()
+    check_status("network")
+    eer_net = metrics.equal_error_point(net_out, truth)[0]
+    hist_plan, hist_probs = plan_of(P.ML_K, iters, hist=True)
+    hist_plan.launch()
+    torch.cuda.synchronize()
+    check_status("PSCA-200 with iterates")
+    hists = np.stack([pb.hist.cpu().numpy() for pb in hist_probs])     # [B, iters + 1, N]
+    hist_plan.close()
+    del hist_probs
+    eer_psca = [metrics.equal_error_point(hists[:, k, :].ravel(), truth)[0] for k in range(1, iters + 1)]
+    del hists
+    progress("equal-error rates of the network and of PSCA-1..200 done")
     matched = [k for k in range(1, iters + 1) if eer_psca[k - 1] <= eer_net]
     k_star = matched[0] if matched else iters
+    kstar_plan, _ = plan_of(P.ML_K, k_star)
+    mlk_plan, _ = plan_of(P.ML_K, iters)
+    mur_plan, mur_probs = plan_of(P.MAP_UR, iters)
+    mur_out = torch.cat(mur_plan.launch()).cpu().numpy()
+    check_status("MAP-UR PSCA-200")
+    mur_lin_plan, _ = plan_of(P.MAP_UR, iters, law=P.DIST_LINEAR)
+    mur_lin_out = torch.cat(mur_lin_plan.launch()).cpu().numpy()
+    check_status("MAP-UR PSCA-200, uniform-in-d law")
+    mur_lin_plan.close()
 
-    # timings: one detection per launch, inputs resident in HBM
-    pool = evals[:LARGE_POOL]
-    res = {}
-    for name, variant in (("ML-K", P.ML_K), ("MAP-UR", P.MAP_UR)):
-        res[name] = timed(lambda i, v=variant: P.detect(pool[i % LARGE_POOL][0], pool[i % LARGE_POOL][1],
-                                                        params(v, pool[i % LARGE_POOL][3], pool[i % LARGE_POOL][2],
-                                                               iters), ctx=ctx), args.steps)
-    ms_k_star = timed(lambda i: P.detect(pool[i % LARGE_POOL][0], pool[i % LARGE_POOL][1],
-                                         params(P.ML_K, pool[i % LARGE_POOL][3], pool[i % LARGE_POOL][2], k_star),
-                                         ctx=ctx), args.steps)
-    ms_net = timed(lambda i: P.net_forward(pool[i % LARGE_POOL][0], pool[i % LARGE_POOL][1],
-                                           params(P.ML_K, pool[i % LARGE_POOL][3], pool[i % LARGE_POOL][2], K, rho_net),
-                                           ctx=ctx), args.steps)
-    ms = float(np.mean(list(res.values())))
-    flops = iters * iteration_flops(N, L)
-    achieved = flops / (ms / 1e3) / 1e12
+    progress("timing")
+    # timings: inputs resident in HBM; the network's step includes SigmaHat
+    # of every instance from its Y
+    ms_kstar = timed(kstar_plan, max(2, args.steps // 4))
+    ms_mlk = timed(mlk_plan, 2)
+    ms_mur = timed(mur_plan, 2)
+    launch_ms = timed(net_plan, args.steps)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        for Y, sh in zip(Ys, shs):
+            P.sample_cov(Y, ctx=ctx, out=sh)
+        net_plan.launch()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    check_status("timed network steps")
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+    value = B / (ms_step / 1e3)
+    if args.copy_probe_mib > 0:
+        copy_probe(dev, args.copy_probe_mib)
+
+    parity = None
+    if cpu_x:
+        # the network's output against the oracle's, and its layers one at a
+        # time (the oracle's layer from each recorded GPU iterate): this
+        # network's trajectory amplifies per-layer rounding, so the output
+        # error exceeds the per-layer one
+        S4 = list(range(LARGE_CPU_SAMPLE))
+        probs4 = [P.Problem(Sigma_hat=shs[b], S=Ss[b], params=params(P.ML_K, insts[b], gs[b], K, rho_net),
+                            status=status[b:b + 1], hist=torch.empty((K + 1, N), dtype=torch.float32, device=dev))
+                  for b in S4]
+        plan4 = P.Plan(probs4, team_size=args.team_size if args.team_size > 0 else 4, ctx=ctx)
+        plan4.launch()
+        torch.cuda.synchronize()
+        check_status("network, recorded layers")
+        hists4 = [pb.hist.cpu().numpy() for pb in probs4]
+        plan4.close()
+        out_err = max(float(np.max(np.abs(hists4[i][-1].astype(np.float64) - cpu_x[i]))) for i in S4)
+        with mp.get_context("spawn").Pool(len(S4)) as pool:
+            steps = pool.map(_large_net_steps_task, [(i, trained["rho"], hists4[i]) for i in S4])
+        parity = {"network ML-K": {"max_abs_err_alpha_per_layer": max(w for _, w in steps),
+                                   "max_abs_err_alpha_output": out_err, "instances_compared": len(S4),
+                                   "bar": 1e-4}}
+
+    flops = B * K * iteration_flops(N, L)
+    achieved = flops / (launch_ms / 1e3) / 1e12
+    team = net_plan.team_size
     tr = trained["train"]
     line = {
-        "metric": METRIC, "value": round(1e3 / ms_net, 4), "unit": "instances/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_net, 3), "higher_is_better": True,
+        "metric": METRIC, "value": round(value, 3), "unit": "instances/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"large-scale detection, one instance per launch: N={N}, L={L}, M={M}, "
-                               f"p={w['p']}; unrolled ML-K network (K={K}, step sizes trained at "
-                               f"N={tr['N']}, L={tr['L']}, M={tr['M']}, p={tr['p']}) against ML-K PSCA at the "
-                               f"same equal-error rate; plain PSCA-{iters} for ML-K and MAP-UR",
-                   "N": N, "L": L, "M": M, "iters": iters, "K": K, "eval_instances": LARGE_EVAL},
+        "config": {"workload": f"large-scale detection: a batch of {B} instances, N={N}, L={L}, M={M}, "
+                               f"p={w['p']}; unrolled ML-K network (K={K} layers, trained step sizes) against "
+                               f"ML-K PSCA at the same equal-error rate (P_MD = P_FA), plain PSCA-{iters} for "
+                               f"ML-K and MAP-UR; each batch in one persistent launch; a step is SigmaHat of "
+                               f"every instance plus the network's launch",
+                   "N": N, "L": L, "M": M, "p": w["p"], "batch": B, "iters": iters, "K": K, "team_size": team,
+                   "net_trained_at": {k: tr[k] for k in ("N", "L", "M", "p", "steps", "batch", "lr")}},
         "equal_error": {"net": round(eer_net, 5), "psca_at_k_star": round(eer_psca[k_star - 1], 5),
-                        f"psca_{iters}": round(eer_psca[iters - 1], 5), "k_star": k_star, "matched": bool(matched)},
-        "net_ms": round(ms_net, 3),
-        "psca_at_k_star_instances_per_s": round(1e3 / ms_k_star, 4),
-        f"psca_{iters}_instances_per_s": {k: round(1e3 / v, 4) for k, v in res.items()},
-        "net_speedup_vs_psca_at_k_star": round(ms_k_star / ms_net, 3),
+                        f"psca_{iters}": round(eer_psca[iters - 1], 5), "k_star": k_star, "matched": bool(matched),
+                        f"map_ur_psca_{iters}": round(metrics.equal_error_point(mur_out, truth)[0], 5),
+                        f"map_ur_psca_{iters}_uniform_in_d_prior":
+                            round(metrics.equal_error_point(mur_lin_out, truth)[0], 5)},
+        "net_instances_per_s": round(value, 3),
+        "psca_at_k_star_instances_per_s": round(B / (ms_kstar / 1e3), 3),
+        f"psca_{iters}_instances_per_s": {"ML-K": round(B / (ms_mlk / 1e3), 3),
+                                          "MAP-UR": round(B / (ms_mur / 1e3), 3)},
+        "net_speedup_vs_psca_at_k_star": round(ms_kstar / launch_ms, 3),
+        "map_ur_prior": "distance law of eq. dispdf (area-uniform) while the instances are drawn uniform in d; "
+                        "the uniform-in-d prior's equal-error rate is reported beside it",
+        "parity_vs_oracle": parity,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6), "traffic": None,
-                     "kernel": f"k_psca_large (PSCA-{iters}, ML-K and MAP-UR)", "flops_per_launch": flops,
-                     "avg_launch_ms": round(ms, 3)},
-        "cpu_baseline": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 6),
+                     "traffic": LARGE_TRAFFIC_BYTES_PER_LAUNCH.get(team),
+                     "kernel": f"k_psca_large_teams (network: {B} instances x {K} layers, one launch)",
+                     "flops_per_launch": flops, "avg_launch_ms": round(launch_ms, 4),
+                     "algorithmic_bytes_per_launch": B * launch_bytes(N, L)},
+        "cpu_baseline": cpu_info,
     }
     print(json.dumps(line), flush=True)
+    for pl in (net_plan, kstar_plan, mlk_plan, mur_plan):
+        pl.close()
     ctx.close()
 
 
@@ -541,13 +722,14 @@ def run_train(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain copy kernel of this many MiB (profiler calibration)")
-    ap.add_argument("--workload", choices=["single", "uneven", "net", "large", "train"], default="single",
-                    help="single: the four estimators on N=1000, L=64 (default); uneven: a batch of "
+    ap.add_argument("--workload", choices=["large", "single", "uneven", "net", "train"], default="large",
+                    help="large (default): 64 instances at N=10^4, L=200, the unrolled network against PSCA at "
+                         "matched P_MD = P_FA; single: the four estimators on N=1000, L=64; uneven: a batch of "
                          "independent ML-UD instances of mixed sizes in one persistent launch")
     ap.add_argument("--instances", type=int, default=4096, help="uneven workload: instances per batch")
     ap.add_argument("--batch", type=int, default=512, help="train workload: instances per minibatch")
@@ -667,13 +849,7 @@ def main():
     value = 4.0 * args.steps / (total_ms / 1e3)
 
     if args.copy_probe_mib > 0:
-        # a plain copy kernel of known size (read n bytes, write n bytes), for
-        # scaling the HBM byte counters of a profiler pass
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
+        copy_probe(dev, args.copy_probe_mib)
 
     # detection quality at the equal-error point, one pass over the pool
     eer = {}

@@ -1422,20 +1422,14 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
 // Pilot lengths 97..256: the L x L matrices no longer fit a workgroup's LDS
 // beside an S tile, so Sigma, its factor L and Sigma - SigmaHat live in
 // device memory (packed lower 16x16 blocks) and the factorisation is spread
-// over the instance's workgroups.  Block step J: every workgroup factors the
-// diagonal block J redundantly in registers and keeps W_JJ = L_JJ^-1 in LDS;
-// the trailing updates A_IK -= L_IJ L_KJ^H are spread over all wavefronts
-// of the instance, each forming the panel blocks L_IJ = A_IJ W_JJ^H it
-// needs, with one device-wide barrier per block step.  Each workgroup then
-// solves its own tile, Y = L^-1 S_t (q = |y|^2) and B = L^-H Y, one
-// wavefront per 16-column block, and forms q - r = b^H (Sigma - SigmaHat) b,
-// the difference taken in phase B from the FP64 sum.
-
-struct LargeArgs {
-  CoopArgs c;             // sigma: packed Sigma, updated in place by the trailing steps
-  float2 *delta;          // packed Sigma - SigmaHat of the iteration
-  float2 *lbuf;           // packed off-diagonal blocks of the factor L
-};
+// over the instance's team of workgroups.  Block step J: every workgroup
+// factors the diagonal block J redundantly in registers and keeps
+// W_JJ = L_JJ^-1 in LDS; the trailing updates A_IK -= L_IJ L_KJ^H are spread
+// over all wavefronts of the team, each forming the panel blocks
+// L_IJ = A_IJ W_JJ^H it needs, with one team barrier per block step.  The
+// solves Y = L^-1 S (q = |y|^2), B = L^-H Y and q - r = b^H (Sigma - SigmaHat) b
+// (the difference taken in phase B from the FP64 sum) then run per 16-column
+// block in registers (k_psca_large_teams below).
 
 // Touches n float2 at p (16-byte loads spread over `nthreads` threads from
 // thread `t`) so that a later pass finds them in this XCD's L2; the loaded
@@ -1456,52 +1450,6 @@ __device__ __forceinline__ void cmfma3(float2 a, float2 b, f4 &t1, f4 &t2, f4 &t
   t1 = mfma4(a.x, b.x, t1);
   t2 = mfma4(a.y, b.y, t2);
   t3 = mfma4(a.x + a.y, b.x + b.y, t3);
-}
-
-// Gauss accumulators (t1, t2, t3) += the 16x16 block products get(q) returns
-// for q in [q0, q1), four blocks at a time so that their loads are in flight
-// together.
-template <class Get>
-__device__ __forceinline__ void block_sum_gauss(int q0, int q1, f4 &t1, f4 &t2, f4 &t3, Get get) {
-  for (int q = q0; q < q1; q += 4) {
-    float2 a4[4][4], b4[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (q + u < q1) get(q + u, a4[u], b4[u]);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (q + u < q1) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma3(a4[u][ks], b4[u][ks], t1, t2, t3);
-      }
-  }
-}
-
-// acc += A B over a run of 16x16 blocks, operands fetched four blocks at a
-// time so that their loads are in flight together.  get(q, a4, b4) fills
-// the operands of term q.
-template <typename Get>
-__device__ __forceinline__ void block_sum(int q0, int q1, int qs, f4 &cr, f4 &ci, Get get) {
-  for (int q = q0; q < q1; q += 4 * qs) {
-    float2 a4[4][4], b4[4][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (q + u * qs < q1) get(q + u * qs, a4[u], b4[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (q + u * qs < q1) {
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) cmfma(a4[u][ks], b4[u][ks], cr, ci);
-      }
-    }
-  }
-}
-
-__host__ __device__ inline size_t lds_large_bytes(int Lp, int NT, int waves) {
-  const size_t f2 = (size_t)Lp * (NT + 1) + (size_t)(Lp / 16) * 256 + (size_t)waves * 256;
-  const size_t fl = 3 * (size_t)NT + 2 * (size_t)(Lp / 16) * NT;
-  return f2 * sizeof(float2) + fl * 4;
 }
 
 __device__ __forceinline__ const float2 *pblk(const float2 *packed, int I, int J) {
@@ -1702,246 +1650,6 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
   return res;
 }
 
-template <int THREADS>
-__device__ __forceinline__ void large_body(const LargeArgs &Lg, const int g) {
-  const CoopArgs &A = Lg.c;
-  constexpr int kWaves = THREADS / 64;
-  extern __shared__ float4 smem_raw[];
-  __shared__ int s_ok, s_pd;
-  const int Lp = (A.L + 15) & ~15, Lb = Lp / 16, NB = Lb * (Lb + 1) / 2, E = NB * 256;
-  const int NT = A.NT, PT = A.NT + 1, ncb = A.ncb;
-  float2 *Yt = (float2 *)smem_raw;     // [Lp][PT] tile: S, then Y = L^-1 S, then B = L^-H Y
-  float2 *Wd = Yt + Lp * PT;           // [Lb][256] W_JJ, column-major blocks
-  float2 *scr = Wd + Lb * 256;         // [kWaves][256]
-  float *xs = (float *)(scr + kWaves * 256);
-  float *gs = xs + NT, *ls = gs + NT;
-  float *red_q = ls + NT;              // [Lb][NT]
-  float *red_r = red_q + Lb * NT;      // [Lb][NT]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lq = lane >> 4;
-  const int n0 = g * NT;
-  const int gwave = g * kWaves + wave, nwaves = A.G * kWaves;
-  unsigned gen = 0;
-  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K || A.a.variant == PSCA_MAP_K2);
-  const bool pairs = (A.a.variant == PSCA_MAP_K2);
-  float2 *sig = A.sigma;
-
-  for (int c = tid; c < NT; c += THREADS) {
-    const int n = n0 + c;
-    const bool in = n < A.N;
-    xs[c] = (in && A.x_in) ? A.x_in[n] : 0.0f;
-    if (in && A.x_hist) A.x_hist[n] = xs[c];
-    gs[c] = (in && A.a.g) ? A.a.g[n] : 0.0f;
-    float lg = 0.0f;
-    if (in && A.a.p) {
-      const float pn = A.a.p[n];
-      lg = logf(pn / (1.0f - pn));
-    }
-    if (in && pairs) {
-      lg = A.a.c1[n];
-      A.a.xg[n] = xs[c];   // x^(0), read after the first barrier
-    }
-    ls[c] = lg;
-  }
-  auto s_at = [&](int i, int c) -> float2 {   // S element (row i, tile column c), zero outside
-    const int n = n0 + c;
-    return (i < A.L && n < A.N) ? A.S[(size_t)n * A.L + i] : make_float2(0.f, 0.f);
-  };
-
-  double rho_d = A.rho0;
-  bool failed = false, aborted = false;
-  for (int it = 0; it < A.iters; ++it) {
-    // ---- A. packed Gram partial of the tile; the S tile is staged in Yt,
-    // where it stays until the solves of C4 overwrite it
-    PSCA_MARK(it, 0);
-    for (int c = tid; c < NT; c += THREADS) red_q[c] = known ? gs[c] * xs[c] : xs[c];
-    {
-      constexpr int kU = 8;   // loads in flight per thread
-      const int tot = Lp * NT;
-      for (int e0 = tid; e0 < tot; e0 += kU * THREADS) {
-        float2 v[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;   // down a column: coalesced
-          v[u] = e < tot ? s_at(i, c) : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;
-          if (e < tot) Yt[i * PT + c] = v[u];
-        }
-      }
-    }
-    __syncthreads();
-    gram_tile_fp64<THREADS>(Yt, PT, ncb, red_q, NB, A.partials + (size_t)g * A.pstride);
-    PSCA_MARK(it, 1);
-    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
-
-    // ---- B. reduce a slice into Sigma and its copy
-    PSCA_MARK(it, 2);
-    reduce_sigma_slice<THREADS>(A, Lg.delta, A.G, A.G, g, (double2 *)scr);
-    PSCA_MARK(it, 3);
-    if (!grid_sync(A.bar, A.G, g, gen, &s_ok)) { aborted = true; break; }
-
-    // ---- C1. cooperative blocked Cholesky in memory
-    PSCA_MARK(it, 4);
-    {
-      const int f = factor_in_memory<THREADS>(A, Lg.delta, Lg.lbuf, Wd, scr, A.G, g, gen, &s_ok, &s_pd);
-      failed = f == 1;
-      aborted = f == 2;
-    }
-    if (failed || aborted) break;
-
-    // ---- C4. local solves Y = L^-1 S_t (q = |y|^2), then B = L^-H Y, in place
-    // of the S tile.  The column blocks of the tile are independent, so each
-    // is solved by one wavefront from top to bottom and back with no
-    // workgroup barrier; a block row's products fetch four blocks at a time,
-    // then the diagonal W_RR (or W_RR^H) applies through a 16x16 stage.
-    PSCA_MARK(it, 5);   // Yt still holds the S tile of phase A
-    warm_l2(Lg.lbuf, E, tid, THREADS);   // the factor L, read block by block below
-    for (int cb = wave; cb < ncb; cb += kWaves) {
-      float2 *T = scr + wave * 256;   // row-major stage
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int r = 0; r < Lb; ++r) {
-          const int R = pass == 0 ? r : Lb - 1 - r;
-          f4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
-          if (pass == 0) {   // sum_{K<R} L_RK Y_K
-            block_sum_gauss(0, R, t1, t2, t3, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-              const float2 *lrk = pblk(Lg.lbuf, R, K);
-#pragma unroll
-              for (int ks = 0; ks < 4; ++ks) {
-                const int k = 4 * ks + lq;
-                a4[ks] = lrk[k * 16 + l16];
-                b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
-              }
-            });
-          } else {           // sum_{K>R} L_KR^H B_K
-            block_sum_gauss(R + 1, Lb, t1, t2, t3, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-              const float2 *lkr = pblk(Lg.lbuf, K, R);
-#pragma unroll
-              for (int ks = 0; ks < 4; ++ks) {
-                const int k = 4 * ks + lq;
-                const float2 x = lkr[l16 * 16 + k];   // L_KR[k][l16]; A = conj of it
-                a4[ks] = make_float2(x.x, -x.y);
-                b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
-              }
-            });
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {   // T = rhs_R - sum
-            const float2 y = Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16];
-            T[(4 * lq + v) * 16 + l16] = make_float2(y.x - (t1[v] - t2[v]), y.y - (t3[v] - t1[v] - t2[v]));
-          }
-          wave_lds_sync();
-          t1 = f4{0.f, 0.f, 0.f, 0.f};
-          t2 = t1;
-          t3 = t1;
-          float2 a4[4], b4[4];
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lq;
-            if (pass == 0) {
-              a4[ks] = Wd[R * 256 + k * 16 + l16];            // W_RR[l16][k]
-            } else {
-              const float2 w = Wd[R * 256 + l16 * 16 + k];    // W_RR[k][l16]; A = conj of it
-              a4[ks] = make_float2(w.x, -w.y);
-            }
-            b4[ks] = T[k * 16 + l16];
-          }
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) cmfma3(a4[ks], b4[ks], t1, t2, t3);
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            Yt[(16 * R + 4 * lq + v) * PT + 16 * cb + l16] = make_float2(t1[v] - t2[v], t3[v] - t1[v] - t2[v]);
-          wave_lds_sync();
-        }
-        if (pass == 0) {   // q of this column block, per row block
-          for (int I = 0; I < Lb; ++I) {
-            float qv = 0.0f;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float2 y = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
-              qv += y.x * y.x + y.y * y.y;
-            }
-            qv += __shfl_xor(qv, 16);
-            qv += __shfl_xor(qv, 32);
-            if (lq == 0) red_q[I * NT + 16 * cb + l16] = qv;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    PSCA_MARK(it, 6);   // both solves: the wavefronts do not meet between them
-    PSCA_MARK(it, 7);
-    PSCA_MARK(it, 8);
-    // q - r = b^H (Sigma - SigmaHat) b, Sigma - SigmaHat from phase B.  The
-    // difference is Hermitian, so b^H D b = sum_I b_I^H D_II b_I
-    // + 2 Re sum_{K<I} b_I^H D_IK b_K: lower blocks only.
-    for (int t = wave; t < Lb * ncb; t += kWaves) {
-      const int I = Lb - 1 - t / ncb, cb = t % ncb;   // longest rows first
-      f4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-      block_sum(0, I + 1, 1, cr, ci, [&](int K, float2 (&a4)[4], float2 (&b4)[4]) {
-        const float2 *dk = pblk(Lg.delta, I, K);
-        const float f = K < I ? 2.0f : 1.0f;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int k = 4 * ks + lq;
-          const float2 x = dk[k * 16 + l16];
-          a4[ks] = make_float2(f * x.x, f * x.y);
-          b4[ks] = Yt[(16 * K + k) * PT + 16 * cb + l16];
-        }
-      });
-      float rp = 0.0f;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float2 bv = Yt[(16 * I + 4 * lq + v) * PT + 16 * cb + l16];
-        rp += bv.x * cr[v] + bv.y * ci[v];
-      }
-      rp += __shfl_xor(rp, 16);
-      rp += __shfl_xor(rp, 32);
-      if (lq == 0) red_r[I * NT + 16 * cb + l16] = rp;
-    }
-    __syncthreads();
-
-    // ---- C5. coordinate step and update
-    PSCA_MARK(it, 9);
-    float rho;
-    if (A.rho_fixed >= 0.0f) rho = A.rho_fixed;
-    else if (A.rho_dev) rho = A.rho_dev[it];
-    else rho = (float)rho_d;
-    rho_d = rho_d * (1.0 - A.rho_decay * rho_d);
-    const bool last = (it == A.iters - 1);
-    for (int c = tid; c < NT; c += THREADS) {
-      const int n = n0 + c;
-      if (n < A.N) {
-        float q = 0.0f, qmr = 0.0f;
-        for (int I = 0; I < Lb; ++I) {
-          q += red_q[I * NT + c];
-          qmr += red_r[I * NT + c];
-        }
-        const float x = xs[c];
-        const float prior = pairs ? ls[c] + pair_sum(A.a, n, A.N, A.a.xg + (size_t)(it & 1) * A.N) : ls[c];
-        const float xt = coordinate_step(x, q, qmr, gs[c], prior, A.a);
-        xs[c] = (1.0f - rho) * x + rho * xt;
-        if (pairs) A.a.xg[(size_t)((it + 1) & 1) * A.N + n] = xs[c];
-        if (A.x_hist) A.x_hist[(size_t)(it + 1) * A.N + n] = xs[c];
-        if (last) {
-          if (A.q_out) A.q_out[n] = q;
-          if (A.r_out) A.r_out[n] = q - qmr;
-          if (A.xt_out) A.xt_out[n] = xt;
-        }
-      }
-    }
-    __syncthreads();
-    PSCA_MARK(it, 10);
-  }
-  for (int c = tid; c < NT; c += THREADS) {
-    const int n = n0 + c;
-    if (n < A.N) A.x_out[n] = xs[c];
-  }
-  if (g == 0 && tid == 0 && A.status) *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
-}
-
-__global__ void __launch_bounds__(512) k_psca_large(LargeArgs Lg) { large_body<512>(Lg, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // Pilot lengths 97..256 on teams of workgroups: k_psca_large_teams
@@ -2669,64 +2377,6 @@ void fill_args(CoopArgs &a, const float2 *Sh, const float2 *S, int L, int N, con
   a.xt_out = xt_out;
   a.x_hist = nullptr;
   a.status = status;
-}
-
-// Pilot lengths above 96: k_psca_large (cooperative factorisation in memory).
-int run_large(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm, int iters,
-              float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out, float *xt_out,
-              int32_t *status, hipStream_t st, float *x_hist) {
-  const int Lp = (L + 15) & ~15;
-  const KernelChoice kc{(const void *)k_psca_large, 512, Lp};
-  InstPlan p{};
-  for (int ncb = 1;; ++ncb) {
-    if (ncb > kMaxNcb) return PSCA_ENOTSUP;
-    const int NT = 16 * ncb, G = (N + NT - 1) / NT;
-    const size_t lds = lds_large_bytes(Lp, NT, 8);
-    if (lds > 159 * 1024) return PSCA_ENOTSUP;
-    const int cap = max_coresident(ctx, kc, lds);
-    if (cap <= 0) return PSCA_ENOTSUP;
-    if (G <= cap) {
-      p = InstPlan{Lp, ncb, NT, G, lds, 0};
-      break;
-    }
-  }
-  const size_t E = (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256;
-  const size_t o_pa = 0;
-  const size_t o_sig = align_up(o_pa + (size_t)p.G * E * sizeof(float2));
-  const size_t o_cp = align_up(o_sig + E * sizeof(float2));
-  const size_t o_lb = align_up(o_cp + E * sizeof(float2));
-  const size_t o_arr = align_up(o_lb + E * sizeof(float2));
-  const size_t o_rel = align_up(o_arr + (size_t)p.G * 16 * sizeof(unsigned));
-  const size_t o_abt = align_up(o_rel + sizeof(unsigned));
-  const size_t o_st = align_up(o_abt + sizeof(unsigned));
-  const size_t o_xg = align_up(o_st + sizeof(unsigned));
-  const size_t total = align_up(o_xg + 2 * (size_t)N * sizeof(float));
-  int rc = ensure_ws(ctx, total);
-  if (rc != PSCA_OK) return rc;
-  char *base = (char *)ctx->ws;
-  LargeArgs a;
-  fill_args(a.c, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
-  a.c.x_hist = x_hist;
-  a.c.partials = (float2 *)(base + o_pa);
-  a.c.pstride = E;
-  a.c.sigma = (float2 *)(base + o_sig);
-  a.c.bar.arrive = (unsigned *)(base + o_arr);
-  a.c.bar.release = (unsigned *)(base + o_rel);
-  a.c.bar.abort_flag = (int32_t *)(base + o_abt);
-  if (!a.c.status) a.c.status = (int32_t *)(base + o_st);
-  a.delta = (float2 *)(base + o_cp);
-  a.lbuf = (float2 *)(base + o_lb);
-
-  a.c.a.xg = (float *)(base + o_xg);
-  hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.c.bar.arrive, p.G, a.c.bar.release,
-                     a.c.bar.abort_flag, a.c.status);
-  if ((rc = launch_ok()) != PSCA_OK) return rc;
-  void *args[] = {&a};
-  if (hipLaunchCooperativeKernel(kc.fn, dim3(p.G), dim3(512), args, (unsigned)p.lds, st) != hipSuccess) {
-    (void)hipGetLastError();
-    return PSCA_EHIP;
-  }
-  return PSCA_OK;
 }
 
 int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,

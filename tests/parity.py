@@ -91,6 +91,9 @@ def stepwise_parity(prob, hist_gpu, rhos, delta=BRANCH_DELTA):
         skipped += int((~keep).sum())
         rep = parity_report(hist[k + 1][keep], rec.x_next[keep], prob.variant)
         rep["step"] = k
-        if worst is None or rep["n_bad"] > worst["n_bad"]:
+        err = rep.get("max_abs", rep.get("max_rel_big", 0.0))
+        if worst is None or (rep["n_bad"], err) > (worst["n_bad"], worst.get("max_abs", worst.get("max_rel_big", 0.0))):
             worst = rep
+        if (k + 1) % 25 == 0:
+            print(f"  step-by-step check: {k + 1}/{len(rhos)} steps", flush=True)
     return worst, skipped
