@@ -270,11 +270,6 @@ def test_host_validation_errors(P):
     with pytest.raises(P.PscaError) as e:
         P.detect_y(c64(big.Y), c64(big.S), P.Params(variant=O.ML_UD, iters=5, M=8))
     assert e.value.code == -5
-    mid = I.make_instance(5, 5, 20, 97, 8, 0.2).fp32_inputs()   # batches keep L x L in LDS
-    with pytest.raises(P.PscaError) as e:
-        P.detect_batch([P.Problem(Sigma_hat=P.sample_cov(c64(mid.Y)), S=c64(mid.S),
-                                  params=P.Params(variant=O.ML_UD, iters=5, M=8))])
-    assert e.value.code == -5
 
 
 def test_batch_mixed_instances_match_oracle_and_single_calls(P):
