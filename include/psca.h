@@ -279,6 +279,26 @@ int psca_plan_launch(psca_plan *plan, void *stream);
 int psca_plan_team_size(const psca_plan *plan);
 int psca_plan_destroy(psca_plan *plan);   /* waits for the device; NULL is a no-op */
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * detection as psca_detect (same kernels, tiles and results, bit for bit),
+ * with its work buffers (partials of Sigma, packed Sigma, barrier and status
+ * words) in a fixed array of PSCA_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends; the call makes no
+ * allocation (no hipMalloc, hipFree or allocating library routine).  The
+ * caller passes inputs and outputs as for psca_detect, and `ctx` is only
+ * read (psca_create set the array's device address up).  Limits: L <= 96
+ * (the single-workgroup factorisation), and a problem whose work buffers
+ * exceed the array returns PSCA_ENOTSUP before any launch (the array holds
+ * every L <= 96 detection the library can tile: up to 256 workgroups of
+ * partials).  Every call on one GPU shares that GPU's array and finds the
+ * previous call's contents in it (the barrier and status words are reset by
+ * a kernel at the start of each call): calls that overlap in time on one GPU,
+ * from any context or stream, race and must not be issued. */
+#define PSCA_NOALLOC_SCRATCH_BYTES ((size_t)12 << 20)
+int psca_detect_noalloc(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                        const psca_params *prm, float *x_out, int32_t *status, void *stream);
+
 /* Threshold module: support[n] = (x[n] >= theta) ? 1 : 0 (Sec. III-A). */
 int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *stream);
 

@@ -26,7 +26,7 @@ EXPORTED = (
     "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
     "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold", "psca_detect_batch",
     "psca_autotune_batch", "psca_plan_create", "psca_plan_launch", "psca_plan_team_size", "psca_plan_destroy",
-    "psca_net_forward", "psca_layer_backward", "psca_layer_backward_batch",
+    "psca_net_forward", "psca_layer_backward", "psca_layer_backward_batch", "psca_detect_noalloc",
 )
 
 
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "psca_sample_cov": ([vp, vp, i32, i32, vp, vp], i32),
         "psca_detect": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
         "psca_detect_y": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
+        "psca_detect_noalloc": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
         "psca_iterate": ([vp, vp, vp, i32, i32, P, f32, vp, vp, vp, vp, vp, vp, vp], i32),
         "psca_threshold": ([vp, i32, f32, vp, vp], i32),
         "psca_detect_batch": ([vp, i32, ctypes.POINTER(PscaProblem), vp], i32),

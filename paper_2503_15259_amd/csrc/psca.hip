@@ -39,6 +39,7 @@
 #include <algorithm>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -2164,6 +2165,18 @@ __global__ void k_threshold(const float *__restrict__ x, int N, float theta, uin
 // Host side
 // ---------------------------------------------------------------------------
 
+// Scratch of psca_detect_noalloc: one array per GPU, allocated by the loader
+// with the code object and held until the process ends.  Host code never
+// passes `scratch` itself (a host-side stand-in, not a device address): it
+// takes the device address from hipGetSymbolAddress once per device, with
+// that device current, and uses that.
+constexpr size_t kScratchBytes = PSCA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
 struct psca_ctx {
   int device;
   int n_cu;
@@ -2386,8 +2399,10 @@ int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int 
 // Runs k_psca for `iters` iterations from x_in (null: zeros).
 int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, const psca_params *prm,
                int iters, float rho_fixed, const float *x_in, float *x_out, float *q_out, float *r_out,
-               float *xt_out, int32_t *status, hipStream_t st, float *x_hist = nullptr) {
+               float *xt_out, int32_t *status, hipStream_t st, float *x_hist = nullptr, char *fixed_ws = nullptr,
+               size_t fixed_bytes = 0) {
   const int Lp = (L + 15) & ~15;
+  if (fixed_ws && Lp > kMaxLdsL) return PSCA_ENOTSUP;   // the fixed workspace serves L <= 96
   if (Lp > kMaxLdsL)
     return run_large_team(ctx, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, st,
                           x_hist);
@@ -2405,11 +2420,15 @@ int run_detect(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int N, c
     }
   }
   int rc;
-  if ((rc = ensure_ws(ctx, p.ws)) != PSCA_OK) return rc;
+  if (fixed_ws) {
+    if (p.ws > fixed_bytes) return PSCA_ENOTSUP;
+  } else if ((rc = ensure_ws(ctx, p.ws)) != PSCA_OK) {
+    return rc;
+  }
   CoopArgs a;
   fill_args(a, Sh, S, L, N, prm, iters, rho_fixed, x_in, x_out, q_out, r_out, xt_out, status, p);
   a.x_hist = x_hist;
-  bind_ws(a, (char *)ctx->ws, p);
+  bind_ws(a, fixed_ws ? fixed_ws : (char *)ctx->ws, p);
   hipLaunchKernelGGL(k_prepare, dim3(1), dim3(256), 0, st, a.bar.arrive, p.G, a.bar.release, a.bar.abort_flag,
                      a.status);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
@@ -3265,6 +3284,19 @@ int psca_create(psca_ctx **ctx, int device) {
       delete c;
       return PSCA_EHIP;
     }
+    if (device < kMaxDevices) {   // the no-allocation scratch of this device, once
+      std::lock_guard<std::mutex> lock(g_scratch_mu);
+      if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+          (void)hipGetLastError();
+          (void)hipEventDestroy(c->desc_done);
+          delete c;
+          return PSCA_EHIP;
+        }
+        g_scratch_ptr[device] = ptr;
+      }
+    }
   }
   *ctx = c;
   return PSCA_OK;
@@ -3306,6 +3338,19 @@ int psca_detect(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int
   if (!g.ok) return PSCA_EHIP;
   return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr,
                     x_out, nullptr, nullptr, nullptr, status, as_stream(stream));
+}
+
+int psca_detect_noalloc(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
+                        const psca_params *prm, float *x_out, int32_t *status, void *stream) {
+  if (!ctx || !Sigma_hat || !S || !x_out) return PSCA_EINVAL;
+  int rc = validate_params(prm, L, N, true);
+  if (rc != PSCA_OK) return rc;
+  if (ctx->device >= kMaxDevices || !g_scratch_ptr[ctx->device]) return PSCA_EHIP;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PSCA_EHIP;
+  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr,
+                    x_out, nullptr, nullptr, nullptr, status, as_stream(stream), nullptr,
+                    (char *)g_scratch_ptr[ctx->device], kScratchBytes);
 }
 
 int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, int N,

@@ -225,6 +225,29 @@ def detect(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: Option
     return x
 
 
+def detect_noalloc(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, out: torch.Tensor,
+                   ctx: Optional[Context] = None, stream=None, status: Optional[torch.Tensor] = None):
+    """psca_detect_noalloc: psca_detect with the library's fixed per-GPU
+    scratch array (no device allocation in the call; L <= 96).  Sigma_hat
+    and S must already be column-major and `out` given: this wrapper makes
+    no copies.  Calls on one GPU must not overlap in time."""
+    ctx = ctx or default_context(S.device)
+    _need(S, torch.complex64, ctx.device, "S")
+    _need(Sigma_hat, torch.complex64, ctx.device, "Sigma_hat")
+    _need(out, torch.float32, ctx.device, "out")
+    L, n = S.shape
+    if S.stride() != (1, L) or Sigma_hat.shape != (L, L) or Sigma_hat.stride() != (1, L):
+        raise ValueError("S and Sigma_hat must be column-major (see colmajor)")
+    if out.numel() != n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 vector of length N")
+    params.check_tensors(ctx.device, n)
+    c = params.to_c()
+    _on_stream(ctx.device, stream, ())
+    N.check(ctx._lib.psca_detect_noalloc(ctx.handle, _ptr(Sigma_hat), _ptr(S), L, n, ctypes.byref(c), _ptr(out),
+                                         _ptr(status), _stream(ctx.device, stream)), "psca_detect_noalloc")
+    return out
+
+
 def detect_y(Y: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Context] = None,
              stream=None, out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
     """psca_detect_y: SigmaHat from Y (M = Y.shape[1]) then Algorithm 1."""
