@@ -237,8 +237,8 @@ __device__ __forceinline__ float prior_log_ratio_deriv(float x, const StepArgs &
 struct StepDerivs {
   float xt, mask, dq, dr, own, kappa;
 };
-__device__ __forceinline__ StepDerivs step_derivs(float x, float q, float r, float g, float logit,
-                                                  const StepArgs &a) {
+__device__ __forceinline__ StepDerivs step_derivs_qmr(float x, float q, float qmr, float g, float logit,
+                                                      const StepArgs &a) {
   float kappa = 1.0f, c = 0.0f, cp = 0.0f, hi;
   switch (a.variant) {
     case PSCA_ML_K: kappa = g; hi = 1.0f; break;
@@ -250,7 +250,7 @@ __device__ __forceinline__ StepDerivs step_derivs(float x, float q, float r, flo
       hi = a.g_u;
       break;
   }
-  const float grad = kappa * (q - r) - c;
+  const float grad = kappa * qmr - c;
   const float kq = kappa * q;
   const float curv = kq * kq;
   const float pre = x - grad / curv;
@@ -262,6 +262,10 @@ __device__ __forceinline__ StepDerivs step_derivs(float x, float q, float r, flo
   d.own = 1.0f + cp / curv;
   d.kappa = kappa;
   return d;
+}
+__device__ __forceinline__ StepDerivs step_derivs(float x, float q, float r, float g, float logit,
+                                                  const StepArgs &a) {
+  return step_derivs_qmr(x, q, q - r, g, logit, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1491,18 +1495,14 @@ __device__ __forceinline__ void gram_tile_fp64(const float2 *Yt, int PT, int ncb
   }
 }
 
-// Phase B of a detection on T workgroups: workgroup g sums its 1/T slice of
-// packed Sigma over `parts` partial slots (FP64), adds sigma^2 on the
-// diagonal (unit pivots on padding rows) and writes Sigma and
-// Delta = Sigma - SigmaHat (from the FP64 sum) to memory.  dscr: THREADS
-// double2 of LDS.
-template <int THREADS>
-__device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *delta, int parts, int T, int g,
-                                                   double2 *dscr) {
+// Workgroup g of T sums its 1/T slice of the E packed entries over `parts`
+// partial slots (stride pstride) in FP64: Pp threads per entry each sum
+// every Pp-th slot, then one thread per entry adds the Pp sums in LDS and
+// hands the total to store(e, sum).  dscr: THREADS double2 of LDS.
+template <int THREADS, class Store>
+__device__ __forceinline__ void reduce_packed_slice(const float2 *partials, size_t pstride, int parts, int T, int g,
+                                                    int E, double2 *dscr, Store store) {
   const int tid = threadIdx.x;
-  const int Lp = (A.L + 15) & ~15, Lb = Lp / 16, E = Lb * (Lb + 1) / 2 * 256;
-  // Pp threads per element of the slice each sum every Pp-th partial
-  // (double), then one thread per element adds the Pp sums in LDS.
   const int per = (E + T - 1) / T;
   const int start = g * per, end = min(E, start + per), cnt = max(0, end - start);
   const int Pp = cnt > 0 ? max(1, THREADS / cnt) : 1;
@@ -1511,12 +1511,12 @@ __device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *de
     double2 acc = make_double2(0.0, 0.0);
     if (part < Pp && e_loc < cnt) {
       constexpr int kU = 8;   // loads in flight per thread
-      const float2 *src = A.partials + start + e_loc;
+      const float2 *src = partials + start + e_loc;
       int h = part;
       for (; h + (kU - 1) * Pp < parts; h += kU * Pp) {
         float2 v[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v[u] = src[(size_t)(h + u * Pp) * A.pstride];
+        for (int u = 0; u < kU; ++u) v[u] = src[(size_t)(h + u * Pp) * pstride];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           acc.x += v[u].x;
@@ -1524,14 +1524,13 @@ __device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *de
         }
       }
       for (; h < parts; h += Pp) {
-        const float2 v = src[(size_t)h * A.pstride];
+        const float2 v = src[(size_t)h * pstride];
         acc.x += v.x;
         acc.y += v.y;
       }
     }
     dscr[tid] = acc;
     __syncthreads();
-    const int e = start + e0 + tid;
     if (tid < THREADS / Pp && e0 + tid < cnt) {
       double2 sm = make_double2(0.0, 0.0);   // summed in double, rounded once
       for (int q = 0; q < Pp; ++q) {
@@ -1539,20 +1538,34 @@ __device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *de
         sm.x += v.x;
         sm.y += v.y;
       }
-      const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
-      int I, J;
-      blk_coords(b, I, J);
-      if (I == J && ii == jj) {
-        sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
-        sm.y = 0.0;
-      }
-      A.sigma[e] = make_float2((float)sm.x, (float)sm.y);
-      const int i = 16 * I + ii, k = 16 * J + jj;   // Sigma - SigmaHat from the FP64 sum
-      const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
-      delta[e] = make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y));
+      store(start + e0 + tid, sm);
     }
     __syncthreads();
   }
+}
+
+// Phase B of a detection on T workgroups: workgroup g sums its 1/T slice of
+// packed Sigma over `parts` partial slots (FP64), adds sigma^2 on the
+// diagonal (unit pivots on padding rows) and writes Sigma and
+// Delta = Sigma - SigmaHat (from the FP64 sum) to memory.  dscr: THREADS
+// double2 of LDS.
+template <int THREADS>
+__device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *delta, int parts, int T, int g,
+                                                   double2 *dscr) {
+  const int Lp = (A.L + 15) & ~15, Lb = Lp / 16, E = Lb * (Lb + 1) / 2 * 256;
+  reduce_packed_slice<THREADS>(A.partials, A.pstride, parts, T, g, E, dscr, [&](int e, double2 sm) {
+    const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
+    int I, J;
+    blk_coords(b, I, J);
+    if (I == J && ii == jj) {
+      sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
+      sm.y = 0.0;
+    }
+    A.sigma[e] = make_float2((float)sm.x, (float)sm.y);
+    const int i = 16 * I + ii, k = 16 * J + jj;   // Sigma - SigmaHat from the FP64 sum
+    const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
+    delta[e] = make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y));
+  });
 }
 
 // Phase C1 of a detection on T workgroups: blocked Cholesky of packed Sigma
@@ -1719,60 +1732,54 @@ struct Gauss2 {
   }
 };
 
-// One wave: Y = L^-1 S_c (q = sum |y|^2), B = L^-H Y (= Sigma^-1 S_c),
-// q - r = Re b^H (Sigma - SigmaHat) b and the coordinate step of the 16
-// devices c0 .. c0 + 15.  The column block lives in registers in the MFMA
-// output layout: lane (j, h) holds rows 4h .. 4h + 3 of every 16-row block,
-// column j.  Used as the B operand of a 16x16x4 step `ks`, that register
-// set supplies the inner index k = 4h + ks (a permutation of the 16 inner
-// indices over the four steps), so the A operands (blocks of L, W_RR and
-// Sigma - SigmaHat) are read in the same permuted order and no transposition
-// is needed between block rows.  Each pass walks its blocks in a fixed order
-// with the operands of the next two blocks already in flight.
+// Column-block pieces: one wave holds a 16-column block of an L x 16 matrix
+// in registers, y[R][v] = row 16 R + 4 h + v, column j, in lane (j, h) (the
+// MFMA output layout).  Used as the B operand of a 16x16x4 step `ks`, that
+// register set supplies the inner index k = 4h + ks (a permutation of the 16
+// inner indices over the four steps), so the A operands (blocks of L, W_RR,
+// or of a packed Hermitian matrix) are read in the same permuted order and
+// no transposition is needed between block rows.  Each pass walks its
+// blocks in a fixed order with the operands of the next two blocks already
+// in flight (ring of three).  lo_n = 64 h + j: A[j][4h + ks] of a
+// column-major 16x16 block sits at lo_n + 16 ks; lo_t = 16 j + 4 h: A^T at
+// lo_t + ks.
+
+// y = rows of the L x N column-major matrix M for columns c0 .. c0 + 15
+// (zero outside L x N).
 template <int LB>
-__device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, const float2 *Wd, int c0, int it,
-                                                   float rho, bool last) {
-  const CoopArgs &A = Tg.c;
-  const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
-  const int n = c0 + l16;
-  const bool col_in = n < A.N;
-  // The factor and Sigma - SigmaHat are the same for every column block; an
-  // opaque copy of their addresses keeps the compiler from hoisting all of
-  // their loads out of the caller's loop over column blocks (thousands of
-  // registers, spilled).
-  const float2 *lbuf = Tg.lbuf, *dlt = Tg.delta;
-  asm volatile("" : "+v"(lbuf), "+v"(dlt));
-  const int lo_n = (4 * lq) * 16 + l16;   // A[j][4h + ks] at lo_n + 16 ks (column-major block)
-  const int lo_t = l16 * 16 + 4 * lq;     // A^T[j][4h + ks] at lo_t + ks
-  float2 y[LB][4];
+__device__ __forceinline__ void cb_load(float2 (&y)[LB][4], const float2 *M, int L, int N, int n, int lq) {
+  const bool col_in = n < N;
 #pragma unroll
   for (int R = 0; R < LB; ++R)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * R + 4 * lq + v;
-      y[R][v] = (col_in && row < A.L) ? ldg2(A.S, (size_t)n * A.L + row) : make_float2(0.f, 0.f);
+      y[R][v] = (col_in && row < L) ? ldg2(M, (size_t)n * L + row) : make_float2(0.f, 0.f);
     }
-  float2 ring[3][4];   // operands of the current block and the next two
-  Gauss2 acc;
+}
 
-  // forward substitution: Y_R = W_RR (S_R - sum_{K<R} L_RK Y_K); task t is
-  // block (R, K) with R = tri_row(t), K = t - R (R - 1) / 2
+// y <- L^-1 y: Y_R = W_RR (y_R - sum_{K<R} L_RK Y_K); task t is block (R, K)
+// with R = tri_row(t), K = t - R (R - 1) / 2.
+template <int LB>
+__device__ __forceinline__ void cb_forward(float2 (&y)[LB][4], const float2 *lbuf, const float2 *Wd, int lo_n) {
   constexpr int nf = LB * (LB - 1) / 2;
-  auto load_f = [&](int t, float2 (&dst)[4]) {
+  float2 ring[3][4];
+  Gauss2 acc;
+  auto load = [&](int t, float2 (&dst)[4]) {
     const int R = tri_row(t), K = t - R * (R - 1) / 2;
     const float2 *blk = pblk(lbuf, R, K);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) dst[ks] = ldg2(blk, lo_n + 16 * ks);
   };
-  if (nf > 0) load_f(0, ring[0]);
-  if (nf > 1) load_f(1, ring[1]);
+  if (nf > 0) load(0, ring[0]);
+  if (nf > 1) load(1, ring[1]);
 #pragma unroll
   for (int R = 0; R < LB; ++R) {
     acc.zero();
 #pragma unroll
     for (int K = 0; K < R; ++K) {
       const int t = R * (R - 1) / 2 + K;
-      if (t + 2 < nf) load_f(t + 2, ring[(t + 2) % 3]);
+      if (t + 2 < nf) load(t + 2, ring[(t + 2) % 3]);
       acc.add(K & 1, ring[t % 3], y[K]);
     }
     float2 r4[4], w4[4];
@@ -1788,18 +1795,17 @@ __device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, cons
 #pragma unroll
     for (int v = 0; v < 4; ++v) y[R][v] = acc.get(v);
   }
-  float q = 0.0f;
-#pragma unroll
-  for (int R = 0; R < LB; ++R)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) q += y[R][v].x * y[R][v].x + y[R][v].y * y[R][v].y;
-  q += __shfl_xor(q, 16);
-  q += __shfl_xor(q, 32);
+}
 
-  // backward substitution: B_R = W_RR^H (Y_R - sum_{K>R} L_KR^H B_K), R from
-  // the last block row up; task t is block (K, R) with r = tri_row(t),
-  // R = LB - 1 - r, K = R + 1 + t - r (r - 1) / 2
-  auto load_b = [&](int t, float2 (&dst)[4]) {
+// y <- L^-H y: B_R = W_RR^H (y_R - sum_{K>R} L_KR^H B_K), R from the last
+// block row up; task t is block (K, R) with r = tri_row(t), R = LB - 1 - r,
+// K = R + 1 + t - r (r - 1) / 2.
+template <int LB>
+__device__ __forceinline__ void cb_backward(float2 (&y)[LB][4], const float2 *lbuf, const float2 *Wd, int lo_t) {
+  constexpr int nf = LB * (LB - 1) / 2;
+  float2 ring[3][4];
+  Gauss2 acc;
+  auto load = [&](int t, float2 (&dst)[4]) {
     const int r = tri_row(t), R = LB - 1 - r, K = R + 1 + t - r * (r - 1) / 2;
     const float2 *blk = pblk(lbuf, K, R);
 #pragma unroll
@@ -1808,8 +1814,8 @@ __device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, cons
       dst[ks] = make_float2(x.x, -x.y);
     }
   };
-  if (nf > 0) load_b(0, ring[0]);
-  if (nf > 1) load_b(1, ring[1]);
+  if (nf > 0) load(0, ring[0]);
+  if (nf > 1) load(1, ring[1]);
 #pragma unroll
   for (int r = 0; r < LB; ++r) {
     const int R = LB - 1 - r;
@@ -1817,7 +1823,7 @@ __device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, cons
 #pragma unroll
     for (int j = 0; j < r; ++j) {
       const int t = r * (r - 1) / 2 + j, K = R + 1 + j;
-      if (t + 2 < nf) load_b(t + 2, ring[(t + 2) % 3]);
+      if (t + 2 < nf) load(t + 2, ring[(t + 2) % 3]);
       acc.add(j & 1, ring[t % 3], y[K]);
     }
     float2 r4[4], w4[4];
@@ -1836,38 +1842,115 @@ __device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, cons
 #pragma unroll
     for (int v = 0; v < 4; ++v) y[R][v] = acc.get(v);
   }
+}
 
-  // q - r = b^H (Sigma - SigmaHat) b = sum_I b_I^H D_II b_I + 2 Re sum_{K<I} b_I^H D_IK b_K;
-  // task t is the packed block t = (I, K), K <= I
+// This lane's share of Re y^H H y for the Hermitian H given by its packed
+// lower blocks: sum_I y_I^H H_II y_I + 2 Re sum_{K<I} y_I^H H_IK y_K (the
+// caller adds the shares of the four lanes of a column).  Task t is the
+// packed block t = (I, K), K <= I.
+template <int LB>
+__device__ __forceinline__ float cb_quad_lower(const float2 (&y)[LB][4], const float2 *H, int lo_n) {
   constexpr int nd = LB * (LB + 1) / 2;
-  auto load_d = [&](int t, float2 (&dst)[4]) {
+  float2 ring[3][4];
+  Gauss2 acc;
+  auto load = [&](int t, float2 (&dst)[4]) {
     const int I = tri_row(t) - 1, K = t - I * (I + 1) / 2;
     const float f = K < I ? 2.0f : 1.0f;
-    const float2 *blk = dlt + (size_t)t * 256;
+    const float2 *blk = H + (size_t)t * 256;
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const float2 x = ldg2(blk, lo_n + 16 * ks);   // D_IK[j][4h + ks]
+      const float2 x = ldg2(blk, lo_n + 16 * ks);   // H_IK[j][4h + ks]
       dst[ks] = make_float2(f * x.x, f * x.y);
     }
   };
-  load_d(0, ring[0]);
-  if (nd > 1) load_d(1, ring[1]);
-  float qmr = 0.0f;
+  load(0, ring[0]);
+  if (nd > 1) load(1, ring[1]);
+  float s = 0.0f;
 #pragma unroll
   for (int I = 0; I < LB; ++I) {
     acc.zero();
 #pragma unroll
     for (int K = 0; K <= I; ++K) {
       const int t = I * (I + 1) / 2 + K;
-      if (t + 2 < nd) load_d(t + 2, ring[(t + 2) % 3]);
+      if (t + 2 < nd) load(t + 2, ring[(t + 2) % 3]);
       acc.add(K & 1, ring[t % 3], y[K]);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const float2 d = acc.get(v);
-      qmr += y[I][v].x * d.x + y[I][v].y * d.y;
+      s += y[I][v].x * d.x + y[I][v].y * d.y;
     }
   }
+  return s;
+}
+
+// (H y)_I for every block row I of the Hermitian H given by its packed lower
+// blocks (H_IK for K <= I, H_KI^H for K > I); sink(I, acc) receives each
+// block row's accumulators.  Task t is (I, K) = (t / LB, t % LB).
+template <int LB, class Sink>
+__device__ __forceinline__ void cb_hermv(const float2 (&y)[LB][4], const float2 *H, int lo_n, int lo_t, Sink sink) {
+  constexpr int nt = LB * LB;
+  float2 ring[3][4];
+  Gauss2 acc;
+  auto load = [&](int t, float2 (&dst)[4]) {
+    const int I = t / LB, K = t % LB;
+    if (K <= I) {
+      const float2 *blk = pblk(H, I, K);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) dst[ks] = ldg2(blk, lo_n + 16 * ks);   // H_IK[j][4h + ks]
+    } else {
+      const float2 *blk = pblk(H, K, I);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const float2 x = ldg2(blk, lo_t + ks);   // H_KI[4h + ks][j]; (H_KI^H)[j][4h + ks] its conjugate
+        dst[ks] = make_float2(x.x, -x.y);
+      }
+    }
+  };
+  load(0, ring[0]);
+  if (nt > 1) load(1, ring[1]);
+#pragma unroll
+  for (int I = 0; I < LB; ++I) {
+    acc.zero();
+#pragma unroll
+    for (int K = 0; K < LB; ++K) {
+      const int t = I * LB + K;
+      if (t + 2 < nt) load(t + 2, ring[(t + 2) % 3]);
+      acc.add(K & 1, ring[t % 3], y[K]);
+    }
+    sink(I, acc);
+  }
+}
+
+// One wave: Y = L^-1 S_c (q = sum |y|^2), B = L^-H Y (= Sigma^-1 S_c),
+// q - r = Re b^H (Sigma - SigmaHat) b and the coordinate step of the 16
+// devices c0 .. c0 + 15.
+template <int LB>
+__device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, const float2 *Wd, int c0, int it,
+                                                   float rho, bool last) {
+  const CoopArgs &A = Tg.c;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+  const int n = c0 + l16;
+  const bool col_in = n < A.N;
+  // The factor and Sigma - SigmaHat are the same for every column block; an
+  // opaque copy of their addresses keeps the compiler from hoisting all of
+  // their loads out of the caller's loop over column blocks (thousands of
+  // registers, spilled).
+  const float2 *lbuf = Tg.lbuf, *dlt = Tg.delta;
+  asm volatile("" : "+v"(lbuf), "+v"(dlt));
+  const int lo_n = (4 * lq) * 16 + l16, lo_t = l16 * 16 + 4 * lq;
+  float2 y[LB][4];
+  cb_load<LB>(y, A.S, A.L, A.N, n, lq);
+  cb_forward<LB>(y, lbuf, Wd, lo_n);
+  float q = 0.0f;
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q += y[R][v].x * y[R][v].x + y[R][v].y * y[R][v].y;
+  q += __shfl_xor(q, 16);
+  q += __shfl_xor(q, 32);
+  cb_backward<LB>(y, lbuf, Wd, lo_t);
+  float qmr = cb_quad_lower<LB>(y, dlt, lo_n);   // q - r = b^H (Sigma - SigmaHat) b
   qmr += __shfl_xor(qmr, 16);
   qmr += __shfl_xor(qmr, 32);
   // coordinate step and convex update of device n
@@ -1925,6 +2008,7 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
   double rho_d = A.rho0;
   for (int it = 0; it < A.iters && !aborted; ++it) {
     // ---- A. packed Gram partials of this rank's tiles
+    PSCA_MARK(it, 0);
     for (int v = g; v < Gv; v += T) {
       const int n0 = v * NT;
       __syncthreads();   // the previous tile's Gram is done with Yt and wv
@@ -1954,12 +2038,17 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
       __syncthreads();
       gram_tile_fp64<THREADS>(Yt, PT, ncb, wv, NB, A.partials + (size_t)v * A.pstride);
     }
+    PSCA_MARK(it, 1);
     if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
     // ---- B. Sigma and Sigma - SigmaHat, 1/T of the packed entries per rank
+    PSCA_MARK(it, 2);
     reduce_sigma_slice<THREADS>(A, Tg.delta, Gv, T, g, dscr);
+    PSCA_MARK(it, 3);
     if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
     // ---- C1. blocked Cholesky in memory
+    PSCA_MARK(it, 4);
     const int f = factor_in_memory<THREADS>(A, Tg.delta, Tg.lbuf, Wd, nullptr, T, g, gen, &s_ok, &s_pd);
+    PSCA_MARK(it, 5);
     if (f == 1) failed = true;
     if (f == 2) aborted = true;
     if (failed || aborted) break;
@@ -1972,7 +2061,9 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
     const bool last = (it == A.iters - 1);
     for (int cb = g * kWaves + wave; cb < ncol; cb += T * kWaves)
       solve_column_block<LB>(Tg, Wd, 16 * cb, it, rho, last);
+    PSCA_MARK(it, 6);
     if (!last && !grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    PSCA_MARK(it, 7);
   }
   if (A.iters == 0 || failed || aborted)   // x_out holds the last finite iterate
     for (int n = g * THREADS + tid; n < A.N; n += T * THREADS) A.x_out[n] = Tg.xw[n];
@@ -2015,6 +2106,295 @@ __global__ void __launch_bounds__(512) k_psca_large_teams(const LargeTeamArgs *_
       }
     }
     __syncthreads();   // the next instance reuses the LDS
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of one unrolled layer for 65 <= L <= 256: k_psca_back_large_teams.
+// The quantities of the LDS backward (k_psca_back) on teams of workgroups as
+// k_psca_large_teams runs them: Sigma(x) rebuilt and factored in memory (not
+// stored by the forward pass), then per 16-column block in registers
+// b_m = Sigma^-1 s_m, q, q - r, c_m = Sigma^-1 SigmaHat b_m
+// = b_m - Sigma^-1 (Sigma - SigmaHat) b_m and the per-device weights
+// a_n, b_n of the two Gram matrices G_a = S diag(a) S^H, G_b = S diag(b) S^H
+// (Gram tiles in LDS, FP64, partials per tile), then per column block
+// dL/dx_m = v_m (1 - rho) + rho v_m mask_m (1 + c'/curv)
+//           - kappa_m (b_m^H G_a b_m + 2 Re c_m^H G_b b_m).
+// Five team barriers plus those of the factorisation.
+// ---------------------------------------------------------------------------
+struct LargeBackArgs {
+  LargeTeamArgs f;         // f.c: instance, x_in = the layer's input; tiles, Sigma, factor, barrier (xw unused)
+  float rho;               // the layer's step size
+  const float *v;          // [N] dL/dx'
+  float *grad_x;           // [N] dL/dx
+  float *grad_rho;         // this instance's dL/drho
+  float *rho_part;         // [T] per-rank parts of dL/drho
+  float2 *partials_b;      // [Gv][pstride] partials of G_b (Sigma's and G_a's use f.c.partials)
+  float2 *gram_a, *gram_b; // packed G_a, G_b
+  float2 *bmat, *cmat;     // per column block [LB][4][64], lane-major: b_m and c_m in the register layout
+  float *wa, *wb, *d0;     // [N] weights a_n, b_n and the diagonal term of dL/dx
+};
+
+__host__ __device__ inline size_t lds_large_back_bytes(int Lp, int NT, int threads) {
+  return lds_large_team_bytes(Lp, NT, threads) + (size_t)NT * sizeof(float);
+}
+
+__device__ __forceinline__ size_t cb_slot(int cb, int LB, int R, int v, int lane) {
+  return ((size_t)(cb * LB + R) * 4 + v) * 64 + lane;
+}
+
+// b_m, q, q - r, c_m and the weights of the 16 devices of column block cb;
+// returns this lane's part of dL/drho.
+template <int LB>
+__device__ __forceinline__ float back_column_block_1(const LargeBackArgs &Bk, const float2 *Wd, int cb) {
+  const CoopArgs &A = Bk.f.c;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+  const int n = 16 * cb + l16;
+  const bool col_in = n < A.N;
+  const float2 *lbuf = Bk.f.lbuf, *dlt = Bk.f.delta;
+  asm volatile("" : "+v"(lbuf), "+v"(dlt));   // keep the block loads inside the caller's loop
+  const int lo_n = (4 * lq) * 16 + l16, lo_t = l16 * 16 + 4 * lq;
+  float2 y[LB][4];
+  cb_load<LB>(y, A.S, A.L, A.N, n, lq);
+  cb_forward<LB>(y, lbuf, Wd, lo_n);
+  float q = 0.0f;
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q += y[R][v].x * y[R][v].x + y[R][v].y * y[R][v].y;
+  q += __shfl_xor(q, 16);
+  q += __shfl_xor(q, 32);
+  cb_backward<LB>(y, lbuf, Wd, lo_t);   // y = b
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bk.bmat[cb_slot(cb, LB, R, v, lane)] = y[R][v];
+  float qmr = cb_quad_lower<LB>(y, dlt, lo_n);
+  qmr += __shfl_xor(qmr, 16);
+  qmr += __shfl_xor(qmr, 32);
+  // z = (Sigma - SigmaHat) b, staged in cmat; then c = b - Sigma^-1 z
+  cb_hermv<LB>(y, dlt, lo_n, lo_t, [&](int I, const Gauss2 &acc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Bk.cmat[cb_slot(cb, LB, I, v, lane)] = acc.get(v);
+  });
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[R][v] = ldg2(Bk.cmat, cb_slot(cb, LB, R, v, lane));
+  cb_forward<LB>(y, lbuf, Wd, lo_n);
+  cb_backward<LB>(y, lbuf, Wd, lo_t);
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const size_t k = cb_slot(cb, LB, R, v, lane);
+      const float2 b = ldg2(Bk.bmat, k);
+      Bk.cmat[k] = make_float2(b.x - y[R][v].x, b.y - y[R][v].y);
+    }
+  float rho_term = 0.0f;
+  if (lq == 0 && col_in) {
+    const float x = A.x_in[n], vn = Bk.v[n];
+    const float gn = A.a.g ? A.a.g[n] : 0.0f;
+    float logit = 0.0f;
+    if (A.a.p) {
+      const float pn = A.a.p[n];
+      logit = logf(pn / (1.0f - pn));
+    }
+    const StepDerivs d = step_derivs_qmr(x, q, qmr, gn, logit, A.a);
+    const float rv = Bk.rho * vn * d.mask;
+    Bk.wa[n] = rv * d.dq;
+    Bk.wb[n] = rv * d.dr;
+    Bk.d0[n] = vn * (1.0f - Bk.rho) + rv * d.own;
+    rho_term = vn * (d.xt - x);
+  }
+  return rho_term;
+}
+
+// dL/dx of the 16 devices of column block cb from b_m, c_m and G_a, G_b.
+template <int LB>
+__device__ __forceinline__ void back_column_block_2(const LargeBackArgs &Bk, int cb) {
+  const CoopArgs &A = Bk.f.c;
+  const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
+  const int n = 16 * cb + l16;
+  const float2 *ga = Bk.gram_a, *gb = Bk.gram_b;
+  asm volatile("" : "+v"(ga), "+v"(gb));
+  const int lo_n = (4 * lq) * 16 + l16, lo_t = l16 * 16 + 4 * lq;
+  float2 y[LB][4];
+#pragma unroll
+  for (int R = 0; R < LB; ++R)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y[R][v] = ldg2(Bk.bmat, cb_slot(cb, LB, R, v, lane));
+  float t1 = cb_quad_lower<LB>(y, ga, lo_n);   // b^H G_a b
+  float t2 = 0.0f;                              // Re c^H G_b b
+  cb_hermv<LB>(y, gb, lo_n, lo_t, [&](int I, const Gauss2 &acc) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float2 c = ldg2(Bk.cmat, cb_slot(cb, LB, I, v, lane)), d = acc.get(v);
+      t2 += c.x * d.x + c.y * d.y;
+    }
+  });
+  t1 += __shfl_xor(t1, 16);
+  t1 += __shfl_xor(t1, 32);
+  t2 += __shfl_xor(t2, 16);
+  t2 += __shfl_xor(t2, 32);
+  if (lq == 0 && n < A.N) {
+    const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
+    const float kappa = known ? A.a.g[n] : 1.0f;
+    Bk.grad_x[n] = Bk.d0[n] - kappa * (t1 + 2.0f * t2);
+  }
+}
+
+template <int LB, int THREADS>
+__device__ __forceinline__ void large_back_body(const LargeBackArgs &Bk, const int g) {
+  const LargeTeamArgs &Tg = Bk.f;
+  const CoopArgs &A = Tg.c;
+  constexpr int kWaves = THREADS / 64;
+  constexpr int Lp = 16 * LB, NB = LB * (LB + 1) / 2;
+  extern __shared__ float4 smem_raw[];
+  __shared__ int s_ok, s_pd;
+  __shared__ float s_red[kWaves];
+  const int NT = A.NT, PT = A.NT + 1, ncb = A.ncb, T = A.G, Gv = Tg.Gv;
+  float2 *Yt = (float2 *)smem_raw;              // [Lp][PT] Gram tile of S
+  float2 *Wd = Yt + Lp * PT;                    // [LB][256] W_JJ
+  double2 *dscr = (double2 *)(Wd + LB * 256);   // [THREADS]
+  float *wv = (float *)(dscr + THREADS);        // [NT] weights of the tile
+  float *wv2 = wv + NT;                         // [NT] second weights
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K);
+  const int ncol = (A.N + 15) / 16;
+  const int E = NB * 256;
+  unsigned gen = 0;
+  bool failed = false, aborted = false;
+  // stage the S tile v (columns v NT ..) in Yt and its weights by `weights`
+  auto stage = [&](int v, auto weights) {
+    const int n0 = v * NT;
+    __syncthreads();   // the previous tile's Grams are done with Yt and the weights
+    for (int c = tid; c < NT; c += THREADS) weights(c, n0 + c);
+    constexpr int kU = 8;   // loads in flight per thread
+    const int tot = Lp * NT;
+    for (int e0 = tid; e0 < tot; e0 += kU * THREADS) {
+      float2 val[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;   // down a column: coalesced
+        const int n = n0 + c;
+        val[u] = (e < tot && i < A.L && n < A.N) ? A.S[(size_t)n * A.L + i] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;
+        if (e < tot) Yt[i * PT + c] = val[u];
+      }
+    }
+    __syncthreads();
+  };
+  do {
+    // ---- Sigma(x) and its factor, as the forward pass
+    for (int v = g; v < Gv; v += T) {
+      stage(v, [&](int c, int n) {
+        const float x = n < A.N ? A.x_in[n] : 0.0f;
+        wv[c] = n < A.N ? (known ? A.a.g[n] * x : x) : 0.0f;
+      });
+      gram_tile_fp64<THREADS>(Yt, PT, ncb, wv, NB, A.partials + (size_t)v * A.pstride);
+    }
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    reduce_sigma_slice<THREADS>(A, Tg.delta, Gv, T, g, dscr);
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    const int f = factor_in_memory<THREADS>(A, Tg.delta, Tg.lbuf, Wd, nullptr, T, g, gen, &s_ok, &s_pd);
+    if (f == 1) failed = true;
+    if (f == 2) aborted = true;
+    if (failed || aborted) break;
+    // ---- b, q, q - r, c and the weights per column block
+    float rho_term = 0.0f;
+    for (int cb = g * kWaves + wave; cb < ncol; cb += T * kWaves) rho_term += back_column_block_1<LB>(Bk, Wd, cb);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) rho_term += __shfl_xor(rho_term, o);
+    if (lane == 0) s_red[wave] = rho_term;
+    __syncthreads();
+    if (tid == 0) {
+      float t = 0.0f;
+      for (int w = 0; w < kWaves; ++w) t += s_red[w];
+      Bk.rho_part[g] = t;
+    }
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    // ---- G_a and G_b
+    for (int v = g; v < Gv; v += T) {
+      stage(v, [&](int c, int n) {
+        wv[c] = n < A.N ? Bk.wa[n] : 0.0f;
+        wv2[c] = n < A.N ? Bk.wb[n] : 0.0f;
+      });
+      gram_tile_fp64<THREADS>(Yt, PT, ncb, wv, NB, A.partials + (size_t)v * A.pstride);
+      gram_tile_fp64<THREADS>(Yt, PT, ncb, wv2, NB, Bk.partials_b + (size_t)v * A.pstride);
+    }
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    reduce_packed_slice<THREADS>(A.partials, A.pstride, Gv, T, g, E, dscr, [&](int e, double2 sm) {
+      Bk.gram_a[e] = make_float2((float)sm.x, (float)sm.y);
+    });
+    reduce_packed_slice<THREADS>(Bk.partials_b, A.pstride, Gv, T, g, E, dscr, [&](int e, double2 sm) {
+      Bk.gram_b[e] = make_float2((float)sm.x, (float)sm.y);
+    });
+    if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
+    // ---- dL/dx per column block; dL/drho from the ranks' parts
+    for (int cb = g * kWaves + wave; cb < ncol; cb += T * kWaves) back_column_block_2<LB>(Bk, cb);
+    if (g == 0 && tid == 0) {
+      float t = 0.0f;
+      for (int r = 0; r < T; ++r) t += Bk.rho_part[r];
+      *Bk.grad_rho = t;
+    }
+  } while (false);
+  if (g == 0 && tid == 0 && A.status) *A.status = aborted ? PSCA_ESYNC : (failed ? PSCA_ENOTPD : PSCA_OK);
+}
+
+template <int LB>
+__device__ __noinline__ void large_back_member(const LargeBackArgs *__restrict__ desc, int g) {
+  const LargeBackArgs A = *desc;
+  large_back_body<LB, 512>(A, g);
+}
+
+__global__ void __launch_bounds__(512) k_psca_back_large_teams(const LargeBackArgs *__restrict__ descs,
+                                                               const int *__restrict__ lists,
+                                                               const int *__restrict__ offsets,
+                                                               const int *__restrict__ team_start, int n_teams) {
+  const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);
+  int t = 0, hi = n_teams - 1;   // the team with team_start[t] <= b < team_start[t + 1]
+  while (t < hi) {
+    const int mid = (t + hi + 1) >> 1;
+    if (team_start[mid] <= b) t = mid;
+    else hi = mid - 1;
+  }
+  const int g = b - team_start[t];
+  const int i1 = offsets[t + 1];
+  for (int idx = offsets[t]; idx < i1; ++idx) {
+    const LargeBackArgs *desc = descs + lists[idx];
+    if (g < desc->f.c.G) {
+      switch ((desc->f.c.L + 15) >> 4) {
+        case 5: large_back_member<5>(desc, g); break;
+        case 6: large_back_member<6>(desc, g); break;
+        case 7: large_back_member<7>(desc, g); break;
+        case 8: large_back_member<8>(desc, g); break;
+        case 9: large_back_member<9>(desc, g); break;
+        case 10: large_back_member<10>(desc, g); break;
+        case 11: large_back_member<11>(desc, g); break;
+        case 12: large_back_member<12>(desc, g); break;
+        case 13: large_back_member<13>(desc, g); break;
+        case 14: large_back_member<14>(desc, g); break;
+        case 15: large_back_member<15>(desc, g); break;
+        default: large_back_member<16>(desc, g); break;
+      }
+    }
+    __syncthreads();   // the next instance reuses the LDS
+  }
+}
+
+// Barrier words, abort word and status of every instance of a large-L
+// backward launch: block b resets instance b.
+__global__ void k_prepare_large_back(const LargeBackArgs *__restrict__ descs) {
+  const CoopArgs &A = descs[blockIdx.x].f.c;
+  for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
+  if (threadIdx.x == 0) {
+    *A.bar.release = 0u;
+    *A.bar.abort_flag = 0;
+    *A.status = PSCA_OK;
   }
 }
 
@@ -3041,6 +3421,143 @@ int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int 
   return launch_batch(plan, (const char *)ctx->ddesc, st);
 }
 
+// ---- layer backward for 65 <= L <= 256 on teams (k_psca_back_large_teams) --
+int large_back_tile(int Lp) {
+  for (int nt = 64; nt >= 16; nt -= 16)
+    if (lds_large_back_bytes(Lp, nt, kLargeThreads) <= kMaxLds) return nt;
+  return 0;
+}
+
+// Per-instance workspace of a large-L backward: the forward's buffers (Sigma,
+// Sigma - SigmaHat, L, barrier and status words, exchange, iterate), packed
+// G_a and G_b, b_m and c_m per column block, three per-device vectors and
+// the T parts of dL/drho.
+size_t large_back_inst_ws_bytes(int Lp, int T, int N) {
+  const size_t E = packed_entries(Lp), ncol = (size_t)(N + 15) / 16;
+  return large_inst_ws_bytes(Lp, T, N) + 2 * align_up(E * sizeof(float2)) +
+         2 * align_up(ncol * (size_t)Lp * 16 * sizeof(float2)) + 3 * align_up((size_t)N * sizeof(float)) +
+         align_up((size_t)T * sizeof(float));
+}
+
+int large_back_capacity(psca_ctx *ctx) {
+  const KernelChoice kc{(const void *)k_psca_back_large_teams, kLargeThreads, 256};
+  return max_coresident(ctx, kc, kMaxLds);
+}
+
+// B layer backwards (every L in 65..256) in one persistent launch on uniform
+// teams of T workgroups (T = 0: the co-resident grid shared evenly, and for
+// a single instance as many workgroups as Gram tiles).
+int run_large_backward(psca_ctx *ctx, int B, const psca_back_problem *pr, float rho, hipStream_t st) {
+  const int cap = large_back_capacity(ctx);
+  if (cap <= 0) return PSCA_ENOTSUP;
+  std::vector<int> nt(B), gv(B), lp(B);
+  for (int b = 0; b < B; ++b) {
+    lp[b] = (pr[b].L + 15) & ~15;
+    nt[b] = large_back_tile(lp[b]);
+    if (nt[b] == 0) return PSCA_ENOTSUP;
+    gv[b] = (pr[b].N + nt[b] - 1) / nt[b];
+  }
+  const int T = B == 1 ? std::min(cap, gv[0]) : std::max(1, cap / B);
+  const int n = std::max(1, std::min(cap / T, B));
+  std::vector<double> cost(B);
+  for (int b = 0; b < B; ++b) cost[b] = (double)pr[b].N * lp[b] * lp[b] + 2.0e5 * (lp[b] / 16);
+  std::vector<std::vector<int>> team(n);
+  std::vector<int> team_of(B), all(B);
+  for (int b = 0; b < B; ++b) all[b] = b;
+  assign_longest_first(all, cost, 0, n, team, team_of);
+  BatchPlan plan;   // the launch geometry (launch_back_large reads it)
+  plan.large = true;
+  plan.B = B;
+  plan.T = T;
+  plan.n_teams = n;
+  plan.team_start.assign(1, 0);
+  for (int t = 0; t < n; ++t) plan.team_start.push_back(plan.team_start.back() + T);
+  plan.offsets.push_back(0);
+  for (int t = 0; t < n; ++t) {
+    for (int b : team[t]) plan.lists.push_back(b);
+    plan.offsets.push_back((int)plan.lists.size());
+  }
+  std::vector<size_t> off(B);
+  size_t total = 0;
+  for (int b = 0; b < B; ++b) {
+    off[b] = total;
+    total += large_back_inst_ws_bytes(lp[b], T, pr[b].N);
+    plan.lds = std::max(plan.lds, lds_large_back_bytes(lp[b], nt[b], kLargeThreads));
+  }
+  std::vector<size_t> part_off(n);
+  for (int t = 0; t < n; ++t) {   // per team: the partials of Sigma / G_a and of G_b
+    size_t need = 0;
+    for (int b : team[t]) need = std::max(need, (size_t)gv[b] * packed_entries(lp[b]));
+    part_off[t] = total;
+    total += 2 * align_up(need * sizeof(float2));
+  }
+  int rc = ensure_ws(ctx, total);
+  if (rc != PSCA_OK) return rc;
+  char *base = (char *)ctx->ws;
+  const size_t bytes = align_up((size_t)B * sizeof(LargeBackArgs)) + align_up(plan.lists.size() * sizeof(int)) +
+                       align_up(plan.offsets.size() * sizeof(int)) + align_up(plan.team_start.size() * sizeof(int));
+  char *host = nullptr;
+  if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) return rc;
+  LargeBackArgs *d = (LargeBackArgs *)host;
+  for (int b = 0; b < B; ++b) {
+    const psca_back_problem &q = pr[b];
+    const InstPlan ip{lp[b], nt[b] / 16, nt[b], T, plan.lds, 0};
+    LargeBackArgs a;
+    fill_args(a.f.c, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, 1, rho, q.x_in, nullptr,
+              nullptr, nullptr, nullptr, q.status, ip);
+    char *w = base + off[b];
+    bind_large_ws(a.f, w, lp[b], T, q.N);
+    w += large_inst_ws_bytes(lp[b], T, q.N);
+    const size_t E = packed_entries(lp[b]), ncol = (size_t)(q.N + 15) / 16;
+    a.gram_a = (float2 *)w;   w += align_up(E * sizeof(float2));
+    a.gram_b = (float2 *)w;   w += align_up(E * sizeof(float2));
+    a.bmat = (float2 *)w;     w += align_up(ncol * (size_t)lp[b] * 16 * sizeof(float2));
+    a.cmat = (float2 *)w;     w += align_up(ncol * (size_t)lp[b] * 16 * sizeof(float2));
+    a.wa = (float *)w;        w += align_up((size_t)q.N * sizeof(float));
+    a.wb = (float *)w;        w += align_up((size_t)q.N * sizeof(float));
+    a.d0 = (float *)w;        w += align_up((size_t)q.N * sizeof(float));
+    a.rho_part = (float *)w;
+    a.f.c.partials = (float2 *)(base + part_off[team_of[b]]);
+    a.f.c.pstride = E;
+    size_t need = 0;
+    for (int bb : team[team_of[b]]) need = std::max(need, (size_t)gv[bb] * packed_entries(lp[bb]));
+    a.partials_b = (float2 *)(base + part_off[team_of[b]] + align_up(need * sizeof(float2)));
+    a.f.Gv = gv[b];
+    a.rho = rho;
+    a.v = q.v;
+    a.grad_x = q.grad_x;
+    a.grad_rho = q.grad_rho;
+    d[b] = a;
+  }
+  char *p = host + align_up((size_t)B * sizeof(LargeBackArgs));
+  memcpy(p, plan.lists.data(), plan.lists.size() * sizeof(int));
+  p += align_up(plan.lists.size() * sizeof(int));
+  memcpy(p, plan.offsets.data(), plan.offsets.size() * sizeof(int));
+  p += align_up(plan.offsets.size() * sizeof(int));
+  memcpy(p, plan.team_start.data(), plan.team_start.size() * sizeof(int));
+  if (hipMemcpyAsync(ctx->ddesc, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  if (hipEventRecord(ctx->desc_done, st) != hipSuccess) return PSCA_EHIP;
+  ctx->desc_pending = true;
+  const char *dimg = (const char *)ctx->ddesc;
+  const LargeBackArgs *descs = (const LargeBackArgs *)dimg;
+  const int *lists = (const int *)(dimg + align_up((size_t)B * sizeof(LargeBackArgs)));
+  const int *offsets = (const int *)((const char *)lists + align_up(plan.lists.size() * sizeof(int)));
+  const int *team_start = (const int *)((const char *)offsets + align_up(plan.offsets.size() * sizeof(int)));
+  int n_teams = n;
+  hipLaunchKernelGGL(k_prepare_large_back, dim3(B), dim3(256), 0, st, descs);
+  if ((rc = launch_ok()) != PSCA_OK) return rc;
+  void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&team_start, (void *)&n_teams};
+  if (hipLaunchCooperativeKernel((const void *)k_psca_back_large_teams, dim3(plan.team_start.back()),
+                                 dim3(kLargeThreads), args, (unsigned)plan.lds, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return PSCA_EHIP;
+  }
+  return PSCA_OK;
+}
+
 // Whole-batch pilot-length class: 0 when every L <= 96 (k_psca_teams), 1
 // when every L is 97..256 (k_psca_large_teams), -1 for a batch mixing both.
 int batch_class(int B, const psca_problem *pr) {
@@ -3588,9 +4105,23 @@ int psca_layer_backward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32
   if (!(rho >= 0.0f) || rho > 1.0f) return PSCA_EINVAL;
   int rc = validate_params(prm, L, N, false);
   if (rc != PSCA_OK) return rc;
-  if (L > 64 || prm->variant == PSCA_MAP_K2) return PSCA_ENOTSUP;
+  if (prm->variant == PSCA_MAP_K2) return PSCA_ENOTSUP;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
+  if (L > 64) {   // Sigma and the Gram matrices in memory, on one team
+    psca_back_problem q;
+    q.Sigma_hat = Sigma_hat;
+    q.S = S;
+    q.L = L;
+    q.N = N;
+    q.prm = *prm;
+    q.x_in = x_in;
+    q.v = v;
+    q.grad_x = grad_x;
+    q.grad_rho = grad_rho;
+    q.status = status;
+    return run_large_backward(ctx, 1, &q, rho, as_stream(stream));
+  }
   return run_layer_backward(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, rho, x_in, v, grad_x,
                             grad_rho, status, as_stream(stream));
 }
@@ -3625,12 +4156,14 @@ int psca_layer_backward_batch(psca_ctx *ctx, int B, const psca_back_problem *pro
     if (!q.Sigma_hat || !q.S || !q.x_in || !q.v || !q.grad_x || !q.grad_rho) return PSCA_EINVAL;
     const int rc = validate_params(&q.prm, q.L, q.N, false);
     if (rc != PSCA_OK) return rc;
-    if (q.L > 64 || q.prm.variant == PSCA_MAP_K2) return PSCA_ENOTSUP;
+    if (q.prm.variant == PSCA_MAP_K2) return PSCA_ENOTSUP;
+    if ((q.L > 64) != (problems[0].L > 64)) return PSCA_ENOTSUP;   // one launch runs one of the two kernels
   }
   if (B == 0) return PSCA_OK;
   DeviceGuard guard(ctx->device);
   if (!guard.ok) return PSCA_EHIP;
   hipStream_t st = as_stream(stream);
+  if (problems[0].L > 64) return run_large_backward(ctx, B, problems, rho, st);
   const KernelChoice kc{(const void *)k_psca_back_teams, 512, 64};
   const int cap = max_coresident(ctx, kc, kMaxLds);
   if (cap <= 0) return PSCA_ENOTSUP;
