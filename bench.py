@@ -58,6 +58,17 @@ def iteration_flops(N, L):
     return 20.0 * N * L * L + 8.0 * N * L + 24.0 * L ** 3
 
 
+def layer_backward_flops(N, L):
+    """Real flops of one layer's backward that the method needs (the
+    vector-Jacobian product written out in the oracle's layer_vjp): Sigma
+    again (Hermitian, 4 N L^2), B = Sigma^-1 S (8 N L^2), C = Sigma^-1 SigmaHat B
+    (16 N L^2), the two Gram matrices G_a, G_b (Hermitian, 8 N L^2),
+    G_a B and G_b B (16 N L^2), q, r and the two quadratic forms per device
+    (40 N L), the factorisation counted as 24 L^3.  52 N L^2 in all, about
+    2.6 forward iterations."""
+    return 52.0 * N * L * L + 40.0 * N * L + 24.0 * L ** 3
+
+
 def sample_cov_flops(L, M):
     """SigmaHat = Y Y^H / M, Hermitian: 4 L^2 M real flops."""
     return 4.0 * L * L * M
@@ -357,7 +368,7 @@ def run_large(args):
     from paper_2503_15259_amd import metrics
     from paper_2503_15259_amd import psca as P
 
-    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20.json")) as f:
+    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20_N10000_L200.json")) as f:
         trained = json.load(f)
     K = trained["K"]
     cpu_info, cpu_x = (None, {})
@@ -509,7 +520,8 @@ def run_large(args):
                                f"ML-K and MAP-UR; each batch in one persistent launch; a step is SigmaHat of "
                                f"every instance plus the network's launch",
                    "N": N, "L": L, "M": M, "p": w["p"], "batch": B, "iters": iters, "K": K, "team_size": team,
-                   "net_trained_at": {k: tr[k] for k in ("N", "L", "M", "p", "steps", "batch", "lr")}},
+                   "net_trained_at": {k: tr.get(k) for k in ("N", "L", "M", "p", "steps", "batch", "lr", "pool",
+                                                              "instance_visits")}},
         "equal_error": {"net": round(eer_net, 5), "psca_at_k_star": round(eer_psca[k_star - 1], 5),
                         f"psca_{iters}": round(eer_psca[iters - 1], 5), "k_star": k_star, "matched": bool(matched),
                         f"map_ur_psca_{iters}": round(metrics.equal_error_point(mur_out, truth)[0], 5),
@@ -693,9 +705,8 @@ def run_train(args):
         b.record(stream)
     torch.cuda.synchronize()
     ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    # forward K iterations plus the backward's recomputation and two Gram
-    # reductions, about 2.2 forwards (the survey's count)
-    flops = B * K * iteration_flops(N, L) * 3.2
+    # K forward iterations and K layer backwards per instance
+    flops = B * K * (iteration_flops(N, L) + layer_backward_flops(N, L))
     achieved = flops / (ms / 1e3) / 1e12
     line = {
         "metric": "unrolled-network training instances/sec (forward + backward + Adam), 1 MI355X",

@@ -3,6 +3,11 @@
     python -m paper_2503_15259_amd.build
 
 produces paper_2503_15259_amd/libpsca.so (hipcc, -O3, --offload-arch=gfx950).
+csrc/psca.hip is compiled as several translation units in parallel: the
+library proper (kernels, host code and C ABI, -DPSCA_TU_MAIN) and one unit
+per range of block counts of the large pilot-length backward kernel
+(-DPSCA_TU_BACK), whose fully unrolled column-block code dominates the
+compile time; the objects are linked into one library.
 """
 from __future__ import annotations
 
@@ -10,11 +15,12 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG_DIR = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG_DIR)
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = [os.path.join(PKG_DIR, "csrc", "psca.hip")]
+SOURCE = os.path.join(PKG_DIR, "csrc", "psca.hip")
 LIB_PATH = os.path.join(PKG_DIR, "libpsca.so")
 ARCH = "gfx950"
 
@@ -23,11 +29,15 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     # packed FP32 instructions are kept out of the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+
+# translation units: (name, defines); the backward ranges match PSCA_BACK_RANGES in psca.hip
+UNITS = [("main", ["-DPSCA_TU_MAIN"])] + [
+    (f"back_{lo}_{hi}", ["-DPSCA_TU_BACK", f"-DPSCA_BACK_LO={lo}", f"-DPSCA_BACK_HI={hi}"])
+    for lo, hi in ((5, 10), (11, 13), (14, 15), (16, 16))]
 
 
 def hipcc() -> str:
@@ -37,20 +47,43 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (set HIPCC or install ROCm)")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into LIB_PATH (always recompiles)."""
-    tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, *SOURCES, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+def _diagnostics(res) -> list:
     # the host pass does not know the packed-fp32 feature and says so; keep other diagnostics
     noise = "is not a recognized feature for this target"
-    msgs = [ln for ln in (res.stdout + res.stderr).splitlines() if noise not in ln]
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
-    if verbose and msgs:
-        print("\n".join(msgs))
+    return [ln for ln in (res.stdout + res.stderr).splitlines() if noise not in ln]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every translation unit (always) and link LIB_PATH."""
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="psca_build_") as tmpdir:
+        procs = []
+        for name, defs in UNITS:
+            obj = os.path.join(tmpdir, f"psca_{name}.o")
+            cmd = [cc, *HIPCC_FLAGS, *defs, "-I", INCLUDE, "-c", SOURCE, "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((name, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                                      text=True)))
+        objs, failed = [], []
+        for name, obj, proc in procs:
+            out, err = proc.communicate()
+            res = subprocess.CompletedProcess(proc.args, proc.returncode, out, err)
+            msgs = _diagnostics(res)
+            if proc.returncode != 0:
+                failed.append(f"[{name}]\n" + "\n".join(msgs))
+            elif verbose and msgs:
+                print("\n".join(msgs))
+            objs.append(obj)
+        if failed:
+            raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
+        tmp = LIB_PATH + ".tmp"
+        cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + "\n".join(_diagnostics(res)))
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

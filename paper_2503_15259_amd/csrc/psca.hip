@@ -47,7 +47,7 @@
 
 #include "psca.h"
 
-namespace {
+namespace psca_impl {
 
 constexpr int kThreads = 256;                              // helper kernels
 constexpr int kBlk = 16;
@@ -1364,6 +1364,7 @@ __device__ __noinline__ void back_member(const BackArgs *__restrict__ desc, int 
   psca_back_body<LP, 512>(*desc, g);
 }
 
+#ifdef PSCA_TU_MAIN
 __global__ void __launch_bounds__(512) k_psca_back_teams(const BackArgs *__restrict__ descs,
                                                          const int *__restrict__ lists,
                                                          const int *__restrict__ offsets, int T) {
@@ -1383,8 +1384,10 @@ __global__ void __launch_bounds__(512) k_psca_back_teams(const BackArgs *__restr
     __syncthreads();   // the next instance reuses the LDS
   }
 }
+#endif
 
 // Barrier words and status of every instance of a batched backward.
+#ifdef PSCA_TU_MAIN
 __global__ void k_prepare_back_batch(const BackArgs *__restrict__ descs) {
   const CoopArgs &A = descs[blockIdx.x].c;
   for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
@@ -1394,8 +1397,10 @@ __global__ void k_prepare_back_batch(const BackArgs *__restrict__ descs) {
     *A.status = PSCA_OK;
   }
 }
+#endif
 
 // dL/drho of every instance: the sum of its workgroups' parts (one block each).
+#ifdef PSCA_TU_MAIN
 __global__ void k_sum_parts_batch(const BackArgs *__restrict__ descs) {
   __shared__ float sh[256];
   const BackArgs &d = descs[blockIdx.x];
@@ -1409,8 +1414,10 @@ __global__ void k_sum_parts_batch(const BackArgs *__restrict__ descs) {
   }
   if (threadIdx.x == 0) *d.grad_rho = sh[0];
 }
+#endif
 
 // dL/drho = the sum of the per-workgroup parts (one workgroup)
+#ifdef PSCA_TU_MAIN
 __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__restrict__ out) {
   __shared__ float sh[256];
   float t = 0.0f;
@@ -1423,6 +1430,7 @@ __global__ void k_sum_parts(const float *__restrict__ parts, int G, float *__res
   }
   if (threadIdx.x == 0) *out = sh[0];
 }
+#endif
 
 // Pilot lengths 97..256: the L x L matrices no longer fit a workgroup's LDS
 // beside an S tile, so Sigma, its factor L and Sigma - SigmaHat live in
@@ -2076,6 +2084,7 @@ __device__ __noinline__ void large_team_member(const LargeTeamArgs *__restrict__
   large_team_body<LB, 512>(A, g);
 }
 
+#ifdef PSCA_TU_MAIN
 __global__ void __launch_bounds__(512) k_psca_large_teams(const LargeTeamArgs *__restrict__ descs,
                                                           const int *__restrict__ lists,
                                                           const int *__restrict__ offsets,
@@ -2108,9 +2117,10 @@ __global__ void __launch_bounds__(512) k_psca_large_teams(const LargeTeamArgs *_
     __syncthreads();   // the next instance reuses the LDS
   }
 }
+#endif
 
 // ---------------------------------------------------------------------------
-// Backward of one unrolled layer for 65 <= L <= 256: k_psca_back_large_teams.
+// Backward of one unrolled layer for 65 <= L <= 256: k_psca_back_large_<lo>_<hi>.
 // The quantities of the LDS backward (k_psca_back) on teams of workgroups as
 // k_psca_large_teams runs them: Sigma(x) rebuilt and factored in memory (not
 // stored by the forward pass), then per 16-column block in registers
@@ -2351,43 +2361,53 @@ __device__ __noinline__ void large_back_member(const LargeBackArgs *__restrict__
   large_back_body<LB, 512>(A, g);
 }
 
-__global__ void __launch_bounds__(512) k_psca_back_large_teams(const LargeBackArgs *__restrict__ descs,
-                                                               const int *__restrict__ lists,
-                                                               const int *__restrict__ offsets,
-                                                               const int *__restrict__ team_start, int n_teams) {
-  const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);
-  int t = 0, hi = n_teams - 1;   // the team with team_start[t] <= b < team_start[t + 1]
-  while (t < hi) {
-    const int mid = (t + hi + 1) >> 1;
-    if (team_start[mid] <= b) t = mid;
-    else hi = mid - 1;
-  }
-  const int g = b - team_start[t];
-  const int i1 = offsets[t + 1];
-  for (int idx = offsets[t]; idx < i1; ++idx) {
-    const LargeBackArgs *desc = descs + lists[idx];
-    if (g < desc->f.c.G) {
-      switch ((desc->f.c.L + 15) >> 4) {
-        case 5: large_back_member<5>(desc, g); break;
-        case 6: large_back_member<6>(desc, g); break;
-        case 7: large_back_member<7>(desc, g); break;
-        case 8: large_back_member<8>(desc, g); break;
-        case 9: large_back_member<9>(desc, g); break;
-        case 10: large_back_member<10>(desc, g); break;
-        case 11: large_back_member<11>(desc, g); break;
-        case 12: large_back_member<12>(desc, g); break;
-        case 13: large_back_member<13>(desc, g); break;
-        case 14: large_back_member<14>(desc, g); break;
-        case 15: large_back_member<15>(desc, g); break;
-        default: large_back_member<16>(desc, g); break;
-      }
-    }
-    __syncthreads();   // the next instance reuses the LDS
+// The large-L backward kernels: one per range of block counts LB = L_p / 16,
+// each built from this file as a translation unit of its own (the fully
+// unrolled column-block code of 12 instantiations compiles for minutes; the
+// ranges compile in parallel).  A launch runs instances of one range.
+#define PSCA_BACK_RANGES(X) X(5, 10) X(11, 13) X(14, 15) X(16, 16)
+#define PSCA_BACK_NAME(lo, hi) k_psca_back_large_##lo##_##hi
+#define PSCA_BACK_DECL(lo, hi)                                                                              \
+  __global__ void __launch_bounds__(512) PSCA_BACK_NAME(lo, hi)(                                           \
+      const LargeBackArgs *__restrict__ descs, const int *__restrict__ lists, const int *__restrict__ offsets, \
+      const int *__restrict__ team_start, int n_teams);
+PSCA_BACK_RANGES(PSCA_BACK_DECL)
+
+#ifdef PSCA_TU_BACK   // -DPSCA_TU_BACK -DPSCA_BACK_LO=lo -DPSCA_BACK_HI=hi
+template <int LO, int HI>
+__device__ __forceinline__ void back_dispatch(int lb, const LargeBackArgs *desc, int g) {
+  if constexpr (LO <= HI) {
+    if (lb == LO) large_back_member<LO>(desc, g);
+    else back_dispatch<LO + 1, HI>(lb, desc, g);
   }
 }
 
+#define PSCA_BACK_DEF(lo, hi) PSCA_BACK_DEF_(lo, hi)
+#define PSCA_BACK_DEF_(lo, hi)                                                                              \
+  __global__ void __launch_bounds__(512) PSCA_BACK_NAME(lo, hi)(                                           \
+      const LargeBackArgs *__restrict__ descs, const int *__restrict__ lists, const int *__restrict__ offsets, \
+      const int *__restrict__ team_start, int n_teams) {                                                    \
+    const int b = xcd_major((int)blockIdx.x, (int)gridDim.x);                                               \
+    int t = 0, hi_t = n_teams - 1; /* the team with team_start[t] <= b < team_start[t + 1] */             \
+    while (t < hi_t) {                                                                                      \
+      const int mid = (t + hi_t + 1) >> 1;                                                                  \
+      if (team_start[mid] <= b) t = mid;                                                                    \
+      else hi_t = mid - 1;                                                                                  \
+    }                                                                                                       \
+    const int g = b - team_start[t];                                                                        \
+    const int i1 = offsets[t + 1];                                                                          \
+    for (int idx = offsets[t]; idx < i1; ++idx) {                                                           \
+      const LargeBackArgs *desc = descs + lists[idx];                                                       \
+      if (g < desc->f.c.G) back_dispatch<lo, hi>((desc->f.c.L + 15) >> 4, desc, g);                         \
+      __syncthreads(); /* the next instance reuses the LDS */                                              \
+    }                                                                                                       \
+  }
+PSCA_BACK_DEF(PSCA_BACK_LO, PSCA_BACK_HI)
+#endif
+
 // Barrier words, abort word and status of every instance of a large-L
 // backward launch: block b resets instance b.
+#ifdef PSCA_TU_MAIN
 __global__ void k_prepare_large_back(const LargeBackArgs *__restrict__ descs) {
   const CoopArgs &A = descs[blockIdx.x].f.c;
   for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
@@ -2397,9 +2417,11 @@ __global__ void k_prepare_large_back(const LargeBackArgs *__restrict__ descs) {
     *A.status = PSCA_OK;
   }
 }
+#endif
 
 // Barrier words, abort word and status of every instance of a large-L batch
 // launch: block b resets instance b.
+#ifdef PSCA_TU_MAIN
 __global__ void k_prepare_large_batch(const LargeTeamArgs *__restrict__ descs) {
   const CoopArgs &A = descs[blockIdx.x].c;
   for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
@@ -2409,6 +2431,7 @@ __global__ void k_prepare_large_batch(const LargeTeamArgs *__restrict__ descs) {
     *A.status = PSCA_OK;
   }
 }
+#endif
 
 template <int LPMAX, int THREADS>
 __global__ void __launch_bounds__(THREADS) k_psca(CoopArgs A) {
@@ -2430,6 +2453,7 @@ __device__ __noinline__ void team_member(const CoopArgs *__restrict__ desc, int 
   psca_body<LP, kBatchThreads>(A, g);
 }
 
+#ifdef PSCA_TU_MAIN
 __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__restrict__ descs,
                                                               const int *__restrict__ lists,
                                                               const int *__restrict__ offsets,
@@ -2458,6 +2482,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__
     __syncthreads();   // the next instance reuses the LDS
   }
 }
+#endif
 
 // SigmaHat = Y Y^H / M.  Each workgroup stages Y through 64 KiB of LDS,
 // cov_chunk(L, M) columns at a time (all of Y when it fits) with coalesced
@@ -2466,6 +2491,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__
 __host__ __device__ inline int cov_chunk(int L, int M) { return min(M, 8192 / L); }
 inline size_t cov_lds_bytes(int L, int M) { return (size_t)cov_chunk(L, M) * L * sizeof(float2); }
 
+#ifdef PSCA_TU_MAIN
 __global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restrict__ Y, int L, int M,
                                                          float2 *__restrict__ Sh) {
   extern __shared__ float4 smem_raw[];
@@ -2512,8 +2538,10 @@ __global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restric
   Sh[i + (size_t)j * L] = acc;
   Sh[j + (size_t)i * L] = make_float2(acc.x, -acc.y);
 }
+#endif
 
 // Reset the barrier words, the abort word and the status before a launch of k_psca.
+#ifdef PSCA_TU_MAIN
 __global__ void k_prepare(unsigned *arrive, int G, unsigned *release, int32_t *abort_flag, int32_t *status) {
   for (int w = threadIdx.x; w < G; w += blockDim.x) arrive[w * 16] = 0u;
   if (threadIdx.x == 0) {
@@ -2522,8 +2550,10 @@ __global__ void k_prepare(unsigned *arrive, int G, unsigned *release, int32_t *a
     if (status) *status = PSCA_OK;
   }
 }
+#endif
 
 // The same for every instance of a batch launch: block b resets instance b.
+#ifdef PSCA_TU_MAIN
 __global__ void k_prepare_batch(const CoopArgs *__restrict__ descs) {
   const CoopArgs &A = descs[blockIdx.x];
   for (int w = threadIdx.x; w < A.G; w += blockDim.x) A.bar.arrive[w * 16] = 0u;
@@ -2533,13 +2563,20 @@ __global__ void k_prepare_batch(const CoopArgs *__restrict__ descs) {
     *A.status = PSCA_OK;
   }
 }
+#endif
 
+#ifdef PSCA_TU_MAIN
 __global__ void k_threshold(const float *__restrict__ x, int N, float theta, uint8_t *__restrict__ out) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n < N) out[n] = x[n] >= theta ? 1 : 0;
 }
+#endif
 
-}  // namespace
+}  // namespace psca_impl
+
+using namespace psca_impl;
+
+#ifdef PSCA_TU_MAIN   // host code, the C ABI and the no-allocation scratch: one translation unit
 
 // ---------------------------------------------------------------------------
 // Host side
@@ -3421,7 +3458,7 @@ int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int 
   return launch_batch(plan, (const char *)ctx->ddesc, st);
 }
 
-// ---- layer backward for 65 <= L <= 256 on teams (k_psca_back_large_teams) --
+// ---- layer backward for 65 <= L <= 256 on teams (k_psca_back_large_<lo>_<hi>)
 int large_back_tile(int Lp) {
   for (int nt = 64; nt >= 16; nt -= 16)
     if (lds_large_back_bytes(Lp, nt, kLargeThreads) <= kMaxLds) return nt;
@@ -3439,95 +3476,129 @@ size_t large_back_inst_ws_bytes(int Lp, int T, int N) {
          align_up((size_t)T * sizeof(float));
 }
 
-int large_back_capacity(psca_ctx *ctx) {
-  const KernelChoice kc{(const void *)k_psca_back_large_teams, kLargeThreads, 256};
-  return max_coresident(ctx, kc, kMaxLds);
+// The backward kernel for instances of LB = L_p / 16 blocks.
+struct BackRange {
+  int lo, hi;
+  const void *fn;
+};
+const BackRange kBackRanges[] = {
+#define PSCA_BACK_ENTRY(lo, hi) {lo, hi, (const void *)PSCA_BACK_NAME(lo, hi)},
+    PSCA_BACK_RANGES(PSCA_BACK_ENTRY)
+#undef PSCA_BACK_ENTRY
+};
+constexpr int kNumBackRanges = (int)(sizeof(kBackRanges) / sizeof(kBackRanges[0]));
+
+int back_range(int L) {
+  const int lb = (L + 15) >> 4;
+  for (int r = 0; r < kNumBackRanges; ++r)
+    if (lb >= kBackRanges[r].lo && lb <= kBackRanges[r].hi) return r;
+  return -1;
 }
 
-// B layer backwards (every L in 65..256) in one persistent launch on uniform
-// teams of T workgroups (T = 0: the co-resident grid shared evenly, and for
-// a single instance as many workgroups as Gram tiles).
-int run_large_backward(psca_ctx *ctx, int B, const psca_back_problem *pr, float rho, hipStream_t st) {
-  const int cap = large_back_capacity(ctx);
+// One launch of the backward of instances `idx` (one range of LB) on uniform
+// teams of T workgroups (T: the co-resident grid shared evenly, and for a
+// single instance as many workgroups as Gram tiles), its workspace at `base`.
+struct BackLaunch {
+  int range = -1, T = 0, n = 0;
+  size_t lds = 0, bytes = 0;
+  std::vector<int> idx, lp, nt, gv, team_of;
+  std::vector<std::vector<int>> team;
+  std::vector<size_t> off, part_off, part_need;
+  BatchPlan geo;   // lists, offsets and team starts
+};
+
+int plan_large_back(psca_ctx *ctx, const psca_back_problem *pr, BackLaunch &bl) {
+  const KernelChoice kc{kBackRanges[bl.range].fn, kLargeThreads, 256};
+  const int cap = max_coresident(ctx, kc, kMaxLds);
   if (cap <= 0) return PSCA_ENOTSUP;
-  std::vector<int> nt(B), gv(B), lp(B);
-  for (int b = 0; b < B; ++b) {
-    lp[b] = (pr[b].L + 15) & ~15;
-    nt[b] = large_back_tile(lp[b]);
-    if (nt[b] == 0) return PSCA_ENOTSUP;
-    gv[b] = (pr[b].N + nt[b] - 1) / nt[b];
+  const int B = (int)bl.idx.size();
+  bl.lp.resize(B);
+  bl.nt.resize(B);
+  bl.gv.resize(B);
+  for (int k = 0; k < B; ++k) {
+    const psca_back_problem &q = pr[bl.idx[k]];
+    bl.lp[k] = (q.L + 15) & ~15;
+    bl.nt[k] = large_back_tile(bl.lp[k]);
+    if (bl.nt[k] == 0) return PSCA_ENOTSUP;
+    bl.gv[k] = (q.N + bl.nt[k] - 1) / bl.nt[k];
   }
-  const int T = B == 1 ? std::min(cap, gv[0]) : std::max(1, cap / B);
-  const int n = std::max(1, std::min(cap / T, B));
+  bl.T = B == 1 ? std::min(cap, bl.gv[0]) : std::max(1, cap / B);
+  bl.n = std::max(1, std::min(cap / bl.T, B));
   std::vector<double> cost(B);
-  for (int b = 0; b < B; ++b) cost[b] = (double)pr[b].N * lp[b] * lp[b] + 2.0e5 * (lp[b] / 16);
-  std::vector<std::vector<int>> team(n);
-  std::vector<int> team_of(B), all(B);
-  for (int b = 0; b < B; ++b) all[b] = b;
-  assign_longest_first(all, cost, 0, n, team, team_of);
-  BatchPlan plan;   // the launch geometry (launch_back_large reads it)
-  plan.large = true;
-  plan.B = B;
-  plan.T = T;
-  plan.n_teams = n;
-  plan.team_start.assign(1, 0);
-  for (int t = 0; t < n; ++t) plan.team_start.push_back(plan.team_start.back() + T);
-  plan.offsets.push_back(0);
-  for (int t = 0; t < n; ++t) {
-    for (int b : team[t]) plan.lists.push_back(b);
-    plan.offsets.push_back((int)plan.lists.size());
+  for (int k = 0; k < B; ++k) cost[k] = (double)pr[bl.idx[k]].N * bl.lp[k] * bl.lp[k] + 2.0e5 * (bl.lp[k] / 16);
+  bl.team.assign(bl.n, {});
+  bl.team_of.assign(B, 0);
+  std::vector<int> all(B);
+  for (int k = 0; k < B; ++k) all[k] = k;
+  assign_longest_first(all, cost, 0, bl.n, bl.team, bl.team_of);
+  bl.geo = BatchPlan();
+  bl.geo.large = true;
+  bl.geo.B = B;
+  bl.geo.T = bl.T;
+  bl.geo.n_teams = bl.n;
+  bl.geo.team_start.assign(1, 0);
+  for (int t = 0; t < bl.n; ++t) bl.geo.team_start.push_back(bl.geo.team_start.back() + bl.T);
+  bl.geo.offsets.push_back(0);
+  for (int t = 0; t < bl.n; ++t) {
+    for (int k : bl.team[t]) bl.geo.lists.push_back(k);
+    bl.geo.offsets.push_back((int)bl.geo.lists.size());
   }
-  std::vector<size_t> off(B);
+  bl.off.resize(B);
   size_t total = 0;
-  for (int b = 0; b < B; ++b) {
-    off[b] = total;
-    total += large_back_inst_ws_bytes(lp[b], T, pr[b].N);
-    plan.lds = std::max(plan.lds, lds_large_back_bytes(lp[b], nt[b], kLargeThreads));
+  for (int k = 0; k < B; ++k) {
+    bl.off[k] = total;
+    total += large_back_inst_ws_bytes(bl.lp[k], bl.T, pr[bl.idx[k]].N);
+    bl.lds = std::max(bl.lds, lds_large_back_bytes(bl.lp[k], bl.nt[k], kLargeThreads));
   }
-  std::vector<size_t> part_off(n);
-  for (int t = 0; t < n; ++t) {   // per team: the partials of Sigma / G_a and of G_b
-    size_t need = 0;
-    for (int b : team[t]) need = std::max(need, (size_t)gv[b] * packed_entries(lp[b]));
-    part_off[t] = total;
-    total += 2 * align_up(need * sizeof(float2));
+  bl.part_off.assign(bl.n, 0);
+  bl.part_need.assign(bl.n, 0);
+  for (int t = 0; t < bl.n; ++t) {   // per team: the partials of Sigma / G_a and of G_b
+    for (int k : bl.team[t]) bl.part_need[t] = std::max(bl.part_need[t], (size_t)bl.gv[k] * packed_entries(bl.lp[k]));
+    bl.part_off[t] = total;
+    total += 2 * align_up(bl.part_need[t] * sizeof(float2));
   }
-  int rc = ensure_ws(ctx, total);
-  if (rc != PSCA_OK) return rc;
-  char *base = (char *)ctx->ws;
+  bl.bytes = total;
+  return PSCA_OK;
+}
+
+int launch_large_back(psca_ctx *ctx, const psca_back_problem *pr, float rho, const BackLaunch &bl, char *base,
+                      hipStream_t st) {
+  const int B = (int)bl.idx.size();
+  const BatchPlan &plan = bl.geo;
   const size_t bytes = align_up((size_t)B * sizeof(LargeBackArgs)) + align_up(plan.lists.size() * sizeof(int)) +
                        align_up(plan.offsets.size() * sizeof(int)) + align_up(plan.team_start.size() * sizeof(int));
   char *host = nullptr;
+  int rc;
   if ((rc = stage_desc(ctx, bytes, &host)) != PSCA_OK) return rc;
   LargeBackArgs *d = (LargeBackArgs *)host;
-  for (int b = 0; b < B; ++b) {
-    const psca_back_problem &q = pr[b];
-    const InstPlan ip{lp[b], nt[b] / 16, nt[b], T, plan.lds, 0};
+  for (int k = 0; k < B; ++k) {
+    const psca_back_problem &q = pr[bl.idx[k]];
+    const InstPlan ip{bl.lp[k], bl.nt[k] / 16, bl.nt[k], bl.T, bl.lds, 0};
     LargeBackArgs a;
     fill_args(a.f.c, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, 1, rho, q.x_in, nullptr,
               nullptr, nullptr, nullptr, q.status, ip);
-    char *w = base + off[b];
-    bind_large_ws(a.f, w, lp[b], T, q.N);
-    w += large_inst_ws_bytes(lp[b], T, q.N);
-    const size_t E = packed_entries(lp[b]), ncol = (size_t)(q.N + 15) / 16;
+    char *w = base + bl.off[k];
+    bind_large_ws(a.f, w, bl.lp[k], bl.T, q.N);
+    w += large_inst_ws_bytes(bl.lp[k], bl.T, q.N);
+    const size_t E = packed_entries(bl.lp[k]), ncol = (size_t)(q.N + 15) / 16;
     a.gram_a = (float2 *)w;   w += align_up(E * sizeof(float2));
     a.gram_b = (float2 *)w;   w += align_up(E * sizeof(float2));
-    a.bmat = (float2 *)w;     w += align_up(ncol * (size_t)lp[b] * 16 * sizeof(float2));
-    a.cmat = (float2 *)w;     w += align_up(ncol * (size_t)lp[b] * 16 * sizeof(float2));
+    a.bmat = (float2 *)w;     w += align_up(ncol * (size_t)bl.lp[k] * 16 * sizeof(float2));
+    a.cmat = (float2 *)w;     w += align_up(ncol * (size_t)bl.lp[k] * 16 * sizeof(float2));
     a.wa = (float *)w;        w += align_up((size_t)q.N * sizeof(float));
     a.wb = (float *)w;        w += align_up((size_t)q.N * sizeof(float));
     a.d0 = (float *)w;        w += align_up((size_t)q.N * sizeof(float));
     a.rho_part = (float *)w;
-    a.f.c.partials = (float2 *)(base + part_off[team_of[b]]);
+    const int t = bl.team_of[k];
+    a.f.c.partials = (float2 *)(base + bl.part_off[t]);
     a.f.c.pstride = E;
-    size_t need = 0;
-    for (int bb : team[team_of[b]]) need = std::max(need, (size_t)gv[bb] * packed_entries(lp[bb]));
-    a.partials_b = (float2 *)(base + part_off[team_of[b]] + align_up(need * sizeof(float2)));
-    a.f.Gv = gv[b];
+    a.partials_b = (float2 *)(base + bl.part_off[t] + align_up(bl.part_need[t] * sizeof(float2)));
+    a.f.Gv = bl.gv[k];
     a.rho = rho;
     a.v = q.v;
     a.grad_x = q.grad_x;
     a.grad_rho = q.grad_rho;
-    d[b] = a;
+    d[k] = a;
   }
   char *p = host + align_up((size_t)B * sizeof(LargeBackArgs));
   memcpy(p, plan.lists.data(), plan.lists.size() * sizeof(int));
@@ -3546,14 +3617,40 @@ int run_large_backward(psca_ctx *ctx, int B, const psca_back_problem *pr, float 
   const int *lists = (const int *)(dimg + align_up((size_t)B * sizeof(LargeBackArgs)));
   const int *offsets = (const int *)((const char *)lists + align_up(plan.lists.size() * sizeof(int)));
   const int *team_start = (const int *)((const char *)offsets + align_up(plan.offsets.size() * sizeof(int)));
-  int n_teams = n;
+  int n_teams = bl.n;
   hipLaunchKernelGGL(k_prepare_large_back, dim3(B), dim3(256), 0, st, descs);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
   void *args[] = {(void *)&descs, (void *)&lists, (void *)&offsets, (void *)&team_start, (void *)&n_teams};
-  if (hipLaunchCooperativeKernel((const void *)k_psca_back_large_teams, dim3(plan.team_start.back()),
-                                 dim3(kLargeThreads), args, (unsigned)plan.lds, st) != hipSuccess) {
+  if (hipLaunchCooperativeKernel(kBackRanges[bl.range].fn, dim3(plan.team_start.back()), dim3(kLargeThreads), args,
+                                 (unsigned)bl.lds, st) != hipSuccess) {
     (void)hipGetLastError();
     return PSCA_EHIP;
+  }
+  return PSCA_OK;
+}
+
+// B layer backwards (every L in 65..256): one persistent launch per range of
+// block counts present (one launch for a batch of one pilot length).
+int run_large_backward(psca_ctx *ctx, int B, const psca_back_problem *pr, float rho, hipStream_t st) {
+  std::vector<BackLaunch> launches;
+  for (int r = 0; r < kNumBackRanges; ++r) {
+    BackLaunch bl;
+    bl.range = r;
+    for (int b = 0; b < B; ++b)
+      if (back_range(pr[b].L) == r) bl.idx.push_back(b);
+    if (!bl.idx.empty()) launches.push_back(bl);
+  }
+  size_t total = 0;
+  int rc;
+  for (auto &bl : launches) {
+    if ((rc = plan_large_back(ctx, pr, bl)) != PSCA_OK) return rc;
+    total += align_up(bl.bytes);
+  }
+  if ((rc = ensure_ws(ctx, total)) != PSCA_OK) return rc;
+  size_t at = 0;
+  for (auto &bl : launches) {
+    if ((rc = launch_large_back(ctx, pr, rho, bl, (char *)ctx->ws + at, st)) != PSCA_OK) return rc;
+    at += align_up(bl.bytes);
   }
   return PSCA_OK;
 }
@@ -4192,3 +4289,4 @@ int psca_threshold(const float *x, int N, float theta, uint8_t *support, void *s
 }
 
 }  // extern "C"
+#endif   // PSCA_TU_MAIN

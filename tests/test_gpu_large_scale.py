@@ -46,7 +46,7 @@ PERTURB = 1e-6   # relative perturbation of every oracle iterate in the stabilit
 
 
 def _net_rhos():
-    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20.json")) as f:
+    with open(os.path.join(ROOT, "paper_2503_15259_amd", "data", "net_ML-K_K20_N10000_L200.json")) as f:
         return [float(np.float32(r)) for r in json.load(f)["rho"]]
 
 
