@@ -65,10 +65,13 @@ typedef enum {
 } psca_status;
 
 /* Largest pilot length L.  Up to 96 the L x L work matrix lives in each
- * workgroup's LDS; from 97 to 256 a single detection factors Sigma in device
- * memory cooperatively across its workgroups (psca_detect, psca_detect_y,
- * psca_iterate, psca_net_forward).  psca_detect_batch and its plans take
- * L <= 96, psca_layer_backward L <= 64 (PSCA_ENOTSUP beyond). */
+ * workgroup's LDS; from 97 to 256 Sigma is factored in device memory
+ * cooperatively by the instance's team of workgroups.  Every entry point
+ * takes 1 <= L <= 256, with two exceptions: a batch (psca_detect_batch, its
+ * plans, psca_layer_backward_batch) must lie wholly on one side of the
+ * boundary of its kernel family (L <= 96 or L > 96 for detections, L <= 64
+ * or L > 64 for the layer backward), else PSCA_ENOTSUP; and
+ * psca_detect_noalloc takes L <= 96. */
 #define PSCA_MAX_L 256
 
 /*
@@ -186,7 +189,8 @@ int psca_net_forward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S
  * (DEVICE, one float).  Sigma^-1 is recomputed from x_in (the layer's input
  * iterate), not stored.  The clip of Lemmas 1-4 passes gradient where its
  * argument lies inside the bounds (bounds included).  prm->iters and
- * prm->rho are ignored.  Needs L <= 64 (PSCA_ENOTSUP otherwise). */
+ * prm->rho are ignored.  1 <= L <= 256; MAP-K2 has no backward
+ * (PSCA_ENOTSUP). */
 int psca_layer_backward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
                         const psca_params *prm, float rho, const float *x_in, const float *v, float *grad_x,
                         float *grad_rho, int32_t *status, void *stream);
@@ -209,8 +213,8 @@ typedef struct {
  * (teams of workgroups as in psca_detect_batch), equivalent to B calls of
  * psca_layer_backward: the backward of one layer of the unrolled network
  * over a minibatch.  `problems` is a HOST array read before the call
- * returns.  Every instance is validated first (L <= 64; MAP-K2 has no
- * backward: PSCA_ENOTSUP). */
+ * returns.  Every instance is validated first (MAP-K2 has no backward, and
+ * a batch mixing L <= 64 with L > 64 is PSCA_ENOTSUP). */
 int psca_layer_backward_batch(psca_ctx *ctx, int B, const psca_back_problem *problems, float rho, void *stream);
 
 /* One instance of a batch: the arguments of psca_detect.  All pointers are
@@ -235,7 +239,8 @@ typedef struct {
  * for a batch of the same (L, N) list, else a default (one team per instance
  * when the batch fits the GPU at once, else the smallest teams).  Every
  * instance is validated as in psca_detect before anything is launched
- * (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one; L <= 96). */
+ * (PSCA_EINVAL / PSCA_ENOTSUP for the first bad one; a batch mixing L <= 96
+ * with L > 96 is PSCA_ENOTSUP: the two sides run in different kernels). */
 int psca_detect_batch(psca_ctx *ctx, int B, const psca_problem *problems, void *stream);
 
 /* Autotuner for psca_detect_batch: times the batch with every candidate team

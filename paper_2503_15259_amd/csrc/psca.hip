@@ -8,24 +8,36 @@
 //   x~_n = clip(x_n - grad_n / curv_n, lo, hi)    (Lemmas 1-4)
 //   x_n <- (1 - rho_k) x_n + rho_k x~_n           (eqs. Update_*)
 //
-// Execution model.  One detection is ONE cooperative persistent kernel
-// (k_psca) with G workgroups of 256 threads (512 for L > 64).  Workgroup g owns
-// NT = 16 * ncb consecutive columns of S; that tile, the tile's iterate and
-// its pathloss stay in LDS for the whole solve, and the Sigma^-1-independent
-// operand SigmaHat stays in registers.  Per iteration:
-//   A. tile partial  P_g = S_g diag(w_g) S_g^H   (FP32 MFMA, lower 16x16 blocks) -> HBM
-//      grid barrier
-//   B. workgroup g sums a contiguous slice of the G partials (fixed order) -> Sigma
-//      grid barrier
-//   C. every workgroup factors Sigma redundantly in LDS/registers (identical
-//      inputs and code, so all reach identical results and decisions), forms
-//      Sigma^-1 = W^H W on MFMA, then B = Sigma^-1 S_g, D = SigmaHat B (MFMA),
-//      the quadratic forms, the coordinate step and the update of its columns.
-// Two grid barriers per iteration; no atomics on data, so a run is bitwise
-// reproducible for a given launch shape.
+// Execution model.  Every detection, batch and network forward is ONE
+// persistent launch whose workgroups meet at device-wide barriers (agent-scope
+// fences, bounded spins that report PSCA_ESYNC instead of hanging); there are
+// no atomics on data, so a result is bitwise reproducible for a given launch
+// shape.  Workgroup numbers are XCD-major, so the workgroups that share an
+// instance share an L2.  Three kernel families:
 //
-// Complex GEMMs use v_mfma_f32_16x16x4f32 on the real 4-product split:
-//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
+//   k_psca, k_psca_teams (L <= 96).  A workgroup owns NT = 16 * ncb columns
+//     of S; the tile, its iterate and pathloss stay in LDS for the whole
+//     solve.  Per iteration:
+//       A. tile partial P_g = S_g diag(w_g) S_g^H (FP64 MFMA Gram) -> HBM
+//       B. workgroup g sums a fixed slice of the partials (FP64) -> Sigma
+//       C. every workgroup factors Sigma redundantly in LDS (identical inputs
+//          and code, so identical results and decisions), forms Sigma^-1 on
+//          MFMA, then B = Sigma^-1 S_g, D = SigmaHat B, the quadratic forms,
+//          the coordinate step and the update of its columns.
+//     k_psca_teams runs a list of instances (uneven batches, minibatches) on
+//     teams of workgroups, one instance per team at a time.
+//   k_psca_large_teams (97 <= L <= 256).  Sigma, its factor and
+//     Sigma - SigmaHat live in device memory; the factorisation is spread
+//     over the team, and the solves, q, q - r and the coordinate step of each
+//     16-column block run in one wavefront's registers.
+//   k_psca_back_teams (L <= 64) and k_psca_back_large_* (65 <= L <= 256).
+//     The vector-Jacobian product of one unrolled layer with respect to its
+//     input and its step size, Sigma^-1 recomputed from the layer input.
+//
+// Complex GEMMs use v_mfma_f32_16x16x4f32, on the real 4-product split
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B
+// or with three real products (Gauss) where the operands allow it; the Gram
+// partials use v_mfma_f64_16x16x4f64.
 // Operand layout of that instruction (wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; it receives C[4*(l/16)+v][l%16] in accumulator v.
 
@@ -1679,9 +1691,8 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
 // One instance runs on a team of T workgroups.  Its devices are cut into Gv
 // Gram tiles of NT = 16 ncb columns; rank g of the team forms the packed
 // partials of tiles g, g + T, g + 2T, ... (each tile staged in LDS, FP64
-// Gram as in k_psca_large, one partial slot per tile).  Phase B sums the Gv
-// slots, 1/T of packed Sigma per rank; C1 factors Sigma in memory as
-// k_psca_large does.  The solves run per 16-column block with the block
+// Gram, one partial slot per tile).  Phase B sums the Gv slots, 1/T of
+// packed Sigma per rank; C1 factors Sigma in memory (factor_in_memory).  The solves run per 16-column block with the block
 // held in registers: wave w of rank g takes the column blocks 8g + w,
 // 8g + w + 8T, ..., so every wave of the team has work whatever the tile
 // width, and a column block's substitutions, q, q - r and coordinate step

@@ -205,7 +205,7 @@ class PscaNet(torch.nn.Module):
 def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch, batched: bool = True) -> float:
     """One Adam step on a minibatch of (Sigma_hat, S, params, alpha, g): the
     mean BCE over the minibatch.  batched: forward and backward of the whole
-    minibatch in batched launches (L <= 64), else instance by instance."""
+    minibatch in batched launches, else instance by instance."""
     opt.zero_grad()
     if batched:
         loss = batch_loss(net, batch)

@@ -10,8 +10,11 @@ from it, else every step draws fresh instances.  Validation uses seeds from
 10^6 on, disjoint from training.  Every --val-every steps the validation
 loss is evaluated; the step sizes of the best validation loss are kept and
 training stops once --patience evaluations in a row have not improved it
-(the paper trains until the validation loss stops improving).  The
-detection threshold is the one minimising the validation error rate.
+(the paper trains until the validation loss stops improving).  The step
+sizes start from the schedule rho_{k+1} = rho_k (1 - rho_k / 2), rho_0 = 0.5
+(Sec. VI), or with --init from those of a network trained before (a JSON file
+written by this script; its "rho" must have K entries).  The detection
+threshold is the one minimising the validation error rate.
 Every forward and backward pass runs in the HIP kernels: a minibatch goes
 through one psca_detect_batch launch with every iterate recorded and one
 psca_layer_backward_batch launch per layer, validation through
@@ -57,6 +60,7 @@ def main():
     ap.add_argument("--p", type=float, default=0.1)
     ap.add_argument("--eps", type=float, default=0.01)
     ap.add_argument("--workers", type=int, default=16, help="host processes drawing instances")
+    ap.add_argument("--init", default="", help="start from the step sizes of this trained-network JSON file")
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
 
@@ -111,6 +115,16 @@ def main():
     print(json.dumps({"drawn": (len(pool) if pool else 0) + len(val), "seconds": round(time.perf_counter() - t0, 1)}),
           flush=True)
     model = NET.PscaNet(args.K, val[0][2], ctx=ctx)
+    init = {"from": "schedule rho_0 = 0.5, rho_{k+1} = rho_k (1 - rho_k / 2)"}
+    if args.init:
+        with open(args.init) as f:
+            prev = json.load(f)
+        if len(prev["rho"]) != args.K or prev.get("variant") != args.variant:
+            raise SystemExit(f"--init {args.init}: K={len(prev['rho'])} {prev.get('variant')}, "
+                             f"need K={args.K} {args.variant}")
+        with torch.no_grad():
+            model.rho.copy_(torch.tensor(prev["rho"], dtype=torch.float32))
+        init = {"from": os.path.basename(args.init), "rho": prev["rho"], "train": prev.get("train")}
     opt = torch.optim.Adam(model.parameters(), lr=args.lr)
 
     def val_loss():
@@ -163,7 +177,7 @@ def main():
                      "val_every": args.val_every, "patience": args.patience,
                      "N": args.N, "L": args.L, "M": args.M, "p": args.p, "eps": args.eps,
                      "seeds": "training: [3, i] for i < distinct_instances; validation: [3, 10^6 + i]"},
-           "history": history}
+           "init": init, "history": history}
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
