@@ -552,9 +552,14 @@ def run_large(args):
         out_err = max(float(np.max(np.abs(hists4[i][-1].astype(np.float64) - cpu_x[i]))) for i in S4)
         with mp.get_context("spawn").Pool(len(S4)) as pool:
             steps = pool.map(_large_net_steps_task, [(i, trained["rho"], hists4[i]) for i in S4])
+        truth4 = np.concatenate([insts[i].alpha for i in S4])
+        eer_gpu = metrics.equal_error_point(np.concatenate([hists4[i][-1] for i in S4]), truth4)[0]
+        eer_orc = metrics.equal_error_point(np.concatenate([cpu_x[i] for i in S4]), truth4)[0]
         parity = {"network ML-K": {"max_abs_err_alpha_per_layer": max(w for _, w in steps),
                                    "max_abs_err_alpha_output": out_err, "instances_compared": len(S4),
-                                   "bar": 1e-4}}
+                                   "bar": 1e-4,
+                                   "equal_error_rate_of_the_sample": {"gpu": round(float(eer_gpu), 5),
+                                                                      "oracle": round(float(eer_orc), 5)}}}
 
     flops = B * K * iteration_flops(N, L)
     achieved = flops / (launch_ms / 1e3) / 1e12

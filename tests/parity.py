@@ -72,16 +72,19 @@ def map_ur_device_parity(x_gpu, x_ref, margin, delta=BRANCH_DELTA):
     return rep
 
 
-def stepwise_parity(prob, hist_gpu, rhos, delta=BRANCH_DELTA):
+def stepwise_parity(prob, hist_gpu, rhos, delta=BRANCH_DELTA, errors=None):
     """One oracle iteration from each GPU iterate x^(k) (rounded values taken
     as exact) against the GPU's x^(k+1), element by element at the parity
     bar.  MAP-UR devices whose x^(k) lies within delta (relative) of a branch
     point of p^eps are skipped at that step.  Returns (worst report, total
-    skipped device-steps)."""
+    skipped device-steps); with a list `errors`, appends each step's
+    |x_gpu^(k+1) - step(x_gpu^(k))| (float32, every device) to it."""
     hist = np.asarray(hist_gpu, dtype=np.float64)
     worst, skipped = None, 0
     for k, rho in enumerate(rhos):
         rec = O.psca_iteration(prob, hist[k], float(rho))
+        if errors is not None:
+            errors.append(np.abs(hist[k + 1] - rec.x_next).astype(np.float32))
         keep = np.ones(prob.N, dtype=bool)
         if prob.variant == O.MAP_UR:
             pr = prob.prior
