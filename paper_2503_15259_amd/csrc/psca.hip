@@ -1775,6 +1775,7 @@ struct LargeTeamArgs {
   float2 *delta;     // packed Sigma - SigmaHat
   float2 *lbuf;      // packed off-diagonal blocks of the factor L
   float *xw;         // [N] the iterate
+  float2 *xfull;     // [Lp][Lp] column-major: L^-1 (Sigma - SigmaHat) between the two passes of phase C2
   int Gv;            // Gram tiles, ceil(N / NT)
 };
 
@@ -2011,13 +2012,73 @@ __device__ __forceinline__ void cb_hermv(const float2 (&y)[LB][4], const float2 
   }
 }
 
-// One wave: Y = L^-1 S_c (q = sum |y|^2), B = L^-H Y (= Sigma^-1 S_c),
-// q - r = Re b^H (Sigma - SigmaHat) b and the coordinate step of the 16
-// devices c0 .. c0 + 15.  The three passes are the ones of cb_forward,
-// cb_backward and cb_quad_lower written out in one body with one operand
-// ring: built from those helpers, this kernel's solves compile to a
-// schedule that takes 24 % longer (4.03 against 3.24 ms per iteration for
-// 64 instances at N = 10^4, L = 200).
+// Phase C2 of a large-L iteration: Delta' = L^-1 (Sigma - SigmaHat) L^-H, so
+// that q - r = Re b^H (Sigma - SigmaHat) b = y^H Delta' y with y = L^-1 s and
+// the column-block solves need no backward substitution (a third of their
+// block products).  Two passes over the Lb column blocks of an L x L
+// matrix, one column block per wavefront of the team: X = L^-1 Delta (full,
+// column-major, in xfull), a team barrier, then Delta' = L^-1 X^H
+// (X^H = Delta L^-H, Delta Hermitian), whose lower blocks overwrite Delta in
+// packed form, and a team barrier before the solves read them.  Returns
+// false when a barrier gave up.
+template <int LB, int THREADS>
+__device__ __forceinline__ bool transform_delta(const LargeTeamArgs &Tg, const float2 *Wd, int T, int g,
+                                                unsigned &gen, int *s_ok) {
+  const CoopArgs &A = Tg.c;
+  constexpr int kWaves = THREADS / 64, Lp = 16 * LB;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
+  const int lo_n = (4 * lq) * 16 + l16;
+  float2 *X = Tg.xfull, *D = Tg.delta;
+  for (int j = g * kWaves + wave; j < LB; j += T * kWaves) {
+    // column block j of Delta from its packed lower blocks (column-major
+    // within a block): y[R][v] = Delta[16R + 4h + v][16j + l16]
+    float2 y[LB][4];
+#pragma unroll
+    for (int R = 0; R < LB; ++R)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * lq + v;
+        if (R >= j) {
+          y[R][v] = D[(size_t)blk_index(R, j) * 256 + l16 * 16 + i];
+        } else {
+          const float2 t = D[(size_t)blk_index(j, R) * 256 + i * 16 + l16];
+          y[R][v] = make_float2(t.x, -t.y);
+        }
+      }
+    cb_forward<LB>(y, Tg.lbuf, Wd, lo_n);
+#pragma unroll
+    for (int R = 0; R < LB; ++R)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(size_t)(16 * j + l16) * Lp + 16 * R + 4 * lq + v] = y[R][v];
+  }
+  if (!grid_sync(A.bar, T, g, gen, s_ok)) return false;
+  for (int j = g * kWaves + wave; j < LB; j += T * kWaves) {
+    // column block j of X^H: y[R][v] = conj(X[16j + l16][16R + 4h + v])
+    float2 y[LB][4];
+#pragma unroll
+    for (int R = 0; R < LB; ++R)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float2 t = X[(size_t)(16 * R + 4 * lq + v) * Lp + 16 * j + l16];
+        y[R][v] = make_float2(t.x, -t.y);
+      }
+    cb_forward<LB>(y, Tg.lbuf, Wd, lo_n);
+#pragma unroll
+    for (int R = 0; R < LB; ++R)
+      if (R >= j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) D[(size_t)blk_index(R, j) * 256 + l16 * 16 + 4 * lq + v] = y[R][v];
+      }
+  }
+  return grid_sync(A.bar, T, g, gen, s_ok);
+}
+
+// One wave: Y = L^-1 S_c (q = sum |y|^2), q - r = y^H Delta' y (phase C2)
+// and the coordinate step of the 16 devices c0 .. c0 + 15.  The two passes
+// are the ones of cb_forward and cb_quad_lower written out in one body with
+// one operand ring: built from those helpers (then with a backward
+// substitution too), this kernel's solves compiled to a schedule that took
+// 24 % longer.
 template <int LB>
 __device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, const float2 *Wd, int c0, int it,
                                                    float rho, bool last) {
@@ -2085,49 +2146,9 @@ __device__ __forceinline__ void solve_column_block(const LargeTeamArgs &Tg, cons
   q += __shfl_xor(q, 16);
   q += __shfl_xor(q, 32);
 
-  // backward substitution: B_R = W_RR^H (Y_R - sum_{K>R} L_KR^H B_K), R from
-  // the last block row up; task t is block (K, R) with r = tri_row(t),
-  // R = LB - 1 - r, K = R + 1 + t - r (r - 1) / 2
-  auto load_b = [&](int t, float2 (&dst)[4]) {
-    const int r = tri_row(t), R = LB - 1 - r, K = R + 1 + t - r * (r - 1) / 2;
-    const float2 *blk = pblk(lbuf, K, R);
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const float2 x = ldg2(blk, lo_t + ks);   // L_KR[4h + ks][j]
-      dst[ks] = make_float2(x.x, -x.y);
-    }
-  };
-  if (nf > 0) load_b(0, ring[0]);
-  if (nf > 1) load_b(1, ring[1]);
-#pragma unroll
-  for (int r = 0; r < LB; ++r) {
-    const int R = LB - 1 - r;
-    acc.zero();
-#pragma unroll
-    for (int j = 0; j < r; ++j) {
-      const int t = r * (r - 1) / 2 + j, K = R + 1 + j;
-      if (t + 2 < nf) load_b(t + 2, ring[(t + 2) % 3]);
-      acc.add(j & 1, ring[t % 3], y[K]);
-    }
-    float2 r4[4], w4[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float2 d = acc.get(v);
-      r4[v] = make_float2(y[R][v].x - d.x, y[R][v].y - d.y);
-    }
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const float2 w = Wd[R * 256 + lo_t + ks];   // W_RR[4h + ks][j]
-      w4[ks] = make_float2(w.x, -w.y);
-    }
-    acc.zero();
-    acc.add(0, w4, r4);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) y[R][v] = acc.get(v);
-  }
-
-  // q - r = b^H (Sigma - SigmaHat) b = sum_I b_I^H D_II b_I + 2 Re sum_{K<I} b_I^H D_IK b_K;
-  // task t is the packed block t = (I, K), K <= I
+  // q - r = y^H Delta' y = sum_I y_I^H D'_II y_I + 2 Re sum_{K<I} y_I^H D'_IK y_K with
+  // Delta' = L^-1 (Sigma - SigmaHat) L^-H from phase C2; task t is the packed
+  // block t = (I, K), K <= I
   constexpr int nd = LB * (LB + 1) / 2;
   auto load_d = [&](int t, float2 (&dst)[4]) {
     const int I = tri_row(t) - 1, K = t - I * (I + 1) / 2;
@@ -2258,6 +2279,9 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
     if (f == 1) failed = true;
     if (f == 2) aborted = true;
     if (failed || aborted) break;
+    // ---- C2. Delta' = L^-1 (Sigma - SigmaHat) L^-H in place of Sigma - SigmaHat
+    if (!transform_delta<LB, THREADS>(Tg, Wd, T, g, gen, &s_ok)) { aborted = true; break; }
+    PSCA_MARK(it, 8);
     // ---- C4, C5. solves, quadratic forms and coordinate steps per column block
     float rho;
     if (A.rho_fixed >= 0.0f) rho = A.rho_fixed;
@@ -3411,11 +3435,12 @@ int large_tile(int Lp) {
 
 // Per-instance workspace of a large-L launch: packed Sigma, Sigma - SigmaHat
 // and L, T barrier words, release/abort/status words, the iterate exchange
-// [2][N] (MAP-K2) and the iterate [N].
+// [2][N] (MAP-K2), the iterate [N] and an Lp x Lp matrix for phase C2.
 size_t large_inst_ws_bytes(int Lp, int T, int N) {
   const size_t E = packed_entries(Lp);
   return 3 * align_up(E * sizeof(float2)) + align_up((size_t)T * 16 * sizeof(unsigned)) +
-         3 * align_up(sizeof(unsigned)) + align_up(2 * (size_t)N * sizeof(float)) + align_up((size_t)N * sizeof(float));
+         3 * align_up(sizeof(unsigned)) + align_up(2 * (size_t)N * sizeof(float)) + align_up((size_t)N * sizeof(float)) +
+         align_up((size_t)Lp * Lp * sizeof(float2));
 }
 
 // Points a descriptor's work buffers into `w` (laid out as large_inst_ws_bytes).
@@ -3430,7 +3455,8 @@ void bind_large_ws(LargeTeamArgs &a, char *w, int Lp, int T, int N) {
   if (!a.c.status) a.c.status = (int32_t *)w;
   w += align_up(sizeof(unsigned));
   a.c.a.xg = (float *)w;            w += align_up(2 * (size_t)N * sizeof(float));
-  a.xw = (float *)w;
+  a.xw = (float *)w;                w += align_up((size_t)N * sizeof(float));
+  a.xfull = (float2 *)w;
 }
 
 // Plans a batch of large-L instances on uniform teams of T workgroups:

@@ -66,6 +66,7 @@ def main():
 
     import torch
     from . import instances as I
+    from . import metrics
     from . import net as NET
     from . import psca as P
 
@@ -127,15 +128,22 @@ def main():
         init = {"from": os.path.basename(args.init), "rho": prev["rho"], "train": prev.get("train")}
     opt = torch.optim.Adam(model.parameters(), lr=args.lr)
 
-    def val_loss():
+    def val_eval():
+        """Validation loss (the stopping criterion) and, for the record, the
+        pooled equal-error rate of the validation outputs."""
         with torch.no_grad():
-            tot = 0.0
+            tot, scores, truths = 0.0, [], []
             for Sh, S, prm, alpha, g in val:
-                tot += float(NET.bce(model(Sh, S, prm), alpha, g, model.known))
+                x = model(Sh, S, prm)
+                tot += float(NET.bce(x, alpha, g, model.known))
+                scores.append((x if model.known else x / g).cpu().numpy())
+                truths.append(alpha.cpu().numpy())
             model.status.check()
-            return tot / len(val)
+            eer = metrics.equal_error_point(np.concatenate(scores), np.concatenate(truths))[0]
+            return tot / len(val), eer
 
-    history = [{"step": 0, "val_loss": val_loss()}]
+    loss0, eer0 = val_eval()
+    history = [{"step": 0, "val_loss": loss0, "val_eer": eer0}]
     best_val, best_rho, best_step, stale = history[0]["val_loss"], model.rho.detach().clone(), 0, 0
     rng = np.random.default_rng([wid, args.batch, args.pool])
     t0 = time.perf_counter()
@@ -149,7 +157,8 @@ def main():
         visits += len(batch)
         loss = NET.train_step(model, opt, batch)
         if step % args.val_every == 0 or step == args.steps:
-            history.append({"step": step, "train_loss": loss, "val_loss": val_loss(),
+            vloss, veer = val_eval()
+            history.append({"step": step, "train_loss": loss, "val_loss": vloss, "val_eer": veer,
                             "seconds": round(time.perf_counter() - t0, 2)})
             print(json.dumps(history[-1]), flush=True)
             if history[-1]["val_loss"] < best_val:   # keep the step sizes of the best validation loss
