@@ -109,6 +109,15 @@ typedef enum {
  *              2d / (d_hi^2 - d_lo^2) (eq. dispdf, the paper's model);
  *              PSCA_DIST_LINEAR (1): uniform in d, p_D(d) = 1 / (d_hi - d_lo).
  *              Other values return PSCA_EINVAL for MAP-UR; ignored otherwise.
+ *   x0         optional DEVICE [N] starting iterate x^(0), inside the
+ *              variant's box; NULL starts from zero (Algorithm 1).  Read once
+ *              at the start of the launch.  Taken by psca_detect,
+ *              psca_detect_y, psca_detect_noalloc, psca_net_forward and the
+ *              batch entry points (continuing a detection, e.g. plain PSCA
+ *              from the unrolled network's output); psca_iterate and the
+ *              layer backward take their iterate as an argument and ignore
+ *              it.  Must not alias the call's outputs (PSCA_EINVAL where the
+ *              output is a single vector).
  */
 typedef struct {
   int32_t variant;
@@ -127,6 +136,7 @@ typedef struct {
   const float *c2_val;
   int32_t c2_nnz;
   int32_t dist_law;
+  const float *x0;
 } psca_params;
 
 /* Values of psca_params.dist_law. */

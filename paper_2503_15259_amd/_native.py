@@ -52,6 +52,7 @@ class PscaParams(ctypes.Structure):
         ("c2_val", ctypes.c_void_p),
         ("c2_nnz", ctypes.c_int32),
         ("dist_law", ctypes.c_int32),
+        ("x0", ctypes.c_void_p),
     ]
 
 

@@ -224,6 +224,40 @@ def train_step(net: PscaNet, opt: torch.optim.Optimizer, batch, batched: bool = 
     return float(total) if total is not None else 0.0
 
 
+def stationarity_residual(Sigma_hat, S, params: P.Params, x: torch.Tensor, ctx=None) -> float:
+    """How far x is from a stationary point of the estimator's objective,
+    judged by plain PSCA: one iteration from x gives the coordinate
+    minimisers x~ (Lemmas 1-4), and x~ = x exactly at a stationary point
+    (Theorems 2-5).  Returns max|x~ - x| / max(max|x|, 1e-30)."""
+    _, _, _, xt = P.iterate(Sigma_hat, S, x, 1.0, replace(params, x0=None), ctx=ctx)
+    scale = torch.clamp(x.abs().max(), min=1e-30)
+    return float(((xt - x).abs().max() / scale).item())
+
+
+def detect_with_fallback(net: "PscaNet", Sigma_hat, S, params: Optional[P.Params] = None, tol: float = 1e-2,
+                         extra_iters: int = 100, ctx=None):
+    """The unrolled network with plain PSCA as its judge and its fallback:
+    the network's output x^(K) is accepted when its stationarity residual
+    (stationarity_residual) is at most tol; otherwise plain PSCA continues
+    from x^(K) for extra_iters iterations with the schedule (one launch,
+    params.x0 = x^(K)).  Returns (x, report) with the residual before and
+    after and whether the fallback ran."""
+    prm = params or net.params
+    ctx = ctx or net.ctx
+    with torch.no_grad():
+        x = net(Sigma_hat, S, prm)
+        net.status.check()
+        res = stationarity_residual(Sigma_hat, S, prm, x, ctx=ctx)
+        report = {"residual_net": res, "fallback": res > tol}
+        if res > tol:
+            status = torch.zeros(1, dtype=torch.int32, device=x.device)
+            x = P.detect(Sigma_hat, S, replace(prm, iters=extra_iters, rho=None, x0=x), ctx=ctx, status=status)
+            if int(status.item()) != 0:
+                raise P.PscaError(int(status.item()), "fallback PSCA")
+            report["residual_after"] = stationarity_residual(Sigma_hat, S, prm, x, ctx=ctx)
+    return x, report
+
+
 def choose_threshold(scores, truths) -> float:
     """Threshold minimising the average error rate ||alpha^ - alpha||_1 / n
     over validation data (detection is score >= threshold)."""

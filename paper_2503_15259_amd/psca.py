@@ -132,6 +132,7 @@ class Params:
     c2_ptr: Optional[torch.Tensor] = None
     c2_col: Optional[torch.Tensor] = None
     c2_val: Optional[torch.Tensor] = None
+    x0: Optional[torch.Tensor] = None   # starting iterate [N] (None: zeros)
 
     def to_c(self) -> N.PscaParams:
         c = N.PscaParams()
@@ -152,10 +153,11 @@ class Params:
         c.c2_val = None if self.c2_val is None else self.c2_val.data_ptr()
         c.c2_nnz = 0 if self.c2_col is None else int(self.c2_col.numel())
         c.dist_law = int(self.dist_law)
+        c.x0 = None if self.x0 is None else self.x0.data_ptr()
         return c
 
     def check_tensors(self, device, n):
-        for name in ("g", "p"):
+        for name in ("g", "p", "x0"):
             t = getattr(self, name)
             if t is not None:
                 _need(t, torch.float32, device, name)
@@ -205,8 +207,8 @@ def sample_cov(Y: torch.Tensor, ctx: Optional[Context] = None, stream=None,
 
 def detect(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Context] = None,
            stream=None, out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
-    """Algorithm 1 from x = 0 for params.iters iterations (psca_detect).
-    Returns x (float32, length N).  `status`, if given, is a device int32[1]
+    """Algorithm 1 from x = params.x0 (zeros when None) for params.iters
+    iterations (psca_detect).  Returns x (float32, length N).  `status`, if given, is a device int32[1]
     that receives 0 or PSCA_ENOTPD."""
     ctx = ctx or default_context(S.device)
     _need(S, torch.complex64, ctx.device, "S")

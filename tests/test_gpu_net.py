@@ -359,3 +359,36 @@ def test_batched_network_gradient_matches_oracle(P, variant):
     got2 = model.rho.grad.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(got2, g_ref, rtol=5e-3, atol=5e-3 * np.max(np.abs(g_ref)))
     np.testing.assert_allclose(got2, got, rtol=1e-5, atol=1e-6 * np.max(np.abs(got)))
+
+
+@pytest.mark.parametrize("variant,tol", [(O.ML_K, 1e-2), (O.ML_UD, 1e-2), (O.ML_K, 1e9)])
+def test_network_with_plain_psca_as_judge_and_fallback(P, variant, tol):
+    """detect_with_fallback: the network's output is judged by its
+    stationarity residual from one PSCA iteration (against the oracle's);
+    above tol, plain PSCA continues from it with the schedule and the result
+    equals the oracle's network followed by the same PSCA iterations, with
+    a smaller residual; at a tolerance it meets, the output is the
+    network's own."""
+    from paper_2503_15259_amd import net as NET
+    inst = I.make_instance(3, 2100 + variant, 300, 32, 64, 0.1).fp32_inputs()
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    K, extra = 3, 40
+    model = NET.PscaNet(K, params_for(P, inst, variant))   # the schedule: far from stationary after 3 layers
+    rhos = model.rho.detach().numpy().astype(np.float64)
+    xk = O.net_forward(prob, rhos)[-1]
+    rec = O.psca_iteration(prob, xk, 1.0)
+    res_ref = np.max(np.abs(rec.x_tilde - xk)) / max(np.max(np.abs(xk)), 1e-30)
+    x, rep = NET.detect_with_fallback(model, P.sample_cov(c64(inst.Y)), c64(inst.S), tol=tol, extra_iters=extra)
+    torch.cuda.synchronize()
+    print(f"[fallback {O.VARIANT_NAMES[variant]} tol={tol:g}] {rep}; oracle residual {res_ref:.4g}", flush=True)
+    assert rep["residual_net"] == pytest.approx(res_ref, rel=1e-3)
+    if tol < res_ref:
+        assert rep["fallback"]
+        x_ref = xk.copy()
+        for rho in O.step_sizes(extra):
+            x_ref = O.psca_iteration(prob, x_ref, float(rho)).x_next
+        assert_parity(x.cpu().numpy(), x_ref, variant, "network + fallback")
+        assert rep["residual_after"] < rep["residual_net"]
+    else:
+        assert not rep["fallback"]
+        assert_parity(x.cpu().numpy(), xk, variant, "network alone")

@@ -608,3 +608,38 @@ def test_large_pilot_length_iterate_and_network_forward(P):
     _, recs = O.psca(prob, len(rhos), rho=rhos.astype(np.float64), record=True)
     for k, rc in enumerate(recs):
         assert_parity(hist[k + 1], rc.x_next, O.ML_K, f"L=200 network layer {k}")
+
+
+@pytest.mark.parametrize("N,L,M,variant", [(300, 32, 64, O.ML_K), (500, 64, 128, O.MAP_K), (400, 130, 64, O.ML_UD)])
+def test_detection_from_a_given_starting_iterate(P, N, L, M, variant):
+    """params.x0: a detection that starts from x^(0) = x0 (here the oracle's
+    6th iterate from zero) equals the oracle's iterations from x0 with the
+    same schedule, single and batched (L <= 96 and L > 96); x0 may not alias
+    the output."""
+    inst = I.make_instance(5, 900 + N + L, N, L, M, 0.1).fp32_inputs()
+    prob = O.problem_from_instance(inst, variant, eps=EPS)
+    x0 = O.psca(prob, 6).astype(np.float32).astype(np.float64)   # the start the kernel sees
+    iters = 12
+    x_ref = x0.copy()
+    for rho in O.step_sizes(iters):
+        x_ref = O.psca_iteration(prob, x_ref, float(rho)).x_next
+    Sh = P.sample_cov(c64(inst.Y))
+    prm = params_for(P, inst, variant, iters)
+    prm.x0 = f32(x0)
+    status = torch.full((1,), 7, dtype=torch.int32, device=dev())
+    print(f"[x0 start {O.VARIANT_NAMES[variant]} N={N} L={L}]", flush=True)
+    x = P.detect(Sh, c64(inst.S), prm, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert_parity(x.cpu().numpy(), x_ref, variant, "x0 single")
+    st2 = torch.full((2,), 7, dtype=torch.int32, device=dev())
+    probs = [P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=prm, status=st2[0:1]),
+             P.Problem(Sigma_hat=Sh, S=c64(inst.S), params=params_for(P, inst, variant, iters), status=st2[1:2])]
+    xs = P.detect_batch(probs)
+    torch.cuda.synchronize()
+    assert st2.cpu().tolist() == [0, 0]
+    assert_parity(xs[0].cpu().numpy(), x_ref, variant, "x0 batch")
+    assert_parity(xs[1].cpu().numpy(), O.psca(prob, iters), variant, "zero start in the same batch")
+    with pytest.raises(P.PscaError) as e:   # the start may not be the output
+        P.detect(Sh, c64(inst.S), prm, out=prm.x0)
+    assert e.value.code == -1
