@@ -3528,7 +3528,7 @@ void bind_large_batch(const BatchPlan &plan, char *base, LargeTeamArgs *out) {
     const InstPlan &ip = plan.ip[b];
     LargeTeamArgs a;
     fill_args(a.c, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, plan.iters[b], -1.0f,
-              nullptr, q.x_out, nullptr, nullptr, nullptr, q.status, ip);
+              q.prm.x0, q.x_out, nullptr, nullptr, nullptr, q.status, ip);
     bind_large_ws(a, base + plan.ws_off[b], ip.Lp, ip.G, q.N);
     a.c.x_hist = q.x_hist;
     a.c.partials = (float2 *)(base + plan.part_off + plan.part_team_off[plan.team_of[b]]);
@@ -3545,7 +3545,7 @@ void bind_batch(const BatchPlan &plan, char *base, CoopArgs *out) {
     const InstPlan &ip = plan.ip[b];
     CoopArgs a;
     fill_args(a, (const float2 *)q.Sigma_hat, (const float2 *)q.S, q.L, q.N, &q.prm, plan.iters[b], -1.0f,
-              nullptr, q.x_out, nullptr, nullptr, nullptr, q.status, ip);
+              q.prm.x0, q.x_out, nullptr, nullptr, nullptr, q.status, ip);
     char *w = base + plan.ws_off[b];
     a.sigma = (float2 *)w;                w += align_up(packed_entries(ip.Lp) * sizeof(float2));
     a.bar.arrive = (unsigned *)w;         w += align_up((size_t)ip.G * 16 * sizeof(unsigned));
@@ -4170,23 +4170,25 @@ int psca_sample_cov(psca_ctx *ctx, const psca_c32 *Y, int L, int M, psca_c32 *Si
 int psca_detect(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
                 const psca_params *prm, float *x_out, int32_t *status, void *stream) {
   if (!ctx || !Sigma_hat || !S || !x_out) return PSCA_EINVAL;
+  if (prm && prm->x0 && prm->x0 == x_out) return PSCA_EINVAL;
   int rc = validate_params(prm, L, N, true);
   if (rc != PSCA_OK) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
-  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr,
+  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, prm->x0,
                     x_out, nullptr, nullptr, nullptr, status, as_stream(stream));
 }
 
 int psca_detect_noalloc(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
                         const psca_params *prm, float *x_out, int32_t *status, void *stream) {
   if (!ctx || !Sigma_hat || !S || !x_out) return PSCA_EINVAL;
+  if (prm && prm->x0 && prm->x0 == x_out) return PSCA_EINVAL;
   int rc = validate_params(prm, L, N, true);
   if (rc != PSCA_OK) return rc;
   if (ctx->device >= kMaxDevices || !g_scratch_ptr[ctx->device]) return PSCA_EHIP;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
-  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr,
+  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, prm->x0,
                     x_out, nullptr, nullptr, nullptr, status, as_stream(stream), nullptr,
                     (char *)g_scratch_ptr[ctx->device], kScratchBytes);
 }
@@ -4194,6 +4196,7 @@ int psca_detect_noalloc(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32
 int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, int N,
                   const psca_params *prm, float *x_out, int32_t *status, void *stream) {
   if (!ctx || !Y || !S || !x_out) return PSCA_EINVAL;
+  if (prm && prm->x0 && prm->x0 == x_out) return PSCA_EINVAL;
   int rc = validate_params(prm, L, N, true);
   if (rc != PSCA_OK) return rc;
   DeviceGuard g(ctx->device);
@@ -4206,7 +4209,7 @@ int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, in
   hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), cov_lds_bytes(L, prm->M),
                      as_stream(stream), (const float2 *)Y, L, prm->M, Sh);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
-  return run_detect(ctx, Sh, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr, x_out, nullptr, nullptr,
+  return run_detect(ctx, Sh, (const float2 *)S, L, N, prm, prm->iters, -1.0f, prm->x0, x_out, nullptr, nullptr,
                     nullptr, status, as_stream(stream));
 }
 
@@ -4415,7 +4418,7 @@ int psca_net_forward(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S
   if (rc != PSCA_OK) return rc;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
-  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, nullptr,
+  return run_detect(ctx, (const float2 *)Sigma_hat, (const float2 *)S, L, N, prm, prm->iters, -1.0f, prm->x0,
                     x_hist + (size_t)prm->iters * N, nullptr, nullptr, nullptr, status, as_stream(stream), x_hist);
 }
 

@@ -42,17 +42,24 @@ def assert_parity(x_gpu, x_ref, variant, what=""):
 def assert_same_support(x_gpu, x_ref, truth, variant, what=""):
     """Identical detected support at the oracle's equal-error threshold (and at
     0.5 for the known-pathloss variants), excluding devices whose oracle score
-    lies within a relative 1e-4 of the threshold."""
+    lies within a relative 1e-4 of the threshold; the excluded devices are
+    counted and printed.  Returns {threshold: (excluded, flips among them)}."""
     x_gpu = np.asarray(x_gpu, dtype=np.float64)
     x_ref = np.asarray(x_ref, dtype=np.float64)
     _, theta, _, _ = O.equal_error_rate(x_ref, truth)
     thetas = [theta] + ([0.5] if variant in O.KNOWN_PATHLOSS else [])
     scale = float(np.max(np.abs(x_ref)))
+    counts = {}
     for th in thetas:
         near = np.abs(x_ref - th) <= 1e-4 * max(scale, abs(th))
         flips = (x_gpu >= th) != (x_ref >= th)
         n_flip = int(np.sum(flips & ~near))
+        counts[float(th)] = (int(near.sum()), int(np.sum(flips & near)))
         assert n_flip == 0, f"{what} {O.VARIANT_NAMES[variant]}: {n_flip} support flips at theta={th}"
+    print(f"  support identity {what} {O.VARIANT_NAMES[variant]}: "
+          + ", ".join(f"theta={th:.4g}: {n} near-threshold devices excluded ({f} of them flipped)"
+                      for th, (n, f) in counts.items()), flush=True)
+    return counts
 
 
 # MAP-UR devices whose iterates pass within this relative distance of a
