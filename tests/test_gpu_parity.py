@@ -643,3 +643,36 @@ def test_detection_from_a_given_starting_iterate(P, N, L, M, variant):
     with pytest.raises(P.PscaError) as e:   # the start may not be the output
         P.detect(Sh, c64(inst.S), prm, out=prm.x0)
     assert e.value.code == -1
+
+
+def test_large_pilot_length_batch_beyond_the_gpu(P):
+    """300 instances with 97 <= L <= 128 on teams of one workgroup: more
+    instances than co-resident workgroups, so teams work through lists of
+    several instances (longest first).  Every status is clean, every result
+    agrees with the same instance alone (its own launch) at the bar, and
+    sampled instances meet the oracle bar."""
+    rng = np.random.default_rng(31)
+    probs, insts, variants = [], [], []
+    for k in range(300):
+        N = int(rng.integers(97, 301))
+        L = int(rng.choice([97, 112, 128]))
+        inst = I.make_instance(6, k, N, L, 32, 0.1).fp32_inputs()
+        variant = (O.ML_K, O.ML_UD)[k % 2]
+        probs.append(P.Problem(Sigma_hat=P.sample_cov(c64(inst.Y)), S=c64(inst.S),
+                               params=params_for(P, inst, variant, 5),
+                               status=torch.full((1,), 7, dtype=torch.int32, device=dev())))
+        insts.append(inst)
+        variants.append(variant)
+    print("[large-L batch of 300 on teams of 1]", flush=True)
+    plan = P.Plan(probs, team_size=1)
+    outs = [x.clone() for x in plan.launch()]
+    torch.cuda.synchronize()
+    plan.close()
+    assert all(int(pb.status.item()) == 0 for pb in probs)
+    for k in range(0, 300, 23):   # against the instance run alone
+        x1 = P.detect(probs[k].Sigma_hat, probs[k].S, probs[k].params)
+        torch.cuda.synchronize()
+        assert_parity(outs[k].cpu().numpy(), x1.cpu().numpy().astype(np.float64), variants[k], f"alone {k}")
+    for k in (0, 151, 299):   # against the oracle
+        ref = O.psca(O.problem_from_instance(insts[k], variants[k], eps=EPS), 5)
+        assert_parity(outs[k].cpu().numpy(), ref, variants[k], f"oracle {k}")
