@@ -2706,59 +2706,62 @@ __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__
 }
 #endif
 
-// SigmaHat = Y Y^H / M.  Each workgroup stages Y through 64 KiB of LDS,
-// cov_chunk(L, M) columns at a time (all of Y when it fits) with coalesced
-// loads; one thread forms one lower-triangle entry and mirrors it, so the
-// result is exactly Hermitian.
-__host__ __device__ inline int cov_chunk(int L, int M) { return min(M, 8192 / L); }
-inline size_t cov_lds_bytes(int L, int M) { return (size_t)cov_chunk(L, M) * L * sizeof(float2); }
-
+// SigmaHat = Y Y^H / M on FP64 MFMA.  Workgroup b computes the lower 16x16
+// block (I, J) = blk_coords(b); its four wavefronts take the columns m of Y
+// in interleaved groups of four, with the complex products on the real
+// four-product split (products of FP32 entries are exact in FP64, sums in
+// FP64), add their sums in LDS in a fixed order, scale by 1/M and round
+// once.  Strictly lower entries are mirrored (conjugated) into the upper
+// triangle and the diagonal's imaginary part is zero, so the result is
+// exactly Hermitian.  Grid: Lb (Lb + 1) / 2 workgroups of 256 threads.
 #ifdef PSCA_TU_MAIN
-__global__ void __launch_bounds__(kThreads) k_sample_cov(const float2 *__restrict__ Y, int L, int M,
-                                                         float2 *__restrict__ Sh) {
-  extern __shared__ float4 smem_raw[];
-  float2 *ys = (float2 *)smem_raw;   // [cov_chunk(L, M)][L]: columns m0.. of Y
-  const int chunk = cov_chunk(L, M);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = e < L * (L + 1) / 2;
-  int i = 0, j = 0;
-  if (active) {
-    i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-    while (i * (i + 1) / 2 > e) --i;
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    j = e - i * (i + 1) / 2;
+__global__ void __launch_bounds__(256) k_sample_cov(const float2 *__restrict__ Y, int L, int M,
+                                                    float2 *__restrict__ Sh) {
+  __shared__ double red[2][4][4][64];   // [re/im][wave][element][lane]
+  int I, J;
+  blk_coords(blockIdx.x, I, J);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
+  const int ra = 16 * I + l16, rb = 16 * J + l16;   // A[l16][k] = Y[ra][m], B[k][l16] = conj(Y[rb][m])
+  const bool ina = ra < L, inb = rb < L;
+  d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
+#pragma unroll 4
+  for (int m0 = 4 * wave; m0 < M; m0 += 16) {
+    const int m = m0 + lq;
+    float2 a = make_float2(0.f, 0.f), b = a;
+    if (m < M) {
+      if (ina) a = Y[(size_t)m * L + ra];
+      if (inb) b = Y[(size_t)m * L + rb];
+    }
+    // a conj(b) = (ax bx + ay by) + i (ay bx - ax by)
+    cr = mfma4d(a.x, b.x, cr);
+    cr = mfma4d(a.y, b.y, cr);
+    ci = mfma4d(a.y, b.x, ci);
+    ci = mfma4d(-a.x, b.y, ci);
   }
-  // Accumulated in double (two interleaved sums) and rounded once: Sigma -
-  // SigmaHat is formed from this matrix every iteration, so its FP32 entries
-  // should carry no more than their own rounding.
-  double ax0 = 0.0, ay0 = 0.0, ax1 = 0.0, ay1 = 0.0;
-  for (int m0 = 0; m0 < M; m0 += chunk) {
-    const int mc = min(chunk, M - m0);
-    __syncthreads();   // the previous chunk has been read
-    for (int t = threadIdx.x; t < mc * L; t += blockDim.x) ys[t] = Y[(size_t)m0 * L + t];
-    __syncthreads();
-    if (active) {
-      int m = 0;
-      for (; m + 1 < mc; m += 2) {
-        const float2 a0 = ys[m * L + i], b0 = ys[m * L + j];
-        const float2 a1 = ys[(m + 1) * L + i], b1 = ys[(m + 1) * L + j];
-        ax0 += (double)a0.x * b0.x + (double)a0.y * b0.y;
-        ay0 += (double)a0.y * b0.x - (double)a0.x * b0.y;
-        ax1 += (double)a1.x * b1.x + (double)a1.y * b1.y;
-        ay1 += (double)a1.y * b1.x - (double)a1.x * b1.y;
-      }
-      if (m < mc) {
-        const float2 a0 = ys[m * L + i], b0 = ys[m * L + j];
-        ax0 += (double)a0.x * b0.x + (double)a0.y * b0.y;
-        ay0 += (double)a0.y * b0.x - (double)a0.x * b0.y;
-      }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    red[0][wave][v][lane] = cr[v];
+    red[1][wave][v][lane] = ci[v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      sr += red[0][w][v][lane];
+      si += red[1][w][v][lane];
+    }
+    // FP64 output layout: element v of lane (j, h) is C[4v + h][j]
+    const int i = 4 * v + lq, jj = l16;
+    const int row = 16 * I + i, col = 16 * J + jj;
+    if (row < L && col < L && (I > J || i >= jj)) {
+      const float re = (float)(sr / M), im = row == col ? 0.0f : (float)(si / M);
+      Sh[(size_t)col * L + row] = make_float2(re, im);
+      if (row != col) Sh[(size_t)row * L + col] = make_float2(re, -im);
     }
   }
-  if (!active) return;
-  float2 acc = make_float2((float)((ax0 + ax1) / M), (float)((ay0 + ay1) / M));
-  if (i == j) acc.y = 0.0f;
-  Sh[i + (size_t)j * L] = acc;
-  Sh[j + (size_t)i * L] = make_float2(acc.x, -acc.y);
 }
 #endif
 
@@ -3207,6 +3210,8 @@ struct BatchPlan {
 };
 
 size_t packed_entries(int Lp) { return (size_t)(Lp / 16) * (Lp / 16 + 1) / 2 * 256; }
+// Lower 16x16 blocks of an L x L matrix (the workgroups of k_sample_cov).
+int packed_blocks(int L) { const int Lb = (L + 15) / 16; return Lb * (Lb + 1) / 2; }
 
 size_t inst_ws_bytes(int Lp, int G, int N) {
   return align_up(packed_entries(Lp) * sizeof(float2)) + align_up((size_t)G * 16 * sizeof(unsigned)) +
@@ -4161,8 +4166,7 @@ int psca_sample_cov(psca_ctx *ctx, const psca_c32 *Y, int L, int M, psca_c32 *Si
   if (L > kMaxL) return PSCA_ENOTSUP;
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
-  const int T = L * (L + 1) / 2;
-  hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), cov_lds_bytes(L, M),
+  hipLaunchKernelGGL(k_sample_cov, dim3(packed_blocks(L)), dim3(256), 0,
                      as_stream(stream), (const float2 *)Y, L, M, (float2 *)Sigma_hat);
   return launch_ok();
 }
@@ -4205,8 +4209,7 @@ int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, in
   rc = ensure_buf(&ctx->sh, &ctx->sh_bytes, (size_t)L * L * sizeof(float2));
   if (rc != PSCA_OK) return rc;
   float2 *Sh = (float2 *)ctx->sh;
-  const int T = L * (L + 1) / 2;
-  hipLaunchKernelGGL(k_sample_cov, dim3((T + kThreads - 1) / kThreads), dim3(kThreads), cov_lds_bytes(L, prm->M),
+  hipLaunchKernelGGL(k_sample_cov, dim3(packed_blocks(L)), dim3(256), 0,
                      as_stream(stream), (const float2 *)Y, L, prm->M, Sh);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
   return run_detect(ctx, Sh, (const float2 *)S, L, N, prm, prm->iters, -1.0f, prm->x0, x_out, nullptr, nullptr,

@@ -69,6 +69,11 @@ def test_sample_covariance(P):
         got = got.cpu().numpy().astype(np.complex128)
         ref = O.sample_covariance(inst.Y)
         assert np.linalg.norm(got - ref) <= 2e-6 * np.linalg.norm(ref)
+        # exact products and FP64 sums, rounded once: within half an FP32 ulp of
+        # each entry (real and imaginary parts), up to the FP64 sums' own error
+        tol = lambda r: 2.0 ** -24 * (1 + 1e-6) * np.abs(r) + 1e-12 * np.abs(ref).max()
+        assert np.all(np.abs(got.real - ref.real) <= tol(ref.real))
+        assert np.all(np.abs(got.imag - ref.imag) <= tol(ref.imag))
         assert np.array_equal(got, got.conj().T)        # exactly Hermitian
 
 
