@@ -1523,7 +1523,7 @@ __device__ __forceinline__ void gram_tile_fp64(const float2 *Yt, int PT, int ncb
 // at a time (b and b + kWaves), six independent MFMA chains, so that one
 // block's LDS reads and FP64 sums overlap the other's products.
 template <int THREADS, bool kTwo>
-__device__ __forceinline__ void gram_blocks_chunked(const float2 *Yt, int PT, int ncb, const float *w, int b0, int b1,
+__device__ __forceinline__ void gram_blocks_chunked(const float2 *Yc, int CP, int ncb, const float *w, int b0, int b1,
                                                     float2 *dst) {
   const int lane = threadIdx.x & 63, l16 = lane & 15, lq = lane >> 4;
   constexpr int kB = kTwo ? 2 : 1;
@@ -1551,8 +1551,8 @@ __device__ __forceinline__ void gram_blocks_chunked(const float2 *Yt, int PT, in
       const float wc = w[c];
 #pragma unroll
       for (int q = 0; q < kB; ++q) {
-        const float2 sv = Yt[(16 * J[q] + l16) * PT + c];
-        const float2 av = Yt[(16 * I[q] + l16) * PT + c];
+        const float2 sv = Yc[c * CP + 16 * J[q] + l16];
+        const float2 av = Yc[c * CP + 16 * I[q] + l16];
         cmfma3(av, make_float2(wc * sv.x, -wc * sv.y), t1[q], t2[q], t3[q]);
       }
     }
@@ -1576,13 +1576,65 @@ __device__ __forceinline__ void gram_blocks_chunked(const float2 *Yt, int PT, in
 }
 
 template <int THREADS>
-__device__ __forceinline__ void gram_tile_chunked(const float2 *Yt, int PT, int ncb, const float *w, int NB,
+__device__ __forceinline__ void gram_tile_chunked(const float2 *Yc, int CP, int ncb, const float *w, int NB,
                                                   float2 *dst) {
   constexpr int kWaves = THREADS / 64;
   const int wave = threadIdx.x >> 6;
   int b = wave;
-  for (; b + kWaves < NB; b += 2 * kWaves) gram_blocks_chunked<THREADS, true>(Yt, PT, ncb, w, b, b + kWaves, dst);
-  if (b < NB) gram_blocks_chunked<THREADS, false>(Yt, PT, ncb, w, b, b, dst);
+  for (; b + kWaves < NB; b += 2 * kWaves) gram_blocks_chunked<THREADS, true>(Yc, CP, ncb, w, b, b + kWaves, dst);
+  if (b < NB) gram_blocks_chunked<THREADS, false>(Yc, CP, ncb, w, b, b, dst);
+}
+
+// Column pitch of the column-major Gram tile: Lp rounded up to an odd
+// multiple of 16 complex, so that the two 16-row halves a wavefront reads at
+// once (columns c and c + 1) start 32 banks apart.
+__host__ __device__ constexpr int tile_pitch(int Lp) { return (Lp / 16) % 2 ? Lp : Lp + 16; }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Columns n0 .. n0 + NT - 1 of S (column-major, L rows) into the
+// column-major LDS tile Yc (pitch CP) by direct global-to-LDS loads: every
+// wavefront issues the loads of its columns back to back, so the whole tile
+// is in flight at once and no register holds it.  With L even a lane moves
+// two complex entries (16 bytes, aligned since every column starts at an
+// even entry); with L odd it moves one float (columns start at odd
+// entries).  Rows L .. Lp - 1 and the columns past N are written as zeros.
+// The caller waits for the loads (s_waitcnt) and synchronises the
+// workgroup before reading the tile.
+template <int THREADS>
+__device__ __forceinline__ void stage_tile_dma(const float2 *__restrict__ S, int L, int Lp, int N, int n0, int NT,
+                                               int CP, float2 *Yc) {
+  constexpr int kWaves = THREADS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = min(NT, N - n0);
+  if ((L & 1) == 0) {
+    const int hp = L >> 1;
+    for (int c = wave; c < nt; c += kWaves) {
+      const float2 *src = S + (size_t)(n0 + c) * L;
+      for (int k = 0; k < hp; k += 64)
+        if (k + lane < hp)
+          __builtin_amdgcn_global_load_lds((const void *)(src + 2 * (k + lane)), (lds_void *)(Yc + c * CP + 2 * k), 16,
+                                           0, 0);
+    }
+  } else {
+    const int nd = 2 * L;
+    for (int c = wave; c < nt; c += kWaves) {
+      const float *src = (const float *)(S + (size_t)(n0 + c) * L);
+      for (int k = 0; k < nd; k += 64)
+        if (k + lane < nd)
+          __builtin_amdgcn_global_load_lds((const void *)(src + k + lane), (lds_void *)((float *)(Yc + c * CP) + k), 4,
+                                           0, 0);
+    }
+  }
+  const int pr = Lp - L;
+  for (int e = threadIdx.x; e < NT * pr; e += THREADS) {
+    const int c = e / pr;
+    Yc[c * CP + L + (e - c * pr)] = make_float2(0.f, 0.f);
+  }
+  for (int e = threadIdx.x; e < (NT - nt) * Lp; e += THREADS) {
+    const int c = nt + e / Lp;
+    Yc[c * CP + e % Lp] = make_float2(0.f, 0.f);
+  }
 }
 
 // Workgroup g of T sums its 1/T slice of the E packed entries over `parts`
@@ -1779,8 +1831,11 @@ struct LargeTeamArgs {
   int Gv;            // Gram tiles, ceil(N / NT)
 };
 
+// The S tile takes the larger of the row-major layout [Lp][NT + 1] (the
+// backward's Gram) and the column-major [NT][tile_pitch(Lp)] (the forward's).
 __host__ __device__ inline size_t lds_large_team_bytes(int Lp, int NT, int threads) {
-  return ((size_t)Lp * (NT + 1) + (size_t)(Lp / 16) * 256) * sizeof(float2) + (size_t)threads * sizeof(double2) +
+  const size_t tile = std::max((size_t)Lp * (NT + 1), (size_t)NT * tile_pitch(Lp));
+  return (tile + (size_t)(Lp / 16) * 256) * sizeof(float2) + (size_t)threads * sizeof(double2) +
          (size_t)NT * sizeof(float);
 }
 
@@ -2212,9 +2267,10 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
   constexpr int Lp = 16 * LB, NB = LB * (LB + 1) / 2;
   extern __shared__ float4 smem_raw[];
   __shared__ int s_ok, s_pd;
-  const int NT = A.NT, PT = A.NT + 1, ncb = A.ncb, T = A.G, Gv = Tg.Gv;
-  float2 *Yt = (float2 *)smem_raw;          // [Lp][PT] Gram tile of S
-  float2 *Wd = Yt + Lp * PT;                // [LB][256] W_JJ, column-major blocks
+  const int NT = A.NT, ncb = A.ncb, T = A.G, Gv = Tg.Gv;
+  constexpr int CP = tile_pitch(Lp);
+  float2 *Yc = (float2 *)smem_raw;          // [NT][CP] Gram tile of S, column-major
+  float2 *Wd = Yc + std::max(Lp * (NT + 1), NT * CP);   // [LB][256] W_JJ, column-major blocks
   double2 *dscr = (double2 *)(Wd + LB * 256);   // [THREADS] phase B
   float *wv = (float *)(dscr + THREADS);    // [NT] weights of the tile
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -2238,32 +2294,16 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
     PSCA_MARK(it, 0);
     for (int v = g; v < Gv; v += T) {
       const int n0 = v * NT;
-      __syncthreads();   // the previous tile's Gram is done with Yt and wv
+      __syncthreads();   // the previous tile's Gram is done with Yc and wv
+      stage_tile_dma<THREADS>(A.S, A.L, Lp, A.N, n0, NT, CP, Yc);
       for (int c = tid; c < NT; c += THREADS) {
         const int n = n0 + c;
         const float x = n < A.N ? Tg.xw[n] : 0.0f;
         wv[c] = n < A.N ? (known ? A.a.g[n] * x : x) : 0.0f;
       }
-      {
-        constexpr int kU = 8;   // loads in flight per thread
-        const int tot = Lp * NT;
-        for (int e0 = tid; e0 < tot; e0 += kU * THREADS) {
-          float2 val[kU];
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;   // down a column: coalesced
-            const int n = n0 + c;
-            val[u] = (e < tot && i < A.L && n < A.N) ? A.S[(size_t)n * A.L + i] : make_float2(0.f, 0.f);
-          }
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int e = e0 + u * THREADS, c = e / Lp, i = e - c * Lp;
-            if (e < tot) Yt[i * PT + c] = val[u];
-          }
-        }
-      }
+      __builtin_amdgcn_s_waitcnt(0);   // the tile's direct loads have landed in LDS
       __syncthreads();
-      gram_tile_chunked<THREADS>(Yt, PT, ncb, wv, NB, A.partials + (size_t)v * A.pstride);
+      gram_tile_chunked<THREADS>(Yc, CP, ncb, wv, NB, A.partials + (size_t)v * A.pstride);
     }
     PSCA_MARK(it, 1);
     if (!grid_sync(A.bar, T, g, gen, &s_ok)) { aborted = true; break; }
@@ -2724,7 +2764,6 @@ __global__ void __launch_bounds__(256) k_sample_cov(const float2 *__restrict__ Y
   const int ra = 16 * I + l16, rb = 16 * J + l16;   // A[l16][k] = Y[ra][m], B[k][l16] = conj(Y[rb][m])
   const bool ina = ra < L, inb = rb < L;
   d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = cr;
-#pragma unroll 4
   for (int m0 = 4 * wave; m0 < M; m0 += 16) {
     const int m = m0 + lq;
     float2 a = make_float2(0.f, 0.f), b = a;
