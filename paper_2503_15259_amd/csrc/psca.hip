@@ -1481,6 +1481,25 @@ __device__ __forceinline__ const float2 *pblk(const float2 *packed, int I, int J
   return packed + (size_t)blk_index(I, J) * 256;
 }
 
+// Global loads and stores through an explicitly global pointer: the
+// descriptors' generic pointers would otherwise give flat instructions, which
+// also count as LDS operations, so that every wait for an LDS read would wait
+// for them too.
+typedef float gvec2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) gvec2 gvec2_g;
+typedef __attribute__((address_space(1))) gvec2 gvec2_gw;
+__device__ __forceinline__ float2 ldg2(const float2 *p, size_t i) {
+  const gvec2 v = ((gvec2_g *)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void stg2(float2 *p, size_t i, float2 x) {
+  ((gvec2_gw *)p)[i] = gvec2{x.x, x.y};
+}
+// streaming store: data read back only after it has left the caches
+__device__ __forceinline__ void stg2_nt(float2 *p, size_t i, float2 x) {
+  __builtin_nontemporal_store(gvec2{x.x, x.y}, (gvec2_gw *)p + i);
+}
+
 // Packed Gram partial S_t diag(w) S_t^H of a tile staged in LDS (Yt
 // [Lp][PT], ncb 16-column blocks, weights w[c]) into dst (NB lower 16x16
 // blocks of 256 entries, column-major within a block).  FP64 MFMA (the
@@ -1515,13 +1534,15 @@ __device__ __forceinline__ void gram_tile_fp64(const float2 *Yt, int PT, int ncb
   }
 }
 
-// The same packed Gram partial with FP32 MFMA on each 16-column chunk of the
-// tile (three products per complex step, FP32 sums of 16 products) and the
-// chunks added in FP64: twice the FP64 MFMA rate, while every FP32 sum spans
-// only 16 columns, so the entries still carry about one FP32 rounding of
-// their magnitude once summed over the tiles.  Each wave works on two blocks
-// at a time (b and b + kWaves), six independent MFMA chains, so that one
-// block's LDS reads and FP64 sums overlap the other's products.
+// The same packed Gram partial on FP32 MFMA (twice the FP64 MFMA rate):
+// three products per complex step, summed in FP32 over each 16-column chunk
+// of the tile, the chunks added in FP64, and each entry combined in FP64 and
+// rounded to FP32 once.  Every FP32 sum spans only 16 columns, so the
+// entries carry about one FP32 rounding of their magnitude once summed over
+// the tiles.  Each wave works on two blocks at a time (b and b + kWaves),
+// six independent MFMA chains, so that one block's LDS reads and FP64 sums
+// overlap the other's products.  The partials go out as streaming global
+// stores: the reduction reads them back after the team barrier.
 template <int THREADS, bool kTwo>
 __device__ __forceinline__ void gram_blocks_chunked(const float2 *Yc, int CP, int ncb, const float *w, int b0, int b1,
                                                     float2 *dst) {
@@ -1568,10 +1589,10 @@ __device__ __forceinline__ void gram_blocks_chunked(const float2 *Yc, int CP, in
   // FP32 output layout: element v of lane (j, h) is C[4h + v][j] (column-major block)
 #pragma unroll
   for (int q = 0; q < kB; ++q) {
-    float2 *o = dst + (size_t)(q == 0 ? b0 : b1) * 256 + l16 * 16 + 4 * lq;
+    const size_t o = (size_t)(q == 0 ? b0 : b1) * 256 + l16 * 16 + 4 * lq;
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-      o[v] = make_float2((float)(s1[q][v] - s2[q][v]), (float)(s3[q][v] - s1[q][v] - s2[q][v]));
+      stg2_nt(dst, o + v, make_float2((float)(s1[q][v] - s2[q][v]), (float)(s3[q][v] - s1[q][v] - s2[q][v])));
   }
 }
 
@@ -1839,15 +1860,6 @@ __host__ __device__ inline size_t lds_large_team_bytes(int Lp, int NT, int threa
          (size_t)NT * sizeof(float);
 }
 
-// Global loads through an explicitly global pointer: the descriptors' generic
-// pointers would otherwise give flat loads, whose waits also cover LDS.
-typedef float gvec2 __attribute__((ext_vector_type(2)));
-typedef const __attribute__((address_space(1))) gvec2 gvec2_g;
-__device__ __forceinline__ float2 ldg2(const float2 *p, size_t i) {
-  const gvec2 v = ((gvec2_g *)p)[i];
-  return make_float2(v.x, v.y);
-}
-
 // Row of flat task t when row r holds r tasks (rows 1, 2, ...): the largest
 // r with r (r - 1) / 2 <= t.  Constant-folded where t is a constant.
 __device__ __forceinline__ constexpr int tri_row(int t) {
@@ -2094,9 +2106,9 @@ __device__ __forceinline__ bool transform_delta(const LargeTeamArgs &Tg, const f
       for (int v = 0; v < 4; ++v) {
         const int i = 4 * lq + v;
         if (R >= j) {
-          y[R][v] = D[(size_t)blk_index(R, j) * 256 + l16 * 16 + i];
+          y[R][v] = ldg2(D, (size_t)blk_index(R, j) * 256 + l16 * 16 + i);
         } else {
-          const float2 t = D[(size_t)blk_index(j, R) * 256 + i * 16 + l16];
+          const float2 t = ldg2(D, (size_t)blk_index(j, R) * 256 + i * 16 + l16);
           y[R][v] = make_float2(t.x, -t.y);
         }
       }
@@ -2104,7 +2116,7 @@ __device__ __forceinline__ bool transform_delta(const LargeTeamArgs &Tg, const f
 #pragma unroll
     for (int R = 0; R < LB; ++R)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) X[(size_t)(16 * j + l16) * Lp + 16 * R + 4 * lq + v] = y[R][v];
+      for (int v = 0; v < 4; ++v) stg2(X, (size_t)(16 * j + l16) * Lp + 16 * R + 4 * lq + v, y[R][v]);
   }
   if (!grid_sync(A.bar, T, g, gen, s_ok)) return false;
   for (int j = g * kWaves + wave; j < LB; j += T * kWaves) {
@@ -2114,7 +2126,7 @@ __device__ __forceinline__ bool transform_delta(const LargeTeamArgs &Tg, const f
     for (int R = 0; R < LB; ++R)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float2 t = X[(size_t)(16 * R + 4 * lq + v) * Lp + 16 * j + l16];
+        const float2 t = ldg2(X, (size_t)(16 * R + 4 * lq + v) * Lp + 16 * j + l16);
         y[R][v] = make_float2(t.x, -t.y);
       }
     cb_forward<LB>(y, Tg.lbuf, Wd, lo_n);
@@ -2122,7 +2134,7 @@ __device__ __forceinline__ bool transform_delta(const LargeTeamArgs &Tg, const f
     for (int R = 0; R < LB; ++R)
       if (R >= j) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) D[(size_t)blk_index(R, j) * 256 + l16 * 16 + 4 * lq + v] = y[R][v];
+        for (int v = 0; v < 4; ++v) stg2(D, (size_t)blk_index(R, j) * 256 + l16 * 16 + 4 * lq + v, y[R][v]);
       }
   }
   return grid_sync(A.bar, T, g, gen, s_ok);
