@@ -329,9 +329,8 @@ LARGE_CPU_SAMPLE = 4  # instances 0..3: the oracle's sample
 # (64 instances x 20 layers, teams of 4 workgroups) from the FETCH_SIZE and
 # WRITE_SIZE counter passes, each scaled by the copy-kernel calibration
 # (profile k_psca_large_teams_net20_N10000_L200_x64_traffic.md).  Keyed by
-# team size; other team sizes report null, and so does every team size until
-# the counters have been taken again after a change of the kernel.
-LARGE_TRAFFIC_BYTES_PER_LAUNCH = {}
+# team size; other team sizes report null.
+LARGE_TRAFFIC_BYTES_PER_LAUNCH = {4: 164730000000}
 
 
 def _large_net_oracle_task(args):

@@ -1679,7 +1679,7 @@ __device__ __forceinline__ void reduce_packed_slice(const float2 *partials, size
       for (; h + (kU - 1) * Pp < parts; h += kU * Pp) {
         float2 v[kU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v[u] = src[(size_t)(h + u * Pp) * pstride];
+        for (int u = 0; u < kU; ++u) v[u] = ldg2(src, (size_t)(h + u * Pp) * pstride);
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           acc.x += v[u].x;
@@ -1687,7 +1687,7 @@ __device__ __forceinline__ void reduce_packed_slice(const float2 *partials, size
         }
       }
       for (; h < parts; h += Pp) {
-        const float2 v = src[(size_t)h * pstride];
+        const float2 v = ldg2(src, (size_t)h * pstride);
         acc.x += v.x;
         acc.y += v.y;
       }
@@ -1724,10 +1724,10 @@ __device__ __forceinline__ void reduce_sigma_slice(const CoopArgs &A, float2 *de
       sm.x += (16 * I + ii < A.L) ? (double)A.sigma2 : 1.0;
       sm.y = 0.0;
     }
-    A.sigma[e] = make_float2((float)sm.x, (float)sm.y);
+    stg2(A.sigma, e, make_float2((float)sm.x, (float)sm.y));
     const int i = 16 * I + ii, k = 16 * J + jj;   // Sigma - SigmaHat from the FP64 sum
-    const float2 sh = (i < A.L && k < A.L) ? A.Sh[(size_t)k * A.L + i] : make_float2(0.f, 0.f);
-    delta[e] = make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y));
+    const float2 sh = (i < A.L && k < A.L) ? ldg2(A.Sh, (size_t)k * A.L + i) : make_float2(0.f, 0.f);
+    stg2(delta, e, make_float2((float)(sm.x - (double)sh.x), (float)(sm.y - (double)sh.y)));
   });
 }
 
@@ -1750,7 +1750,7 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
   int res = 0;
   for (int J = 0; J < Lb; ++J) {
     float2 *Wj = Wd + J * 256;
-    for (int e = tid; e < 256; e += THREADS) Wj[e] = pblk(sig, J, J)[e];
+    for (int e = tid; e < 256; e += THREADS) Wj[e] = ldg2(pblk(sig, J, J), e);
     __syncthreads();
     if (wave == 0) {
       const bool ok = leaf_chol(Wj, 16, lane);
@@ -1780,7 +1780,7 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
           const int k = 4 * ks + lq;
           const float2 w = Wj[k * 16 + l16];   // W_JJ[l16][k]
           a4[ks] = make_float2(w.x, -w.y);
-          b4[ks] = blk[k * 16 + l16];           // A_IJ[l16][k] = A^T[k][l16]
+          b4[ks] = ldg2(blk, k * 16 + l16);     // A_IJ[l16][k] = A^T[k][l16]
         }
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], dr, di);
@@ -1800,13 +1800,13 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
         if (K == J + 1) {
           float2 *lb = lbuf + (size_t)blk_index(I, J) * 256;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) lb[(4 * lq + v) * 16 + l16] = make_float2(lir[v], lii[v]);
+          for (int v = 0; v < 4; ++v) stg2(lb, (4 * lq + v) * 16 + l16, make_float2(lir[v], lii[v]));
         }
         float2 *dst = sig + (size_t)blk_index(I, K) * 256;
         f4 cr, ci;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float2 c = dst[l16 * 16 + 4 * lq + v];
+          const float2 c = ldg2(dst, l16 * 16 + 4 * lq + v);
           cr[v] = c.x;
           ci[v] = c.y;
         }
@@ -1819,7 +1819,7 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) cmfma(a4[ks], b4[ks], cr, ci);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[l16 * 16 + 4 * lq + v] = make_float2(cr[v], ci[v]);
+        for (int v = 0; v < 4; ++v) stg2(dst, l16 * 16 + 4 * lq + v, make_float2(cr[v], ci[v]));
       }
     }
     if (!grid_sync(A.bar, T, g, gen, s_ok)) { res = 2; break; }
@@ -1833,8 +1833,9 @@ __device__ __forceinline__ int factor_in_memory(const CoopArgs &A, const float2 
 //
 // One instance runs on a team of T workgroups.  Its devices are cut into Gv
 // Gram tiles of NT = 16 ncb columns; rank g of the team forms the packed
-// partials of tiles g, g + T, g + 2T, ... (each tile staged in LDS, FP64
-// Gram, one partial slot per tile).  Phase B sums the Gv slots, 1/T of
+// partials of tiles g, g + T, g + 2T, ... (each tile staged in LDS by direct
+// loads, FP32 MFMA Gram in 16-column chunks summed in FP64, one partial slot
+// per tile).  Phase B sums the Gv slots, 1/T of
 // packed Sigma per rank; C1 factors Sigma in memory (factor_in_memory).  The solves run per 16-column block with the block
 // held in registers: wave w of rank g takes the column blocks 8g + w,
 // 8g + w + 8T, ..., so every wave of the team has work whatever the tile
