@@ -539,6 +539,25 @@ __device__ __forceinline__ void chol_trail(float2 *WS, int P, int J, int I, int 
   for (int v = 0; v < 4; ++v) dst[v] = make_float2(cr[v], ci[v]);
 }
 
+// Global loads and stores through an explicitly global pointer: the
+// descriptors' generic pointers would otherwise give flat instructions, which
+// also count as LDS operations, so that every wait for an LDS read would wait
+// for them too.
+typedef float gvec2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) gvec2 gvec2_g;
+typedef __attribute__((address_space(1))) gvec2 gvec2_gw;
+__device__ __forceinline__ float2 ldg2(const float2 *p, size_t i) {
+  const gvec2 v = ((gvec2_g *)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void stg2(float2 *p, size_t i, float2 x) {
+  ((gvec2_gw *)p)[i] = gvec2{x.x, x.y};
+}
+// streaming store: data read back only after it has left the caches
+__device__ __forceinline__ void stg2_nt(float2 *p, size_t i, float2 x) {
+  __builtin_nontemporal_store(gvec2{x.x, x.y}, (gvec2_gw *)p + i);
+}
+
 // ---------------------------------------------------------------------------
 // Phases shared by the forward and the backward bodies
 // ---------------------------------------------------------------------------
@@ -575,9 +594,10 @@ __device__ __forceinline__ void tile_gram(const float2 *St, int PT, int ncb, con
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) cmfma_d3(av4[ks], bv4[ks], t1, t2, t3);
       }
-      float2 *o = dst + b * 256 + l16 * 16 + lq;   // rows lq + 4v of column l16
+      const int o = b * 256 + l16 * 16 + lq;   // rows lq + 4v of column l16
 #pragma unroll
-      for (int v = 0; v < 4; ++v) o[4 * v] = make_float2((float)(t1[v] - t2[v]), (float)(t3[v] - t1[v] - t2[v]));
+      for (int v = 0; v < 4; ++v)
+        stg2(dst, o + 4 * v, make_float2((float)(t1[v] - t2[v]), (float)(t3[v] - t1[v] - t2[v])));
     }
   }
 }
@@ -593,7 +613,7 @@ __device__ __forceinline__ void store_reduced(float2 *out, int e, double2 sm, bo
       sm.y = 0.0;
     }
   }
-  out[e] = make_float2((float)sm.x, (float)sm.y);
+  stg2(out, e, make_float2((float)sm.x, (float)sm.y));
 }
 
 // Workgroup g's 1/G slice of the sum over the G packed partials (rank h at
@@ -619,7 +639,7 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
       for (; h + 3 * Pp < G; h += 4 * Pp) {   // four loads in flight, then the adds in order
         float2 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = partials[(size_t)(h + u * Pp) * pstride + e];
+        for (int u = 0; u < 4; ++u) v[u] = ldg2(partials, (size_t)(h + u * Pp) * pstride + e);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           acc.x += v[u].x;
@@ -627,7 +647,7 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
         }
       }
       for (; h < G; h += Pp) {
-        const float2 v = partials[(size_t)h * pstride + e];
+        const float2 v = ldg2(partials, (size_t)h * pstride + e);
         acc.x += v.x;
         acc.y += v.y;
       }
@@ -647,7 +667,7 @@ __device__ __forceinline__ void reduce_slice(const float2 *partials, size_t pstr
     for (int e = start + tid; e < end; e += THREADS) {
       double2 sm = make_double2(0.0, 0.0);
       for (int h = 0; h < G; ++h) {
-        const float2 v = partials[(size_t)h * pstride + e];
+        const float2 v = ldg2(partials, (size_t)h * pstride + e);
         sm.x += v.x;
         sm.y += v.y;
       }
@@ -682,7 +702,7 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
     const int b = e >> 8, jj = (e & 255) >> 4, ii = e & 15;
     int I, J;
     blk_coords(b, I, J);
-    WS[(16 * J + jj) * P + 16 * I + ii] = sigma[e];
+    WS[(16 * J + jj) * P + 16 * I + ii] = ldg2(sigma, e);
   }
   __syncthreads();
   if (wave == 0) {
@@ -702,12 +722,12 @@ __device__ __forceinline__ bool invert_hpd(const float2 *sigma, float2 *WS, floa
           const int k = e / LP, i = e - k * LP;   // column k, row i
           const int I = i >> 4, K = k >> 4;
           if (I >= K) {
-            sg[u] = sigma[blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15)];
+            sg[u] = ldg2(sigma, blk_index(I, K) * 256 + (k & 15) * 16 + (i & 15));
           } else {
-            const float2 t = sigma[blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15)];
+            const float2 t = ldg2(sigma, blk_index(K, I) * 256 + (i & 15) * 16 + (k & 15));
             sg[u] = make_float2(t.x, -t.y);
           }
-          if (i < L && k < L) sh[u] = shat[(size_t)k * L + i];
+          if (i < L && k < L) sh[u] = ldg2(shat, (size_t)k * L + i);
         }
       }
 #pragma unroll
@@ -1479,25 +1499,6 @@ __device__ __forceinline__ void cmfma3(float2 a, float2 b, f4 &t1, f4 &t2, f4 &t
 
 __device__ __forceinline__ const float2 *pblk(const float2 *packed, int I, int J) {
   return packed + (size_t)blk_index(I, J) * 256;
-}
-
-// Global loads and stores through an explicitly global pointer: the
-// descriptors' generic pointers would otherwise give flat instructions, which
-// also count as LDS operations, so that every wait for an LDS read would wait
-// for them too.
-typedef float gvec2 __attribute__((ext_vector_type(2)));
-typedef const __attribute__((address_space(1))) gvec2 gvec2_g;
-typedef __attribute__((address_space(1))) gvec2 gvec2_gw;
-__device__ __forceinline__ float2 ldg2(const float2 *p, size_t i) {
-  const gvec2 v = ((gvec2_g *)p)[i];
-  return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ void stg2(float2 *p, size_t i, float2 x) {
-  ((gvec2_gw *)p)[i] = gvec2{x.x, x.y};
-}
-// streaming store: data read back only after it has left the caches
-__device__ __forceinline__ void stg2_nt(float2 *p, size_t i, float2 x) {
-  __builtin_nontemporal_store(gvec2{x.x, x.y}, (gvec2_gw *)p + i);
 }
 
 // Packed Gram partial S_t diag(w) S_t^H of a tile staged in LDS (Yt
