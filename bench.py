@@ -330,7 +330,7 @@ LARGE_CPU_SAMPLE = 4  # instances 0..3: the oracle's sample
 # WRITE_SIZE counter passes, each scaled by the copy-kernel calibration
 # (profile k_psca_large_teams_net20_N10000_L200_x64_traffic.md).  Keyed by
 # team size; other team sizes report null.
-LARGE_TRAFFIC_BYTES_PER_LAUNCH = {4: 164730000000}
+LARGE_TRAFFIC_BYTES_PER_LAUNCH = {4: 150900000000}
 
 
 def _large_net_oracle_task(args):

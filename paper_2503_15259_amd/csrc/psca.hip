@@ -1854,12 +1854,25 @@ struct LargeTeamArgs {
   int Gv;            // Gram tiles, ceil(N / NT)
 };
 
-// The S tile takes the larger of the row-major layout [Lp][NT + 1] (the
-// backward's Gram) and the column-major [NT][tile_pitch(Lp)] (the forward's).
+// LDS of the backward body: the row-major S tile [Lp][NT + 1], W_JJ, the
+// reduction's THREADS double2 and the tile's weights.
 __host__ __device__ inline size_t lds_large_team_bytes(int Lp, int NT, int threads) {
-  const size_t tile = std::max((size_t)Lp * (NT + 1), (size_t)NT * tile_pitch(Lp));
-  return (tile + (size_t)(Lp / 16) * 256) * sizeof(float2) + (size_t)threads * sizeof(double2) +
+  return ((size_t)Lp * (NT + 1) + (size_t)(Lp / 16) * 256) * sizeof(float2) + (size_t)threads * sizeof(double2) +
          (size_t)NT * sizeof(float);
+}
+
+// LDS of the forward body: the column-major S tile [NT][tile_pitch(Lp)],
+// with W_JJ [Lp / 16][256] and the reduction's THREADS double2 laid over it
+// (phase A, the only user of the tile, begins after the solves have last
+// read W_JJ and ends before the reduction), then the tile's weights [NT].
+// Freeing the tile of those two lets it take 80 columns at L = 200.
+__host__ __device__ inline size_t lds_large_fwd_overlay(int Lp, int NT, int threads) {
+  const size_t tile = (size_t)NT * tile_pitch(Lp) * sizeof(float2);
+  const size_t over = (size_t)(Lp / 16) * 256 * sizeof(float2) + (size_t)threads * sizeof(double2);
+  return tile > over ? tile : over;
+}
+__host__ __device__ inline size_t lds_large_fwd_bytes(int Lp, int NT, int threads) {
+  return lds_large_fwd_overlay(Lp, NT, threads) + (size_t)NT * sizeof(float);
 }
 
 // Row of flat task t when row r holds r tasks (rows 1, 2, ...): the largest
@@ -2283,10 +2296,10 @@ __device__ __forceinline__ void large_team_body(const LargeTeamArgs &Tg, const i
   __shared__ int s_ok, s_pd;
   const int NT = A.NT, ncb = A.ncb, T = A.G, Gv = Tg.Gv;
   constexpr int CP = tile_pitch(Lp);
-  float2 *Yc = (float2 *)smem_raw;          // [NT][CP] Gram tile of S, column-major
-  float2 *Wd = Yc + std::max(Lp * (NT + 1), NT * CP);   // [LB][256] W_JJ, column-major blocks
-  double2 *dscr = (double2 *)(Wd + LB * 256);   // [THREADS] phase B
-  float *wv = (float *)(dscr + THREADS);    // [NT] weights of the tile
+  float2 *Yc = (float2 *)smem_raw;          // [NT][CP] Gram tile of S, column-major (phase A)
+  float2 *Wd = Yc;                          // [LB][256] W_JJ, column-major blocks (C1 .. C5), over the tile
+  double2 *dscr = (double2 *)(Wd + LB * 256);   // [THREADS] phase B, over the tile
+  float *wv = (float *)((char *)smem_raw + lds_large_fwd_overlay(Lp, NT, THREADS));   // [NT] weights of the tile
   const int tid = threadIdx.x, wave = tid >> 6;
   const bool known = (A.a.variant == PSCA_ML_K || A.a.variant == PSCA_MAP_K || A.a.variant == PSCA_MAP_K2);
   const bool pairs = (A.a.variant == PSCA_MAP_K2);
@@ -3484,10 +3497,10 @@ int make_batch_plan(int B, const psca_problem *pr, int spec, int cap, BatchPlan 
 // ---- large pilot lengths (97..256): teams on k_psca_large_teams ------------
 constexpr int kLargeThreads = 512;
 
-// Widest Gram tile (16..64 columns) whose LDS fits a workgroup.
+// Widest Gram tile (16..80 columns) whose LDS fits a workgroup.
 int large_tile(int Lp) {
-  for (int nt = 64; nt >= 16; nt -= 16)
-    if (lds_large_team_bytes(Lp, nt, kLargeThreads) <= kMaxLds) return nt;
+  for (int nt = 80; nt >= 16; nt -= 16)
+    if (lds_large_fwd_bytes(Lp, nt, kLargeThreads) <= kMaxLds) return nt;
   return 0;
 }
 
@@ -3540,7 +3553,7 @@ int make_large_plan(int B, const psca_problem *pr, int T, int cap, BatchPlan &pl
     if (q.NT == 0) return PSCA_ENOTSUP;
     q.ncb = q.NT / 16;
     q.G = T;
-    q.lds = lds_large_team_bytes(q.Lp, q.NT, kLargeThreads);
+    q.lds = lds_large_fwd_bytes(q.Lp, q.NT, kLargeThreads);
     q.ws = large_inst_ws_bytes(q.Lp, T, pr[b].N);
     plan.gv[b] = (pr[b].N + q.NT - 1) / q.NT;
     plan.lds = std::max(plan.lds, q.lds);
@@ -3704,7 +3717,7 @@ int run_large_team(psca_ctx *ctx, const float2 *Sh, const float2 *S, int L, int 
   plan.B = 1;
   plan.T = T;
   plan.n_teams = 1;
-  plan.lds = lds_large_team_bytes(Lp, NT, kLargeThreads);
+  plan.lds = lds_large_fwd_bytes(Lp, NT, kLargeThreads);
   plan.lists = {0};
   plan.offsets = {0, 1};
   plan.team_start = {0, T};
