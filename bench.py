@@ -46,7 +46,7 @@ PEAK_HBM_GBS = 8000.0
 # each scaled by the copy-kernel calibration (profile
 # k_psca_teams_single_N1000_L64_x4_traffic.md): 176.6 MB fetched + 297.1 MB
 # written.  Keyed by team size; other team sizes report null.
-TRAFFIC_BYTES_PER_LAUNCH = {32: 473766760}
+TRAFFIC_BYTES_PER_LAUNCH = {32: 473700030}
 
 
 def iteration_flops(N, L):
