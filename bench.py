@@ -439,12 +439,16 @@ def run_large(args):
 
     insts = [I.workload_instance("large", i) for i in range(B)]
     progress(f"{B} instances drawn")
-    Ys = [P.colmajor(torch.from_numpy(x.Y.astype(np.complex64)).to(dev)) for x in insts]
+    # Y of the batch in one buffer (instance b column-major at b L M), so that
+    # SigmaHat of every instance is one launch of psca_sample_cov_batch
+    Yb = torch.empty((B, M, L), dtype=torch.complex64, device=dev).transpose(1, 2)
+    for b, x in enumerate(insts):
+        Yb[b].copy_(torch.from_numpy(x.Y.astype(np.complex64)).to(dev))
     Ss = [P.colmajor(torch.from_numpy(x.S.astype(np.complex64)).to(dev)) for x in insts]
     gs = [torch.from_numpy(x.g.astype(np.float32)).to(dev) for x in insts]
-    shs = [torch.empty((L, L), dtype=torch.complex64, device=dev).mT for _ in range(B)]
-    for Y, sh in zip(Ys, shs):
-        P.sample_cov(Y, ctx=ctx, out=sh)
+    shb = torch.empty((B, L, L), dtype=torch.complex64, device=dev).transpose(1, 2)
+    shs = [shb[b] for b in range(B)]
+    P.sample_cov_batch(Yb, ctx=ctx, out=shb)
     truth = np.concatenate([x.alpha for x in insts])
     status = torch.zeros(B, dtype=torch.int32, device=dev)
 
@@ -464,8 +468,7 @@ def run_large(args):
         """Mean ms of n launches (HIP events on the launch stream) after the warm-ups."""
         def once():
             if with_cov:
-                for Y, sh in zip(Ys, shs):
-                    P.sample_cov(Y, ctx=ctx, out=sh)
+                P.sample_cov_batch(Yb, ctx=ctx, out=shb)
             plan.launch()
         for _ in range(args.warmup):
             once()
@@ -522,8 +525,7 @@ def run_large(args):
     torch.cuda.synchronize()
     t_start.record(stream)
     for _ in range(args.steps):
-        for Y, sh in zip(Ys, shs):
-            P.sample_cov(Y, ctx=ctx, out=sh)
+        P.sample_cov_batch(Yb, ctx=ctx, out=shb)
         net_plan.launch()
     t_end.record(stream)
     torch.cuda.synchronize()

@@ -163,6 +163,17 @@ int psca_destroy(psca_ctx *ctx);
 int psca_sample_cov(psca_ctx *ctx, const psca_c32 *Y, int L, int M,
                     psca_c32 *Sigma_hat, void *stream);
 
+/* psca_sample_cov of B independent instances of one size in one launch.
+ * Instance b reads its L x M matrix Y at Y + b * y_stride and writes its
+ * L x L SigmaHat at Sigma_hat + b * sh_stride (strides in complex elements,
+ * each block column-major as above; the outputs must not overlap).  Every
+ * instance's result is bit-identical to psca_sample_cov on the same Y.
+ * Returns PSCA_EINVAL for a NULL ctx, B < 0, L < 1, M < 1, NULL buffers with
+ * B > 0, y_stride < L M or sh_stride < L L; PSCA_ENOTSUP for L > PSCA_MAX_L;
+ * B = 0 launches nothing. */
+int psca_sample_cov_batch(psca_ctx *ctx, int B, const psca_c32 *Y, long long y_stride, int L, int M,
+                          psca_c32 *Sigma_hat, long long sh_stride, void *stream);
+
 /* Algorithm 1 from x^(0) = 0 for prm->iters iterations.
  * Sigma_hat: L x L Hermitian PSD; S: L x N; x_out: [N] final iterate
  * (alpha for the K variants, gamma for the U variants).

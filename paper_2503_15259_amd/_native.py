@@ -23,7 +23,7 @@ MAX_L = 256
 
 # every symbol include/psca.h declares
 EXPORTED = (
-    "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov",
+    "psca_version", "psca_strerror", "psca_create", "psca_destroy", "psca_sample_cov", "psca_sample_cov_batch",
     "psca_detect", "psca_detect_y", "psca_iterate", "psca_threshold", "psca_detect_batch",
     "psca_autotune_batch", "psca_plan_create", "psca_plan_launch", "psca_plan_team_size", "psca_plan_destroy",
     "psca_net_forward", "psca_layer_backward", "psca_layer_backward_batch", "psca_detect_noalloc",
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "psca_create": ([ctypes.POINTER(vp), i32], i32),
         "psca_destroy": ([vp], i32),
         "psca_sample_cov": ([vp, vp, i32, i32, vp, vp], i32),
+        "psca_sample_cov_batch": ([vp, i32, vp, ctypes.c_longlong, i32, i32, vp, ctypes.c_longlong, vp], i32),
         "psca_detect": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
         "psca_detect_y": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),
         "psca_detect_noalloc": ([vp, vp, vp, i32, i32, P, vp, vp, vp], i32),

@@ -2780,11 +2780,14 @@ __global__ void __launch_bounds__(kBatchThreads) k_psca_teams(const CoopArgs *__
 // FP64), add their sums in LDS in a fixed order, scale by 1/M and round
 // once.  Strictly lower entries are mirrored (conjugated) into the upper
 // triangle and the diagonal's imaginary part is zero, so the result is
-// exactly Hermitian.  Grid: Lb (Lb + 1) / 2 workgroups of 256 threads.
+// exactly Hermitian.  Grid: Lb (Lb + 1) / 2 workgroups of 256 threads per
+// instance; instance blockIdx.y reads Y + y * sy and writes Sh + y * ss.
 #ifdef PSCA_TU_MAIN
 __global__ void __launch_bounds__(256) k_sample_cov(const float2 *__restrict__ Y, int L, int M,
-                                                    float2 *__restrict__ Sh) {
+                                                    float2 *__restrict__ Sh, long long sy, long long ss) {
   __shared__ double red[2][4][4][64];   // [re/im][wave][element][lane]
+  Y += (size_t)blockIdx.y * (size_t)sy;
+  Sh += (size_t)blockIdx.y * (size_t)ss;
   int I, J;
   blk_coords(blockIdx.x, I, J);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, l16 = lane & 15, lq = lane >> 4;
@@ -4233,8 +4236,29 @@ int psca_sample_cov(psca_ctx *ctx, const psca_c32 *Y, int L, int M, psca_c32 *Si
   DeviceGuard g(ctx->device);
   if (!g.ok) return PSCA_EHIP;
   hipLaunchKernelGGL(k_sample_cov, dim3(packed_blocks(L)), dim3(256), 0,
-                     as_stream(stream), (const float2 *)Y, L, M, (float2 *)Sigma_hat);
+                     as_stream(stream), (const float2 *)Y, L, M, (float2 *)Sigma_hat, 0LL, 0LL);
   return launch_ok();
+}
+
+int psca_sample_cov_batch(psca_ctx *ctx, int B, const psca_c32 *Y, long long y_stride, int L, int M,
+                          psca_c32 *Sigma_hat, long long sh_stride, void *stream) {
+  if (!ctx || B < 0 || L < 1 || M < 1) return PSCA_EINVAL;
+  if (B > 0 && (!Y || !Sigma_hat)) return PSCA_EINVAL;
+  if (y_stride < (long long)L * M || sh_stride < (long long)L * L) return PSCA_EINVAL;
+  if (L > kMaxL) return PSCA_ENOTSUP;
+  if (B == 0) return PSCA_OK;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return PSCA_EHIP;
+  constexpr int kMaxGridY = 65535;
+  for (int b0 = 0; b0 < B; b0 += kMaxGridY) {
+    const int nb = std::min(kMaxGridY, B - b0);
+    hipLaunchKernelGGL(k_sample_cov, dim3(packed_blocks(L), nb), dim3(256), 0, as_stream(stream),
+                       (const float2 *)Y + (size_t)b0 * (size_t)y_stride, L, M,
+                       (float2 *)Sigma_hat + (size_t)b0 * (size_t)sh_stride, y_stride, sh_stride);
+    const int rc = launch_ok();
+    if (rc != PSCA_OK) return rc;
+  }
+  return PSCA_OK;
 }
 
 int psca_detect(psca_ctx *ctx, const psca_c32 *Sigma_hat, const psca_c32 *S, int L, int N,
@@ -4276,7 +4300,7 @@ int psca_detect_y(psca_ctx *ctx, const psca_c32 *Y, const psca_c32 *S, int L, in
   if (rc != PSCA_OK) return rc;
   float2 *Sh = (float2 *)ctx->sh;
   hipLaunchKernelGGL(k_sample_cov, dim3(packed_blocks(L)), dim3(256), 0,
-                     as_stream(stream), (const float2 *)Y, L, prm->M, Sh);
+                     as_stream(stream), (const float2 *)Y, L, prm->M, Sh, 0LL, 0LL);
   if ((rc = launch_ok()) != PSCA_OK) return rc;
   return run_detect(ctx, Sh, (const float2 *)S, L, N, prm, prm->iters, -1.0f, prm->x0, x_out, nullptr, nullptr,
                     nullptr, status, as_stream(stream));

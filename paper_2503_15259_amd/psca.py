@@ -205,6 +205,31 @@ def sample_cov(Y: torch.Tensor, ctx: Optional[Context] = None, stream=None,
     return out
 
 
+def sample_cov_batch(Y: torch.Tensor, ctx: Optional[Context] = None, stream=None,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """SigmaHat of B instances of one size in one launch (psca_sample_cov_batch).
+    Y: complex64 B x L x M whose instances are column-major (Y[b].stride() ==
+    (1, L)), such as torch.empty(B, M, L).transpose(1, 2).  Returns (or fills
+    `out`, of the same kind) B x L x L with column-major instances."""
+    ctx = ctx or default_context(Y.device)
+    _need(Y, torch.complex64, ctx.device, "Y")
+    if Y.dim() != 3:
+        raise ValueError("Y must be B x L x M")
+    B, L, M = Y.shape
+    if Y.stride(1) != 1 or Y.stride(2) != L:
+        raise ValueError("every instance of Y must be column-major (strides (1, L))")
+    if out is None:
+        out = torch.empty((B, L, L), dtype=torch.complex64, device=ctx.device).transpose(1, 2)
+    else:
+        _need(out, torch.complex64, ctx.device, "out")
+        if out.shape != (B, L, L) or out.stride(1) != 1 or out.stride(2) != L:
+            raise ValueError("out must be B x L x L with column-major instances")
+    N.check(ctx._lib.psca_sample_cov_batch(ctx.handle, B, _ptr(Y), Y.stride(0) if B > 1 else L * M, L, M,
+                                           _ptr(out), out.stride(0) if B > 1 else L * L,
+                                           _stream(ctx.device, stream)), "psca_sample_cov_batch")
+    return out
+
+
 def detect(Sigma_hat: torch.Tensor, S: torch.Tensor, params: Params, ctx: Optional[Context] = None,
            stream=None, out: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
     """Algorithm 1 from x = params.x0 (zeros when None) for params.iters

@@ -41,6 +41,7 @@ int main(void) {
   EXPECT(psca_create(NULL, 0) == PSCA_EINVAL);
   EXPECT(psca_destroy(NULL) == PSCA_OK);
   EXPECT(psca_sample_cov(NULL, dummy_c, 2, 2, dummy_c, NULL) == PSCA_EINVAL);
+  EXPECT(psca_sample_cov_batch(NULL, 1, dummy_c, 4, 2, 2, dummy_c, 4, NULL) == PSCA_EINVAL);
   EXPECT(psca_detect(NULL, dummy_c, dummy_c, 2, 2, &prm, dummy_f, &status, NULL) == PSCA_EINVAL);
   EXPECT(psca_detect_y(NULL, dummy_c, dummy_c, 2, 2, &prm, dummy_f, &status, NULL) == PSCA_EINVAL);
   EXPECT(psca_detect_noalloc(NULL, dummy_c, dummy_c, 2, 2, &prm, dummy_f, &status, NULL) == PSCA_EINVAL);

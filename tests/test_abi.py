@@ -41,6 +41,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.psca_create(None, 0) == N.PSCA_EINVAL
     assert lib.psca_destroy(None) == N.PSCA_OK
     assert lib.psca_sample_cov(None, None, 4, 4, None, None) == N.PSCA_EINVAL
+    assert lib.psca_sample_cov_batch(None, 2, None, 16, 4, 4, None, 16, None) == N.PSCA_EINVAL
     assert lib.psca_detect(None, None, None, 4, 4, ctypes.byref(prm), None, None, None) == N.PSCA_EINVAL
     assert lib.psca_detect_y(None, None, None, 4, 4, ctypes.byref(prm), None, None, None) == N.PSCA_EINVAL
     assert lib.psca_iterate(None, None, None, 4, 4, ctypes.byref(prm), ctypes.c_float(0.5), None, None,

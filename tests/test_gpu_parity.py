@@ -77,6 +77,32 @@ def test_sample_covariance(P):
         assert np.array_equal(got, got.conj().T)        # exactly Hermitian
 
 
+def test_sample_covariance_batch(P):
+    # B instances of one size in one launch, each bit-identical to its own
+    # single call (same kernel, same arithmetic) and within half an FP32 ulp
+    # of the oracle; padded instance strides; B = 0 launches nothing
+    for (B, N, L, M, pad) in [(5, 30, 200, 33, 0), (3, 50, 64, 128, 7), (2, 20, 97, 5, 3)]:
+        insts = [I.make_instance(11 + b, L + b, N, L, M, 0.2).fp32_inputs() for b in range(B)]
+        print(f"sample_cov_batch B={B} L={L} M={M} pad={pad}", flush=True)
+        buf = torch.zeros(B * (L * M + pad), dtype=torch.complex64, device="cuda")
+        Yb = buf.as_strided((B, L, M), (L * M + pad, 1, L))
+        for b, inst in enumerate(insts):
+            Yb[b].copy_(c64(inst.Y))
+        got = P.sample_cov_batch(Yb)
+        singles = [P.sample_cov(c64(inst.Y)) for inst in insts]
+        torch.cuda.synchronize()
+        for b, inst in enumerate(insts):
+            g = got[b].cpu().numpy()
+            assert np.array_equal(g, singles[b].cpu().numpy())
+            ref = O.sample_covariance(inst.Y)
+            tol = lambda r: 2.0 ** -24 * (1 + 1e-6) * np.abs(r) + 1e-12 * np.abs(ref).max()
+            g = g.astype(np.complex128)
+            assert np.all(np.abs(g.real - ref.real) <= tol(ref.real))
+            assert np.all(np.abs(g.imag - ref.imag) <= tol(ref.imag))
+    empty = torch.empty((0, 8, 4), dtype=torch.complex64, device="cuda")
+    assert P.sample_cov_batch(empty.as_strided((0, 8, 4), (32, 1, 8))).shape == (0, 8, 8)
+
+
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_first_iteration_from_zero(P, variant):
     inst = I.workload_instance("small", 1).fp32_inputs()
